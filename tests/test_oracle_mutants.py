@@ -1,0 +1,110 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each mutant is a one-line change of oracle/qdo.c (a dropped term, a wrong
+sign or bound, a missing clearing step), compiled on the CPU into a
+temporary library; the pin checks below must fail for every one of them and
+pass for the unmodified source.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2408_10743_amd import workloads as W
+
+from test_oracle_pins import GOLD, f4_to_bin, py_exhaustive, swt, esym
+
+SRC = os.path.join(os.path.dirname(O.__file__), "qdo.c")
+
+MUTANTS = {
+    "f2_no_full_clearing": ("      if (v != r && R[(size_t)v * len + col])\n        row_add(R + (size_t)v * len, R + (size_t)r * len, len);\n    rem[r] = 0;\n    second[q] = r;",
+                            "      if (v != r && rem[v] && R[(size_t)v * len + col])\n        row_add(R + (size_t)v * len, R + (size_t)r * len, len);\n    rem[r] = 0;\n    second[q] = r;"),
+    "bound_abs_not_max": ("L += c > 0 ? c : 0;", "L += c > 0 ? c : -c;"),
+    "bound_ignores_delta": ("int c = tdone[i] + 1 - delta[i];", "int c = tdone[i] + 1;"),
+    "bound_off_by_one": ("int c = tdone[i] + 1 - delta[i];", "int c = tdone[i] + 2 - delta[i];"),
+    "alpha_times_row_wrong": ("ag[n + q] = (uint8_t)(a ^ b);", "ag[n + q] = (uint8_t)a;"),
+    "weight_xor_not_or": ("w += __builtin_popcountll(c[i] | c[W + i]);", "w += __builtin_popcountll(c[i] ^ c[W + i]);"),
+    "one_row_clearing_skipped": ("if (sv == sr || sv == (sr ^ beta))", "if (0)"),
+    "round_skips_last_package": ("for (int i = start; i <= c->P - (c->t - depth); ++i)",
+                                 "for (int i = start; i < c->P - (c->t - depth); ++i)"),
+    "third_element_missing": ("      ne[i] = 3;", "      ne[i] = 2;"),
+    "stop_one_early": ("if (L >= U || t == P[j]) finished = 1;", "if (L + 1 >= U || t == P[j]) finished = 1;"),
+    "two_dim_clears_with_wrong_row": ("        } else if (sv == ss) {\n          row_add(R + (size_t)v * len, R + (size_t)s * len, len);",
+                                      "        } else if (sv == ss) {\n          row_add(R + (size_t)v * len, R + (size_t)r * len, len);"),
+}
+
+
+def quick_pins():
+    """A compact subset of the pins; True when all of them hold."""
+    try:
+        ex = GOLD["saved1_example"]
+        A = np.array(ex["A"], dtype=np.uint8)
+        if O.bz(A, O.DIAG_F2)[0] != ex["d_true"]:
+            return False
+        ex2 = GOLD["saved2_example"]
+        A4 = f4_to_bin(ex2["A4"])
+        d, _, log = O.bz(A4, O.DIAG_F4, 1)
+        if d != ex2["d_true"] or [[t, L, U] for (t, j, L, U, _) in log] != ex2["trace_B4_after_rounds"]:
+            return False
+        for s in range(400):
+            B = W.tiny_code(90000 + s)
+            if not B.any():
+                continue
+            db = py_exhaustive(B[:10]) if B.shape[0] > 10 else None
+            d0, wit = O.brute(B)
+            if db is not None and O.brute(B[:10])[0] != db:
+                return False
+            if swt(wit) != d0:
+                return False
+            for diag in (O.DIAG_F2, O.DIAG_F4):
+                if O.bz(B, diag, 8)[0] != d0:
+                    return False
+        for s in range(10):
+            G = W.f4_linear(5, 2, W.config_seed(14, s))
+            B = O.expand(G, 4)
+            ref = py_exhaustive(np.concatenate([f4_to_bin(G), f4_to_bin(np.array([[[0, 2, 3, 1][c] for c in r] for r in G]))]))
+            if O.brute(B)[0] != ref:
+                return False
+        rows, dims = W.random_packages(6, 20, W.config_seed(15, 0), 0.5)
+        sizes = [3 if d == 2 else 1 for d in dims]
+        for t in range(1, 7):
+            if O.round_min(rows, dims, t)[2] != esym(sizes, t):
+                return False
+        return True
+    except O.OracleError:
+        return False
+
+
+def _load(path):
+    O._lib = ctypes.CDLL(path)
+
+
+@pytest.fixture
+def restore_lib():
+    saved = O._lib
+    yield
+    O._lib = saved
+
+
+def test_unmodified_oracle_passes(restore_lib):
+    O._lib = None
+    assert quick_pins()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, restore_lib, tmp_path):
+    src = open(SRC).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, f"mutation site for {name} not unique/not found"
+    mpath = tmp_path / "qdo_mut.c"
+    mpath.write_text(src.replace(old, new))
+    hdr = os.path.join(os.path.dirname(SRC), "qdo.h")
+    (tmp_path / "qdo.h").write_text(open(hdr).read())
+    so = tmp_path / "libmut.so"
+    subprocess.check_call(["gcc", "-O1", "-mpopcnt", "-fopenmp", "-std=c99", "-shared", "-fPIC",
+                           str(mpath), "-o", str(so)])
+    _load(str(so))
+    assert not quick_pins(), f"mutant {name} survived the pins"
