@@ -1,0 +1,172 @@
+/*
+ * qdist.h -- C ABI of libqdist: exact symplectic minimum distance of binary
+ * (additive) codes on an MI355X (gfx950) GPU, by Brouwer-Zimmermann
+ * enumeration over package-systematic generator matrices.
+ *
+ * The operation is the one of Hernando, Quintana-Orti and Grassl, "Fast
+ * Algorithms and Implementations for Computing the Minimum Distance of
+ * Quantum Codes":
+ *   d = min { wt_s(c) : c in C, c != 0 },  wt_s(a,b) = #{i : a_i or b_i != 0}
+ * (Sec. 2, the first two displays), for the code C spanned by the rows of
+ * a normalizer-type matrix (Sec. 2, the matrix A; for k = 0 the paper's
+ * modified algorithm updates U with every codeword, Sec. 2.1, which is the
+ * rule used here for any input).  The generator matrices are built by the
+ * diagonalizations of Sec. 2.2 (over F2) and Sec. 2.3 (over F4, with the
+ * second matrix on the principal columns); the lower bound is the one of
+ * Sec. 2.1 and Sec. 2.3.
+ *
+ * Conventions for every entry point:
+ *  - Buffers are host memory owned by the caller, read or written only
+ *    during the call and never retained.
+ *  - Matrix layout, row-major uint8:
+ *      QD_FIELD_F2: m rows x 2n bytes in {0,1}; row = x_1..x_n | z_1..z_n
+ *                   (the paper's (a|b)).
+ *      QD_FIELD_F4: m rows x n bytes in {0,1,2,3}; code a + 2b is the
+ *                   symbol a + alpha*b (Sec. 2.3).  The code is the F4-span
+ *                   of the rows: each row g contributes g and alpha*g.
+ *  - Rows need not be independent; the library works on a basis of their
+ *    span.  A zero span is QD_ERR_ZERO_CODE.
+ *  - 1 <= n <= QD_MAX_N.  Larger n is QD_ERR_TOO_LARGE.
+ *  - On an error the return value is negative, *d is set to -1 (when d is
+ *    not NULL) and the witness is left untouched.
+ *  - The witness, when requested, is 2n bytes (x then z) of a codeword of
+ *    weight d; any such codeword is a correct answer.
+ *  - The current HIP device is used.  Calls from several threads are
+ *    serialized per device.  There is no CPU fallback: without a usable
+ *    gfx950 device the GPU entry points return QD_ERR_DEVICE.
+ */
+#ifndef QDIST_H
+#define QDIST_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QD_FIELD_F2 2
+#define QD_FIELD_F4 4
+
+#define QD_DIAG_AUTO 0
+#define QD_DIAG_F2 2
+#define QD_DIAG_F4 4
+
+#define QD_OK 0
+#define QD_INCOMPLETE 1 /* budget or cancel: *d = U, stats hold L <= d <= U */
+#define QD_ERR_INVALID (-1)
+#define QD_ERR_ZERO_CODE (-2)
+#define QD_ERR_TOO_LARGE (-3)
+#define QD_ERR_NOMEM (-4)
+#define QD_ERR_DEVICE (-5)
+#define QD_ERR_INTERNAL (-6)
+
+#define QD_MAX_N 128
+#define QD_MAX_GAMMA 8
+#define QD_MAX_LOG 96
+
+/* Options of qd_distance_ex.  Zero-initialized means "library defaults". */
+typedef struct qd_options {
+  int diag;                   /* QD_DIAG_AUTO, QD_DIAG_F2 or QD_DIAG_F4 */
+  int max_gamma;              /* 0: planner decides; else at most this many matrices */
+  unsigned long long budget;  /* stop before a round that would exceed this many
+                                 combinations in total (0: no limit) -> QD_INCOMPLETE */
+  const volatile int *cancel; /* host flag polled between rounds (NULL: none) */
+  void *stream;               /* hipStream_t for all work (NULL: the library's own) */
+  int seg_len;                /* tuning override: table entries per tile, multiple of 8 (0: auto) */
+  int saved_depth;            /* tuning override: max packages in the saved-sum table (0: auto) */
+  int timing;                 /* 1: time every enumeration launch with HIP events */
+} qd_options;
+
+/* One (t, Gamma_j) round of the enumeration. */
+typedef struct qd_round_log {
+  int t, j;                   /* packages per combination, generator matrix */
+  int L, U;                   /* bounds after the round */
+  int saved_depth;            /* packages per saved-table entry used by the round */
+  int launches;               /* enumeration kernel launches */
+  unsigned long long combinations; /* combinations visited (exact count) */
+  unsigned long long planned;      /* combinations in the full round, e_t(sizes) */
+  float kernel_ms;            /* summed enumeration-kernel time (timing = 1) */
+} qd_round_log;
+
+/* Statistics of one qd_distance_ex call. */
+typedef struct qd_stats {
+  int n, rank, D;             /* D = 32-bit words per half on the device */
+  int diag;                   /* construction used */
+  int h;                      /* generator matrices enumerated */
+  int P[QD_MAX_GAMMA];        /* packages per matrix */
+  int delta[QD_MAX_GAMMA];    /* packages not pivoted inside the matrix's qubit set */
+  int L, U;                   /* final bounds (L >= U unless QD_INCOMPLETE) */
+  int d_estimate;             /* planner's distance estimate */
+  double predicted;           /* planner's predicted combinations */
+  unsigned long long combinations; /* combinations visited in total */
+  double host_ms;             /* input check, basis, diagonalization, planning */
+  double kernel_ms;           /* summed enumeration-kernel time (timing = 1) */
+  double wall_ms;             /* whole call */
+  int nlog;                   /* rounds run (entries in log, capped at QD_MAX_LOG) */
+  qd_round_log log[QD_MAX_LOG];
+} qd_stats;
+
+/* Structure chosen by the host planner (no GPU needed). */
+typedef struct qd_plan_info {
+  int n, rank;
+  int diag;                   /* construction of the matrices below */
+  int h;                      /* matrices built by that construction */
+  int h_used;                 /* matrices the enumeration would use */
+  int P[QD_MAX_GAMMA];
+  int delta[QD_MAX_GAMMA];
+  int dims[QD_MAX_GAMMA][2 * QD_MAX_N];   /* 1 or 2 per package */
+  int pivot[QD_MAX_GAMMA][2 * QD_MAX_N];  /* qubit, or -1 for delta packages */
+  int d_estimate;
+  double predicted_f2, predicted_f4;      /* predicted combinations per construction */
+} qd_plan_info;
+
+/* Symplectic minimum distance of the code spanned by G (Sec. 2 definition,
+ * computed with the Brouwer-Zimmermann bounds of Sec. 2.1).  witness: 2n
+ * bytes or NULL.  Returns QD_OK or a negative error. */
+int qd_distance(const uint8_t *G, int m, int n, int field, int *d, uint8_t *witness);
+
+/* qd_distance with options and statistics (opt and st may be NULL). */
+int qd_distance_ex(const uint8_t *G, int m, int n, int field, const qd_options *opt,
+                   int *d, uint8_t *witness, qd_stats *st);
+
+/* Distances of `count` independent codes in one persistent launch per
+ * enumeration step, each code's rounds advancing on its own.  Arrays are
+ * indexed by code; witness may be NULL or hold NULL entries; status[i]
+ * receives the per-code status.  Returns QD_OK when every code finished,
+ * else the first negative status.  opt may be NULL (budget and cancel apply
+ * to every code). */
+int qd_distance_batch(int count, const uint8_t *const *G, const int *m, const int *n,
+                      const int *field, int *d, uint8_t *const *witness, int *status);
+int qd_distance_batch_ex(int count, const uint8_t *const *G, const int *m, const int *n,
+                         const int *field, const qd_options *opt, int *d,
+                         uint8_t *const *witness, int *status, qd_stats *st);
+
+/* Host-only: the generator matrices (Sec. 2.2 / Sec. 2.3 diagonalizations)
+ * and the planner's choice for one code.  diag = QD_DIAG_AUTO reports the
+ * construction the planner picks.  No GPU is touched. */
+int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma,
+            qd_plan_info *out);
+
+/* One enumeration round on the GPU over a caller-given package layout:
+ * every choice of t distinct packages and one nonzero element of each
+ * (Sec. 2.3, packages).  rows: 2P rows of 2n bytes; rows 2i and 2i+1 span
+ * package i when dims[i] == 2, row 2i alone when dims[i] == 1.  Writes the
+ * minimum symplectic weight (n + 1 when t > P), one codeword reaching it
+ * (witness: 2n bytes or NULL) and the number of combinations visited. */
+int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int *wmin,
+                 uint8_t *witness, unsigned long long *count);
+
+/* Human-readable status. */
+const char *qd_strerror(int status);
+
+/* Device probe: 0 when a gfx950 device is usable; name receives up to len-1
+ * bytes of the device name. */
+int qd_device_check(char *name, int len);
+
+/* Sustained integer-VALU rate on the current device, measured by a chain of
+ * independent 32-bit XOR/OR/popcount operations: lane-ops per second. */
+int qd_valu_peak(double *lane_ops_per_s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,91 @@
+// host.hpp -- host side of libqdist: input checks, basis, the package-
+// systematic generator matrices of the paper's two diagonalizations, the
+// lower-bound schedule and the work planner.  No GPU code here.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace qd {
+
+constexpr int kMaxN = 128;   // qubits; two 64-bit words per half
+constexpr int kMaxGamma = 8;
+
+// One binary row (x | z) over at most 128 qubits.
+struct BRow {
+  uint64_t x[2] = {0, 0};
+  uint64_t z[2] = {0, 0};
+};
+
+inline int qsym(const BRow &r, int q) {  // F4 symbol x + 2z at qubit q
+  return int((r.x[q >> 6] >> (q & 63)) & 1) | (int((r.z[q >> 6] >> (q & 63)) & 1) << 1);
+}
+inline void radd(BRow &a, const BRow &b) {
+  a.x[0] ^= b.x[0]; a.x[1] ^= b.x[1]; a.z[0] ^= b.z[0]; a.z[1] ^= b.z[1];
+}
+inline bool rzero(const BRow &a) { return !(a.x[0] | a.x[1] | a.z[0] | a.z[1]); }
+int rweight(const BRow &a);  // symplectic weight
+
+// A package: {r} or {r, s, r^s} pivoted on `pivot` (-1: outside the set).
+struct Package {
+  int dim = 1;
+  int pivot = -1;
+  BRow r, s;
+};
+
+struct Gamma {
+  std::vector<Package> pk;
+  int delta = 0;  // packages with pivot == -1
+  int P() const { return int(pk.size()); }
+  int inside() const { return P() - delta; }
+};
+
+// Parses a caller matrix into binary rows; F4 rows expand to g, alpha*g.
+// Returns QD status (0 ok).
+int load_rows(const uint8_t *G, int m, int n, int field, std::vector<BRow> &rows);
+
+// Reduces rows to a basis of their span (row echelon form); returns rank.
+int make_basis(std::vector<BRow> &rows, int n);
+
+// Diagonalization over F4 (Sec. 2.3), generalized to several matrices on
+// disjoint qubit sets; at most max_gamma matrices, each with >= 1 package
+// pivoted inside its own set.
+std::vector<Gamma> build_f4(const std::vector<BRow> &basis, int n, int max_gamma);
+
+// Diagonalization over F2 (Sec. 2.2) with whole-qubit clearing: one matrix.
+Gamma build_f2(const std::vector<BRow> &basis, int n);
+
+// Checks the package invariants behind the lower bound; true when they hold.
+bool check_gamma(const Gamma &g, int n);
+
+// Elementary symmetric polynomials e_r of package sizes (1 or 3) as
+// saturating 64-bit integers.  prefix[h][r] = e_r(c_0..c_{h-1}),
+// suffix[h][r] = e_r(c_h..c_{P-1}); rmax columns + 1.
+constexpr uint64_t kSat = uint64_t(1) << 62;
+void esym_tables(const std::vector<int> &sizes, int rmax, std::vector<uint64_t> &prefix,
+                 std::vector<uint64_t> &suffix);
+uint64_t esym(const std::vector<int> &sizes, int t);
+
+// Lower bound after matrix j has finished round t_j (t_j = 0: nothing yet).
+int lower_bound(const std::vector<int> &tdone, const std::vector<int> &delta);
+
+struct PlanChoice {
+  int diag = 4;
+  int h_used = 1;
+  int d_est = 0;
+  double predicted = 0;
+  double predicted_f2 = 0, predicted_f4 = 0;
+};
+
+// Distance estimate for a code of rank k on n qubits with a known upper
+// bound: the smaller of the upper bound and the weight where a random code
+// of this size expects its first nonzero codeword.
+int estimate_distance(int n, int k, int upper);
+
+// Predicted combinations to certify distance d_est with the given matrices.
+double predict_work(const std::vector<Gamma> &gs, int h, int d_est);
+
+// Picks the construction and number of matrices with the least predicted work.
+PlanChoice choose_plan(const std::vector<Gamma> &f4, const Gamma &f2, int n, int rank,
+                       int diag_req, int max_gamma_req);
+
+}  // namespace qd

@@ -1,0 +1,284 @@
+// kernels.hip -- gfx950 kernels of libqdist.
+//
+// Enumeration scheme for one round (t packages of one generator matrix):
+// a combination is split into its u lowest packages ("bottom") and the
+// t - u others ("top").  All bottom combinations are precomputed once per
+// matrix and depth u into a saved table ordered by their largest package,
+// so the bottoms that fit below a top whose smallest package is h are a
+// prefix of the table.  Each lane of a wavefront holds one top codeword in
+// VGPRs; the wavefront streams a segment of the table through SGPRs (all
+// lanes read the same entry), so each codeword costs one XOR per x word,
+// one fused XOR-OR (v_bitop3) per z word, one v_bcnt per word and one MIN.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace qd {
+
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+  uint32_t r;
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+  return r;
+}
+
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+  uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), off)));
+  return v;
+}
+
+template <int D>
+__device__ __forceinline__ void xor_elem(const uint32_t *__restrict__ elems, int pkg, int e,
+                                         uint32_t (&ax)[D], uint32_t (&az)[D]) {
+  const uint32_t *p = elems + (size_t(3) * pkg + e) * kElemWords;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    ax[d] ^= p[d];
+    az[d] ^= p[4 + d];
+  }
+}
+
+// Weight of (lane codeword) ^ (table entry k); k is wavefront-uniform.
+template <int D>
+__device__ __forceinline__ uint32_t weight_at(const uint32_t *__restrict__ table, unsigned long long k,
+                                              const uint32_t (&ax)[D], const uint32_t (&az)[D]) {
+  const uint32_t *b = table + (k / kBlock) * (2 * D * kBlock) + (k % kBlock);
+  uint32_t acc = 0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    uint32_t o = (ax[d] ^ b[d * kBlock]) | (az[d] ^ b[(D + d) * kBlock]);
+    acc = d == 0 ? __builtin_popcount(o) : bcnt_acc(o, acc);
+  }
+  return acc;
+}
+
+// Minimum over one block of kBlock table entries (SoA: word-major).
+template <int D>
+__device__ __forceinline__ uint32_t block_min(const uint32_t (&ax)[D], const uint32_t (&az)[D],
+                                              const uint32_t *__restrict__ blk, uint32_t best) {
+  uint32_t v[2 * D][kBlock];
+#pragma unroll
+  for (int j = 0; j < 2 * D; ++j)
+#pragma unroll
+    for (int e = 0; e < kBlock; ++e) v[j][e] = blk[j * kBlock + e];
+  uint32_t w[kBlock];
+#pragma unroll
+  for (int e = 0; e < kBlock; ++e) {
+    uint32_t acc = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      uint32_t o = (ax[d] ^ v[d][e]) | (az[d] ^ v[D + d][e]);
+      acc = d == 0 ? __builtin_popcount(o) : bcnt_acc(o, acc);
+    }
+    w[e] = acc;
+  }
+#pragma unroll
+  for (int e = 0; e < kBlock; e += 2) best = min(best, min(w[e], w[e + 1]));
+  return best;
+}
+
+// Top combination number `item` of the group whose smallest package is h:
+// the element of h is the most significant digit, then the remaining
+// t-u-1 packages above h in lexicographic order (suffix counts e_r).
+template <int D>
+__device__ void unrank_top(const RoundParams &p, int h, unsigned long long item, uint32_t (&ax)[D],
+                           uint32_t (&az)[D]) {
+  int r = p.t - p.u - 1;
+  const unsigned long long *F = p.suffix;
+  unsigned long long rest = item;
+  const unsigned long long f = F[size_t(h + 1) * p.R + r];
+  int c = 0;
+  while (rest >= f && c < 2) { rest -= f; ++c; }
+  xor_elem<D>(p.elems, h, c, ax, az);
+  for (int j = h + 1; r > 0 && j < p.P; ++j) {
+    const unsigned long long fj = F[size_t(j + 1) * p.R + (r - 1)];
+    const unsigned long long cnt = fj * p.csize[j];
+    if (rest < cnt) {
+      int cj = 0;
+      while (rest >= fj && cj < 2) { rest -= fj; ++cj; }
+      xor_elem<D>(p.elems, j, cj, ax, az);
+      --r;
+    } else {
+      rest -= cnt;
+    }
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void qd_round_kernel(RoundParams p) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  // Consecutive workgroups land on different XCDs; give each XCD a
+  // contiguous range of tiles so its L2 sees a contiguous table range.
+  const uint32_t per = gridDim.x / 8;
+  const uint32_t wg = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const unsigned long long g = p.tile_lo + static_cast<unsigned long long>(wg) * kWavesPerGroup + wave;
+  if (g >= p.tile_hi) return;
+  DevState *st = p.state;
+  unsigned long long key = uniform64(__hip_atomic_load(&st->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  if (static_cast<int>(key >> 32) <= p.L_before) return;  // bound already met
+
+  int lo = 0, hi = p.ngroups;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (p.groups[mid].tile0 <= g) lo = mid;
+    else hi = mid;
+  }
+  const DevGroup &grp = p.groups[lo];
+  const unsigned long long local = g - grp.tile0;
+  const unsigned long long b = local % grp.nb, s = local / grp.nb;
+  const unsigned long long k0 = s * p.seg;
+  const unsigned long long k1 = min(k0 + p.seg, grp.len);
+  const unsigned long long item = b * kWave + lane;
+  const bool active = item < grp.items;
+
+  uint32_t ax[D], az[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) ax[d] = az[d] = 0;
+  if (active) unrank_top<D>(p, grp.h, item, ax, az);
+
+  uint32_t best = 0xFFFFFFFFu;
+  const uint32_t nfull = static_cast<uint32_t>((k1 - k0) / kBlock);
+  const uint32_t *blk = p.table + (k0 / kBlock) * (2 * D * kBlock);
+  for (uint32_t i = 0; i < nfull; ++i, blk += 2 * D * kBlock) best = block_min<D>(ax, az, blk, best);
+  for (unsigned long long k = k0 + static_cast<unsigned long long>(nfull) * kBlock; k < k1; ++k)
+    best = min(best, weight_at<D>(p.table, k, ax, az));
+  if (!active) best = 0xFFFFFFFFu;
+  const uint32_t wmin = wave_min(best);
+  const unsigned long long nact = __popcll(__ballot(active));
+  if (lane == 0) atomicAdd(&st->count, nact * (k1 - k0));
+
+  key = uniform64(__hip_atomic_load(&st->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  if (wmin < static_cast<uint32_t>(key >> 32)) {
+    // Rare: this tile improves U.  Find where, write the codeword to this
+    // tile's own slot, then publish (U, slot) with one 64-bit atomicMin.
+    unsigned long long kf = ~0ull;
+    for (unsigned long long k = k0; k < k1; ++k) {
+      const uint32_t w = weight_at<D>(p.table, k, ax, az);
+      if (w == wmin && kf == ~0ull) kf = k;
+    }
+    const unsigned long long mask = __ballot(active && best == wmin);
+    const int winner = __ffsll(static_cast<long long>(mask)) - 1;
+    if (static_cast<int>(lane) == winner) {
+      const uint32_t slot = static_cast<uint32_t>(g - p.tile_lo);
+      uint32_t *out = p.slots + static_cast<size_t>(slot) * kElemWords;
+      const uint32_t *e = p.table + (kf / kBlock) * (2 * D * kBlock) + (kf % kBlock);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        out[d] = d < D ? (ax[d] ^ e[d * kBlock]) : 0u;
+        out[4 + d] = d < D ? (az[d] ^ e[(D + d) * kBlock]) : 0u;
+      }
+      atomicMin(&st->key, (static_cast<unsigned long long>(wmin) << 32) | slot);
+    }
+  }
+}
+
+// Saved table: entry k is the k-th bottom combination of u packages in the
+// order (largest package, its element, then the rest recursively), so the
+// combinations inside packages [0, h) are entries [0, e_u(c_0..c_{h-1})).
+template <int D>
+__global__ __launch_bounds__(256) void qd_saved_kernel(SavedParams p) {
+  const unsigned long long k = static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= p.nent_padded) return;
+  uint32_t x[D], z[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) x[d] = z[d] = 0;
+  if (k < p.nent) {
+    unsigned long long rest = k;
+    int hi = p.P;
+    for (int r = p.u; r > 0; --r) {
+      int h = hi - 1;
+      while (h > 0 && p.prefix[size_t(h) * p.R + r] > rest) --h;
+      rest -= p.prefix[size_t(h) * p.R + r];
+      const unsigned long long f = p.prefix[size_t(h) * p.R + r - 1];
+      int c = 0;
+      while (rest >= f && c < 2) { rest -= f; ++c; }
+      xor_elem<D>(p.elems, h, c, x, z);
+      hi = h;
+    }
+  }
+  uint32_t *b = p.table + (k / kBlock) * (2 * D * kBlock) + (k % kBlock);
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    b[d * kBlock] = x[d];
+    b[(D + d) * kBlock] = z[d];
+  }
+}
+
+// Moves the codeword of the winning slot into the code's state.
+__global__ void qd_commit_kernel(DevState *st, const uint32_t *slots) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const unsigned long long key = st->key;
+  const uint32_t slot = static_cast<uint32_t>(key & 0xFFFFFFFFull);
+  if (slot == kNoSlot) return;
+#pragma unroll
+  for (int w = 0; w < kElemWords; ++w) st->wit[w] = slots[static_cast<size_t>(slot) * kElemWords + w];
+  st->key = (key & ~0xFFFFFFFFull) | kNoSlot;
+}
+
+// Integer VALU rate probe: 8 independent XOR / OR / popcount chains per lane.
+__global__ __launch_bounds__(256) void qd_valu_kernel(uint32_t seed, uint32_t iters, uint32_t *out) {
+  uint32_t a[8], c = seed * 2654435761u + threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = c + i * 0x9E3779B9u;
+  for (uint32_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      asm volatile("v_xor_b32 %0, %1, %0" : "+v"(a[i]) : "v"(c));
+      asm volatile("v_or_b32 %0, %1, %0" : "+v"(a[i]) : "v"(c));
+      asm volatile("v_bcnt_u32_b32 %0, %0, %0" : "+v"(a[i]));
+      asm volatile("v_xor_b32 %0, %1, %0" : "+v"(a[i]) : "v"(c));
+    }
+  }
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) s ^= a[i];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+// -- launch helpers (host) ---------------------------------------------------
+
+hipError_t launch_round(int D, const RoundParams &p, hipStream_t s) {
+  const unsigned long long tiles = p.tile_hi - p.tile_lo;
+  unsigned long long wgs = (tiles + kWavesPerGroup - 1) / kWavesPerGroup;
+  wgs = (wgs + 7) / 8 * 8;
+  dim3 grid(static_cast<uint32_t>(wgs)), block(kWave * kWavesPerGroup);
+  switch (D) {
+    case 1: hipLaunchKernelGGL(qd_round_kernel<1>, grid, block, 0, s, p); break;
+    case 2: hipLaunchKernelGGL(qd_round_kernel<2>, grid, block, 0, s, p); break;
+    case 3: hipLaunchKernelGGL(qd_round_kernel<3>, grid, block, 0, s, p); break;
+    case 4: hipLaunchKernelGGL(qd_round_kernel<4>, grid, block, 0, s, p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_saved(int D, const SavedParams &p, hipStream_t s) {
+  dim3 grid(static_cast<uint32_t>((p.nent_padded + 255) / 256)), block(256);
+  switch (D) {
+    case 1: hipLaunchKernelGGL(qd_saved_kernel<1>, grid, block, 0, s, p); break;
+    case 2: hipLaunchKernelGGL(qd_saved_kernel<2>, grid, block, 0, s, p); break;
+    case 3: hipLaunchKernelGGL(qd_saved_kernel<3>, grid, block, 0, s, p); break;
+    case 4: hipLaunchKernelGGL(qd_saved_kernel<4>, grid, block, 0, s, p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_commit(DevState *st, const uint32_t *slots, hipStream_t s) {
+  hipLaunchKernelGGL(qd_commit_kernel, dim3(1), dim3(64), 0, s, st, slots);
+  return hipGetLastError();
+}
+
+hipError_t launch_valu(uint32_t blocks, uint32_t iters, uint32_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(qd_valu_kernel, dim3(blocks), dim3(256), 0, s, 12345u, iters, out);
+  return hipGetLastError();
+}
+
+}  // namespace qd

@@ -1,0 +1,202 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Distances and witness weights are integers and must match exactly; a
+witness must lie in the row space.  Round-level checks compare one
+enumeration round over seeded random package layouts with the oracle's
+plain enumeration of the same round.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as O
+from paper_2408_10743_amd import workloads as W
+
+GOLD_DIR = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2408_10743_amd import qdist
+    st, name = qdist.qd_device_check()
+    assert st == 0, f"no usable gfx950 device ({name}): {qdist.qd_strerror(st)}"
+    return qdist
+
+
+def swt(v):
+    n = v.shape[-1] // 2
+    return int(np.count_nonzero(v[:n] | v[n:]))
+
+
+def check_distance(Q, G, field, d_ref, **opts):
+    st, d, wit, stats = Q.qd_distance_ex(G, field, **opts)
+    assert st == 0, Q.qd_strerror(st)
+    assert d == d_ref
+    assert swt(wit) == d
+    assert O.in_rowspace(O.expand(G, field), wit)
+    return stats
+
+
+def test_device(Q):
+    st, name = Q.qd_device_check()
+    print("device", name, flush=True)
+    assert st == 0 and "gfx950" in name
+
+
+@pytest.mark.parametrize("n", [1, 5, 20, 31, 32, 33, 48, 64, 72, 96, 100, 128])
+def test_round_min_random_packages(Q, n):
+    for rep in range(3):
+        rng = W.SplitMix64(W.config_seed(20, n * 10 + rep))
+        P = rng.uniform_int(1, 14)
+        frac = [1.0, 0.0, 0.5][rep]
+        rows, dims = W.random_packages(P, n, rng.next(), frac)
+        for t in range(1, min(P, 6) + 1):
+            print(f"round n={n} rep={rep} P={P} t={t}", flush=True)
+            st, w, wit, cnt = Q.qd_round_min(rows, dims, t)
+            assert st == 0, Q.qd_strerror(st)
+            wo, _, co = O.round_min(rows, dims, t)
+            assert (w, cnt) == (wo, co)
+            assert swt(wit) == w
+            assert O.in_rowspace(rows, wit)
+
+
+def test_round_min_large_round(Q):
+    # several tiles per group, ragged item blocks and table tails
+    rows, dims = W.random_packages(30, 72, W.config_seed(21, 0), 0.8)
+    for t in (4, 5):
+        print(f"large round t={t}", flush=True)
+        st, w, wit, cnt = Q.qd_round_min(rows, dims, t)
+        wo, _, co = O.round_min(rows, dims, t)
+        assert st == 0 and (w, cnt) == (wo, co)
+        assert swt(wit) == w
+
+
+def test_round_beyond_packages(Q):
+    rows, dims = W.random_packages(3, 10, W.config_seed(21, 1))
+    st, w, wit, cnt = Q.qd_round_min(rows, dims, 4)
+    assert st == 0 and w == 11 and cnt == 0
+
+
+def test_config1_against_brute_force(Q):
+    for i in range(120):
+        G, f = W.config1(i)
+        d_ref, _ = O.brute(O.expand(G, f))
+        print(f"config1 seed {i} d={d_ref}", flush=True)
+        check_distance(Q, G, f, d_ref)
+
+
+def test_config1_both_constructions(Q):
+    for i in range(20):
+        G, f = W.config1(i)
+        d_ref, _ = O.brute(O.expand(G, f))
+        for diag in (2, 4):
+            s = check_distance(Q, G, f, d_ref, diag=diag)
+            assert s.diag == diag
+
+
+def test_config2_against_oracle(Q):
+    gold = json.load(open(os.path.join(GOLD_DIR, "oracle_distances.json")))
+    for i, d_ref in enumerate(gold["config2"][:10]):
+        G, f = W.config2(i)
+        print(f"config2 seed {i} d={d_ref}", flush=True)
+        check_distance(Q, G, f, d_ref)
+
+
+def test_config3_against_oracle(Q):
+    gold = json.load(open(os.path.join(GOLD_DIR, "oracle_distances.json")))
+    G, f = W.config3(0)
+    print("config3 seed 0", flush=True)
+    s = check_distance(Q, G, f, gold["config3"][0], timing=1)
+    # every round enumerated the planned e_t(sizes) combinations except a
+    # round cut short by the bound
+    for r in s.rounds()[:-1]:
+        assert r["combinations"] == r["planned"]
+
+
+def test_structure_matches_oracle(Q):
+    for i in range(10):
+        G, f = W.config2(i) if i % 2 else W.config1(i)
+        B = O.expand(G, f)
+        st, d, wit, s = Q.qd_distance_ex(G, f)
+        assert st == 0
+        gs = O.gamma(B, s.diag, 8)
+        for j in range(s.h):
+            assert (s.P[j], s.delta[j]) == (gs[j]["P"], gs[j]["delta"])
+
+
+def test_edge_cases(Q):
+    # one qubit, one row
+    check_distance(Q, np.array([[1, 0]], np.uint8), 2, 1)
+    # n = 128 (four words per half): span{X^n, Z^n} has d = n
+    n = 128
+    XZ = np.zeros((2, 2 * n), np.uint8); XZ[0, :n] = 1; XZ[1, n:] = 1
+    check_distance(Q, XZ, 2, n)
+    # full space: d = 1
+    check_distance(Q, np.eye(2 * 9, dtype=np.uint8), 2, 1)
+    # dependent rows
+    G, f = W.config1(3)
+    d_ref, _ = O.brute(O.expand(G, f))
+    check_distance(Q, np.concatenate([G, G[:5] ^ G[5:10]]), 2, d_ref)
+    # word boundaries
+    for n in (31, 32, 33, 63, 64, 65, 95, 96, 97):
+        G = W.additive(n, 14, W.config_seed(22, n))
+        d_ref, _ = O.brute(O.expand(G, 2))
+        check_distance(Q, G, 2, d_ref)
+    # F4 input
+    G = W.f4_linear(12, 5, W.config_seed(23, 0))
+    d_ref, _ = O.brute(O.expand(G, 4))
+    check_distance(Q, G, 4, d_ref)
+
+
+def test_errors(Q):
+    st, d, _ = Q.qd_distance(np.zeros((3, 8), np.uint8), 2)
+    assert st == Q.QD_ERR_ZERO_CODE and d == -1
+    st, d, _ = Q.qd_distance(np.full((2, 8), 2, np.uint8), 2)
+    assert st == Q.QD_ERR_INVALID
+    st, d, _ = Q.qd_distance(np.ones((2, 2 * 129), np.uint8), 2)
+    assert st == Q.QD_ERR_TOO_LARGE
+
+
+def test_tuning_overrides_do_not_change_results(Q):
+    G, f = W.config2(1)
+    gold = json.load(open(os.path.join(GOLD_DIR, "oracle_distances.json")))
+    for seg, depth in ((8, 1), (64, 2), (4096, 4), (1024, 3)):
+        check_distance(Q, G, f, gold["config2"][1], seg_len=seg, saved_depth=depth)
+
+
+def test_budget_gives_bounds(Q):
+    G, f = W.config2(0)
+    gold = json.load(open(os.path.join(GOLD_DIR, "oracle_distances.json")))
+    st, d, wit, s = Q.qd_distance_ex(G, f, budget=100000)
+    assert st == Q.QD_INCOMPLETE
+    assert s.L <= gold["config2"][0] <= d
+    assert swt(wit) == d
+
+
+def test_invariance_on_gpu(Q):
+    for i in range(10):
+        G, f = W.config1(100 + i)
+        n = G.shape[1] // 2
+        st, d0, _ = Q.qd_distance(G, f)
+        rng = W.SplitMix64(W.config_seed(24, i))
+        perm = sorted(range(n), key=lambda _: rng.next())
+        Gp = np.concatenate([G[:, perm], G[:, [n + q for q in perm]]], axis=1)
+        Gs = np.concatenate([G[:, n:], G[:, :n]], axis=1)
+        for V in (Gp, Gs):
+            st2, d2, _ = Q.qd_distance(V, f)
+            assert st == st2 == 0 and d2 == d0
+
+
+def test_batch_equals_single(Q):
+    codes = [W.config1(i) for i in range(6)] + [W.config2(i) for i in range(2)]
+    st, ds, wits, sts, _ = Q.qd_distance_batch(codes)
+    assert st == 0 and all(s == 0 for s in sts)
+    for (G, f), d, w in zip(codes, ds, wits):
+        st1, d1, _ = Q.qd_distance(G, f)
+        assert st1 == 0 and d1 == d
+        assert swt(w) == d

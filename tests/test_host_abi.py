@@ -1,0 +1,110 @@
+"""CPU checks of the library: it loads, exports every entry point declared
+in include/qdist.h, validates its inputs, and its host-side generator
+matrices have the same structure as the oracle's (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2408_10743_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2408_10743_amd import qdist
+    return qdist
+
+
+def declared_entry_points():
+    src = open(os.path.join(ROOT, "include", "qdist.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qd_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(Q):
+    names = declared_entry_points()
+    assert len(names) >= 9
+    lib = ctypes.CDLL(Q.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(Q.exported_symbols()) == names
+
+
+def test_strerror(Q):
+    for st in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert Q.qd_strerror(st)
+
+
+def _canon(gs):
+    out = []
+    for g in gs:
+        ins = sorted((p, d) for p, d in zip(g["pivots"], g["dims"]) if p >= 0)
+        outs = sorted(d for p, d in zip(g["pivots"], g["dims"]) if p < 0)
+        out.append((g["P"], g["delta"], tuple(ins), tuple(outs)))
+    return out
+
+
+@pytest.mark.parametrize("diag", [2, 4])
+def test_structure_matches_oracle_random(Q, diag):
+    for s in range(1500):
+        B = W.tiny_code(70000 + s, n_max=10, m_max=20)
+        if not B.any():
+            continue
+        assert _canon(O.gamma(B, diag, 8)) == _canon(Q.qd_plan(B, 2, diag, 8)["gammas"]), s
+
+
+def test_structure_matches_oracle_configs(Q):
+    for G, f in [W.config1(0), W.config2(0), W.config3(0), W.config1(5)]:
+        B = O.expand(G, f)
+        for diag in (2, 4):
+            assert _canon(O.gamma(B, diag, 8)) == _canon(Q.qd_plan(G, f, diag, 8)["gammas"])
+
+
+def test_structure_f4_input_and_wide(Q):
+    for s in range(40):
+        rng = W.SplitMix64(W.config_seed(30, s))
+        n = rng.uniform_int(20, 128)
+        if s % 2:
+            G, f = W.f4_linear(n, rng.uniform_int(1, n // 2), rng.next()), 4
+        else:
+            G, f = W.additive(n, rng.uniform_int(1, min(2 * n, 140)), rng.next()), 2
+        B = O.expand(G, f)
+        for diag in (2, 4):
+            assert _canon(O.gamma(B, diag, 8)) == _canon(Q.qd_plan(G, f, diag, 8)["gammas"])
+
+
+def test_planner_picks_paper_structures(Q):
+    # Config 2 (F4-linear [48,24]): two disjoint information sets of 24
+    # two-row packages; config 3 prefers the F4 construction.
+    p = Q.qd_plan(*W.config2(0))
+    assert p["diag"] == 4 and p["h_used"] == 2
+    assert [g["P"] for g in p["gammas"][:2]] == [24, 24]
+    p3 = Q.qd_plan(*W.config3(0))
+    assert p3["diag"] == 4 and p3["predicted_f4"] < p3["predicted_f2"]
+
+
+def test_plan_input_validation(Q):
+    with pytest.raises(Q.QdError):
+        Q.qd_plan(np.zeros((2, 6), np.uint8), 2)
+    with pytest.raises(Q.QdError):
+        Q.qd_plan(np.full((2, 6), 3, np.uint8), 2)
+    with pytest.raises(Q.QdError):
+        Q.qd_plan(np.ones((2, 2 * 129), np.uint8), 2)
+    with pytest.raises(Q.QdError):
+        Q.qd_plan(np.ones((2, 6), np.uint8), 3)
+
+
+def test_no_cpu_fallback_without_gpu(Q):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    G, f = W.config1(0)
+    st, d, _ = Q.qd_distance(G, f)
+    assert st == Q.QD_ERR_DEVICE and d == -1
+    st, w, _, _ = Q.qd_round_min(*W.random_packages(3, 8, 1), 1)
+    assert st == Q.QD_ERR_DEVICE
