@@ -74,6 +74,8 @@ typedef struct qd_options {
   int seg_len;                /* tuning override: table entries per tile, multiple of 8 (0: auto) */
   int saved_depth;            /* tuning override: max packages in the saved-sum table (0: auto) */
   int timing;                 /* 1: time every enumeration launch with HIP events */
+  int tops_mode;              /* tuning override: 0 auto, 1 tops from a table,
+                                 2 tops unranked by each lane */
 } qd_options;
 
 /* One (t, Gamma_j) round of the enumeration. */

@@ -16,7 +16,7 @@
 namespace qd {
 hipError_t launch_round(int D, const RoundParams &p, hipStream_t s);
 hipError_t launch_saved(int D, const SavedParams &p, hipStream_t s);
-hipError_t launch_commit(DevState *st, const uint32_t *slots, hipStream_t s);
+hipError_t launch_commit(DevState *st, const uint32_t *slots, unsigned long long *counters, hipStream_t s);
 hipError_t launch_valu(uint32_t blocks, uint32_t iters, uint32_t *out, hipStream_t s);
 }  // namespace qd
 
@@ -25,10 +25,13 @@ using namespace qd;
 namespace {
 
 constexpr int kTMax = 48;                         // deepest round supported
-constexpr int kDefaultSavedDepth = 3;             // packages per saved-table entry
-constexpr unsigned long long kMaxTableEntries = 1ull << 25;
+constexpr int kDefaultSavedDepth = 4;             // packages per saved-table entry
+constexpr unsigned long long kMaxTableBytes = 1ull << 29;
+constexpr unsigned long long kMaxTopEntries = 1ull << 24;  // 512 MB of tops
 constexpr unsigned long long kTilesPerLaunch = 1ull << 20;
-constexpr unsigned kDefaultSeg = 1024;
+constexpr unsigned long long kTargetTiles = 1ull << 18;  // ~32 tiles per wave slot
+constexpr unsigned kMinSeg = 256, kMaxSeg = 16384;
+constexpr unsigned kStageMaxBytes = 32768;
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -57,9 +60,8 @@ struct GammaDev {
   std::vector<uint32_t> h_elems;         // host staging kept alive across async copies
   std::vector<unsigned char> h_csize;
   DevBuf elems, csize, dprefix, dsuffix;
-  DevBuf table[kTMax + 1];
-  unsigned long long tent[kTMax + 1] = {};
-  bool built[kTMax + 1] = {};
+  DevBuf table[kTMax + 1], tops[kTMax + 1];
+  bool built[kTMax + 1] = {}, tbuilt[kTMax + 1] = {};
 };
 
 struct Ctx {
@@ -68,11 +70,25 @@ struct Ctx {
   hipStream_t own = nullptr;
   std::mutex mu;
   GammaDev g[kMaxGamma];
-  DevBuf groups, slots, state;
-  std::vector<DevGroup> h_groups;  // host staging of the last round's groups
+  DevBuf groups, runs, slots, state, counters;
+  std::vector<DevGroup> h_groups;  // host staging of the last round's tables
+  std::vector<DevRun> h_runs;
   DevState *hstate = nullptr;  // pinned
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<hipEvent_t> pool;  // start/stop pairs of the current round
 };
+
+// Start/stop events for launch i of a round (created on first use).
+bool launch_events(Ctx &c, size_t i, hipEvent_t *a, hipEvent_t *b) {
+  while (c.pool.size() < 2 * (i + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return false;
+    c.pool.push_back(e);
+  }
+  *a = c.pool[2 * i];
+  *b = c.pool[2 * i + 1];
+  return true;
+}
 
 std::mutex g_ctx_mu;
 std::vector<std::unique_ptr<Ctx>> g_ctx;
@@ -155,48 +171,66 @@ int upload_gamma(GammaDev &gd, const Gamma &g, hipStream_t s) {
       hipMemcpyAsync(gd.dprefix.p, gd.prefix.data(), tb, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(gd.dsuffix.p, gd.suffix.data(), tb, hipMemcpyHostToDevice, s) != hipSuccess)
     return QD_ERR_DEVICE;
-  for (int u = 0; u <= kTMax; ++u) gd.built[u] = false;
+  for (int u = 0; u <= kTMax; ++u) gd.built[u] = gd.tbuilt[u] = false;
   return QD_OK;
 }
 
-int ensure_table(GammaDev &gd, int D, int u, hipStream_t s) {
-  if (gd.built[u]) return QD_OK;
-  const unsigned long long nent = gd.prefix[size_t(gd.P) * gd.R + u];
+// Builds (once per matrix) the saved table of u-package bottoms, or with
+// tops = true the table of u-package tops.
+int ensure_table(GammaDev &gd, int D, int u, bool tops, hipStream_t s) {
+  if (tops ? gd.tbuilt[u] : gd.built[u]) return QD_OK;
+  const unsigned long long nent = tops ? gd.suffix[u] : gd.prefix[size_t(gd.P) * gd.R + u];
   const unsigned long long padded = (nent + kBlock - 1) / kBlock * kBlock;
-  if (!gd.table[u].ensure(size_t(padded) * 2 * D * 4)) return QD_ERR_NOMEM;
+  DevBuf &buf = tops ? gd.tops[u] : gd.table[u];
+  if (!buf.ensure(size_t(padded) * (tops ? kElemWords : 2 * D) * 4)) return QD_ERR_NOMEM;
   SavedParams sp;
   sp.elems = gd.elems.as<uint32_t>();
   sp.prefix = gd.dprefix.as<unsigned long long>();
+  sp.suffix = gd.dsuffix.as<unsigned long long>();
   sp.csize = gd.csize.as<unsigned char>();
-  sp.table = gd.table[u].as<uint32_t>();
+  sp.table = buf.as<uint32_t>();
   sp.nent = nent;
   sp.nent_padded = padded;
   sp.P = gd.P;
   sp.R = gd.R;
   sp.u = u;
+  sp.tops = tops ? 1 : 0;
   if (launch_saved(D, sp, s) != hipSuccess) return QD_ERR_DEVICE;
-  gd.tent[u] = nent;
-  gd.built[u] = true;
+  (tops ? gd.tbuilt[u] : gd.built[u]) = true;
   return QD_OK;
 }
 
-// Saved-table depth for round t: u = t-2 (every top then keeps two
-// packages, so a group fills many lanes) within the cap and the table-size
-// limit; round 1 has only one-package tops.
-int saved_depth(const GammaDev &gd, int t, int cap) {
-  int u = t == 1 ? 0 : std::min(t - 2, cap);
-  while (u > 0 && gd.prefix[size_t(gd.P) * gd.R + u] > kMaxTableEntries) --u;
-  return std::max(u, 0);
+// Saved-table depth for round t: u = t-2, so every top keeps two packages
+// (a group then fills many lanes), within the cap and the table-size limit.
+int saved_depth(const GammaDev &gd, int D, int t, int cap) {
+  int u = std::min(std::max(t - 2, 0), cap);
+  while (u > 0 && gd.prefix[size_t(gd.P) * gd.R + u] * 8ull * D > kMaxTableBytes) --u;
+  return u;
+}
+
+// Table entries per tile: long enough to amortize a tile's setup (group
+// search, unranking of 64 tops), short enough for ~kTargetTiles tiles.
+unsigned choose_seg(unsigned long long planned) {
+  const unsigned long long want = planned / (kWave * kTargetTiles);
+  unsigned seg = kMinSeg;
+  while (seg < want && seg < kMaxSeg) seg <<= 1;
+  return seg;
 }
 
 struct RoundPlan {
-  std::vector<DevGroup> groups;
+  std::vector<DevGroup> groups;  // longest table prefix first
+  std::vector<DevRun> runs;
   unsigned long long tiles = 0;
   unsigned long long combos = 0;
 };
 
+// Tiles of one round.  Group h pairs the tops whose smallest package is h
+// (c_h * e_{t-u-1}(c_{h+1}..)) with the first e_u(c_0..c_{h-1}) table
+// entries.  Segment s of the table is shared by every group reaching it,
+// so its tiles take 64 tops at a time from those groups together.
 void plan_round(const GammaDev &gd, int t, int u, unsigned seg, RoundPlan &rp) {
   rp.groups.clear();
+  rp.runs.clear();
   rp.tiles = rp.combos = 0;
   const int R = gd.R, r = t - u - 1;
   for (int h = 0; h < gd.P; ++h) {
@@ -206,13 +240,33 @@ void plan_round(const GammaDev &gd, int t, int u, unsigned seg, RoundPlan &rp) {
     DevGroup grp{};
     grp.items = items;
     grp.len = len;
-    grp.tile0 = rp.tiles;
-    grp.nb = (items + kWave - 1) / kWave;
-    grp.ns = (len + seg - 1) / seg;
+    grp.top0 = gd.suffix[size_t(h + 1) * R + (t - u)];
     grp.h = h;
-    rp.tiles += grp.nb * grp.ns;
     rp.combos += items * len;
     rp.groups.push_back(grp);
+  }
+  std::stable_sort(rp.groups.begin(), rp.groups.end(),
+                   [](const DevGroup &a, const DevGroup &b) { return a.len > b.len; });
+  unsigned long long cum = 0;
+  std::vector<unsigned long long> ns(rp.groups.size());
+  for (size_t i = 0; i < rp.groups.size(); ++i) {
+    rp.groups[i].cum = cum;
+    cum += rp.groups[i].items;
+    ns[i] = (rp.groups[i].len + seg - 1) / seg;
+  }
+  // Segments [ns[e], ns[e-1]) are reached by exactly the e longest groups.
+  const size_t G = rp.groups.size();
+  for (size_t e = G; e >= 1; --e) {
+    const unsigned long long sa = e == G ? 0 : ns[e], sb = ns[e - 1];
+    if (sa >= sb) continue;
+    DevRun run{};
+    run.tile0 = rp.tiles;
+    run.s_begin = sa;
+    run.e = static_cast<long long>(e);
+    run.items = e == G ? cum : rp.groups[e].cum;
+    run.tps = (run.items + kWave - 1) / kWave;
+    rp.tiles += (sb - sa) * run.tps;
+    rp.runs.push_back(run);
   }
 }
 
@@ -226,55 +280,71 @@ struct RunOut {
 
 // One (t, Gamma) round: saved table, tile plan, launches, commit, readback.
 int run_round(Ctx &c, GammaDev &gd, int D, int t, int u, unsigned seg, int L_before, bool timing,
-              hipStream_t s, RunOut &ro) {
-  int rc = ensure_table(gd, D, u, s);
+              int tops_mode, hipStream_t s, RunOut &ro) {
+  int rc = ensure_table(gd, D, u, false, s);
   if (rc) return rc;
+  // Tops come from a table when it is small enough, else lanes unrank them.
+  const bool use_tops = tops_mode == 1 || (tops_mode == 0 && gd.suffix[t - u] <= kMaxTopEntries);
+  if (use_tops && (rc = ensure_table(gd, D, t - u, true, s))) return rc;
   RoundPlan rp;
   plan_round(gd, t, u, seg, rp);
-  c.h_groups.swap(rp.groups);  // the async copy reads the context's copy
-  std::vector<DevGroup> &groups = c.h_groups;
+  c.h_groups.swap(rp.groups);  // the async copies read the context's copies
+  c.h_runs.swap(rp.runs);
+  const std::vector<DevGroup> &groups = c.h_groups;
+  const std::vector<DevRun> &runs = c.h_runs;
   ro.launches = 0;
   ro.ms = 0.f;
-  if (!groups.empty()) {
-    const size_t gb = groups.size() * sizeof(DevGroup);
-    if (!c.groups.ensure(gb) || !c.slots.ensure(size_t(std::min(rp.tiles, kTilesPerLaunch)) * kElemWords * 4))
+  if (rp.tiles) {
+    const size_t gb = groups.size() * sizeof(DevGroup), rb = runs.size() * sizeof(DevRun);
+    if (!c.groups.ensure(gb) || !c.runs.ensure(rb) ||
+        !c.slots.ensure(size_t(std::min(rp.tiles, kTilesPerLaunch)) * kElemWords * 4))
       return QD_ERR_NOMEM;
-    if (hipMemcpyAsync(c.groups.p, groups.data(), gb, hipMemcpyHostToDevice, s) != hipSuccess)
+    if (hipMemcpyAsync(c.groups.p, groups.data(), gb, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(c.runs.p, runs.data(), rb, hipMemcpyHostToDevice, s) != hipSuccess)
       return QD_ERR_DEVICE;
     RoundParams p;
     p.elems = gd.elems.as<uint32_t>();
     p.table = gd.table[u].as<uint32_t>();
+    p.tops = use_tops ? gd.tops[t - u].as<uint32_t>() : nullptr;
     p.groups = c.groups.as<DevGroup>();
+    p.runs = c.runs.as<DevRun>();
     p.suffix = gd.dsuffix.as<unsigned long long>();
     p.csize = gd.csize.as<unsigned char>();
     p.state = c.state.as<DevState>();
+    p.counters = c.counters.as<unsigned long long>();
     p.slots = c.slots.as<uint32_t>();
     p.ngroups = int(groups.size());
+    p.nruns = int(runs.size());
     p.P = gd.P;
     p.R = gd.R;
     p.t = t;
     p.u = u;
     p.seg = seg;
     p.L_before = L_before;
+    p.stage = use_tops ? 1 : 2;
+    if (round_lds_bytes(gd.P, t, u, p.ngroups, p.stage) > kStageMaxBytes) p.stage = 0;
     for (unsigned long long lo = 0; lo < rp.tiles; lo += kTilesPerLaunch) {
       p.tile_lo = lo;
       p.tile_hi = std::min(rp.tiles, lo + kTilesPerLaunch);
-      if (timing && hipEventRecord(c.e0, s) != hipSuccess) return QD_ERR_DEVICE;
+      hipEvent_t ea = nullptr, eb = nullptr;
+      if (timing && (!launch_events(c, size_t(ro.launches), &ea, &eb) || hipEventRecord(ea, s) != hipSuccess))
+        return QD_ERR_DEVICE;
       if (launch_round(D, p, s) != hipSuccess) return QD_ERR_DEVICE;
-      if (timing) {
-        float ms = 0.f;
-        if (hipEventRecord(c.e1, s) != hipSuccess || hipEventSynchronize(c.e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, c.e0, c.e1) != hipSuccess)
-          return QD_ERR_DEVICE;
-        ro.ms += ms;
-      }
-      if (launch_commit(p.state, p.slots, s) != hipSuccess) return QD_ERR_DEVICE;
+      if (timing && hipEventRecord(eb, s) != hipSuccess) return QD_ERR_DEVICE;
+      if (launch_commit(p.state, p.slots, p.counters, s) != hipSuccess) return QD_ERR_DEVICE;
       ++ro.launches;
     }
   }
   if (hipMemcpyAsync(c.hstate, c.state.p, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return QD_ERR_DEVICE;
+  if (timing) {
+    for (int i = 0; i < ro.launches; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c.pool[2 * i], c.pool[2 * i + 1]) != hipSuccess) return QD_ERR_DEVICE;
+      ro.ms += ms;
+    }
+  }
   ro.U = int(c.hstate->key >> 32);
   ro.wit = from_words(c.hstate->wit);
   ro.visited = c.hstate->count;
@@ -283,6 +353,11 @@ int run_round(Ctx &c, GammaDev &gd, int D, int t, int u, unsigned seg, int L_bef
 
 int reset_state(Ctx &c, int n, hipStream_t s) {
   if (!c.state.ensure(sizeof(DevState))) return QD_ERR_NOMEM;
+  const size_t cb = size_t(kCounters) * kCounterStride * sizeof(unsigned long long);
+  if (c.counters.cap < cb) {
+    if (!c.counters.ensure(cb)) return QD_ERR_NOMEM;
+    if (hipMemsetAsync(c.counters.p, 0, cb, s) != hipSuccess) return QD_ERR_DEVICE;
+  }
   std::memset(c.hstate, 0, sizeof(DevState));
   c.hstate->key = (static_cast<unsigned long long>(n + 1) << 32) | kNoSlot;
   if (hipMemcpyAsync(c.state.p, c.hstate, sizeof(DevState), hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -309,7 +384,9 @@ int distance_impl(const uint8_t *G, int m, int n, int field, const qd_options *o
   if (d) *d = -1;
   if (!d) return QD_ERR_INVALID;
   if (o.diag != QD_DIAG_AUTO && o.diag != QD_DIAG_F2 && o.diag != QD_DIAG_F4) return QD_ERR_INVALID;
-  if (o.seg_len < 0 || o.seg_len % kBlock || o.saved_depth < 0 || o.max_gamma < 0) return QD_ERR_INVALID;
+  if (o.seg_len < 0 || o.seg_len % kBlock || o.saved_depth < 0 || o.max_gamma < 0 || o.tops_mode < 0 ||
+      o.tops_mode > 2)
+    return QD_ERR_INVALID;
   std::vector<BRow> rows;
   int rc = load_rows(G, m, n, field, rows);
   if (rc) return rc;
@@ -341,7 +418,6 @@ int distance_impl(const uint8_t *G, int m, int n, int field, const qd_options *o
   if ((rc = reset_state(c, n, s))) return rc;
   S.host_ms = now_ms() - t0;
 
-  const unsigned seg = o.seg_len ? unsigned(o.seg_len) : kDefaultSeg;
   const int cap = o.saved_depth ? o.saved_depth : kDefaultSavedDepth;
   std::vector<int> tdone(h, 0), delta(h);
   for (int j = 0; j < h; ++j) delta[j] = use[j].delta;
@@ -360,9 +436,10 @@ int distance_impl(const uint8_t *G, int m, int n, int field, const qd_options *o
       GammaDev &gd = c.g[j];
       const uint64_t planned = gd.prefix[size_t(gd.P) * gd.R + t];
       if (planned >= kSat || (o.budget && planned_total + planned > o.budget)) { incomplete = true; break; }
-      const int u = saved_depth(gd, t, cap);
+      const int u = saved_depth(gd, D, t, cap);
+      const unsigned seg = o.seg_len ? unsigned(o.seg_len) : choose_seg(planned);
       RunOut ro;
-      if ((rc = run_round(c, gd, D, t, u, seg, L, o.timing != 0, s, ro))) return rc;
+      if ((rc = run_round(c, gd, D, t, u, seg, L, o.timing != 0, o.tops_mode, s, ro))) return rc;
       planned_total += planned;
       if (ro.U < U) { U = ro.U; wit = ro.wit; }
       const unsigned long long this_round = ro.visited - visited;
@@ -494,7 +571,9 @@ int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int 
   if ((rc = reset_state(c, n, s))) return rc;
   const int D = (n + 31) / 32;
   RunOut ro;
-  if ((rc = run_round(c, gd, D, t, saved_depth(gd, t, kDefaultSavedDepth), kDefaultSeg, -1, false, s, ro)))
+  const unsigned long long planned = gd.prefix[size_t(gd.P) * gd.R + t];
+  if ((rc = run_round(c, gd, D, t, saved_depth(gd, D, t, kDefaultSavedDepth), choose_seg(planned), -1, false, 0,
+                      s, ro)))
     return rc;
   *wmin = ro.U;
   *count = ro.visited;

@@ -85,24 +85,24 @@ __device__ __forceinline__ uint32_t block_min(const uint32_t (&ax)[D], const uin
 
 // Top combination number `item` of the group whose smallest package is h:
 // the element of h is the most significant digit, then the remaining
-// t-u-1 packages above h in lexicographic order (suffix counts e_r).
+// t-u-1 packages above h in lexicographic order.  F(j, r) = e_r(c_j..),
+// read from column r of a table with `ld` columns.
 template <int D>
-__device__ void unrank_top(const RoundParams &p, int h, unsigned long long item, uint32_t (&ax)[D],
-                           uint32_t (&az)[D]) {
-  int r = p.t - p.u - 1;
-  const unsigned long long *F = p.suffix;
+__device__ void unrank_top(const unsigned long long *F, int ld, const uint32_t *elems,
+                           const unsigned char *__restrict__ csize, int P, int r, int h,
+                           unsigned long long item, uint32_t (&ax)[D], uint32_t (&az)[D]) {
   unsigned long long rest = item;
-  const unsigned long long f = F[size_t(h + 1) * p.R + r];
+  const unsigned long long f = F[size_t(h + 1) * ld + r];
   int c = 0;
   while (rest >= f && c < 2) { rest -= f; ++c; }
-  xor_elem<D>(p.elems, h, c, ax, az);
-  for (int j = h + 1; r > 0 && j < p.P; ++j) {
-    const unsigned long long fj = F[size_t(j + 1) * p.R + (r - 1)];
-    const unsigned long long cnt = fj * p.csize[j];
+  xor_elem<D>(elems, h, c, ax, az);
+  for (int j = h + 1; r > 0 && j < P; ++j) {
+    const unsigned long long fj = F[size_t(j + 1) * ld + (r - 1)];
+    const unsigned long long cnt = fj * csize[j];
     if (rest < cnt) {
       int cj = 0;
       while (rest >= fj && cj < 2) { rest -= fj; ++cj; }
-      xor_elem<D>(p.elems, j, cj, ax, az);
+      xor_elem<D>(elems, j, cj, ax, az);
       --r;
     } else {
       rest -= cnt;
@@ -110,8 +110,46 @@ __device__ void unrank_top(const RoundParams &p, int h, unsigned long long item,
   }
 }
 
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), off)));
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), off));
+  return v;
+}
+
+// One tile = one table segment [k0, k0 + seg) x 64 tops.  The tops of a
+// tile come from every group whose table prefix reaches the segment, so
+// lanes stay full; a lane stops at its own group's prefix length.
 template <int D>
 __global__ __launch_bounds__(256) void qd_round_kernel(RoundParams p) {
+  // Unranking reads suffix columns, the group table and the elements with
+  // data-dependent addresses: stage them in LDS once per workgroup.
+  extern __shared__ unsigned long long smem[];
+  const int C = p.t - p.u;  // suffix columns 0..t-u-1
+  const unsigned long long *F = p.suffix;
+  const DevGroup *GR = p.groups;
+  const uint32_t *E = p.elems;
+  int ld = p.R;
+  if (p.stage) {
+    DevGroup *sG = reinterpret_cast<DevGroup *>(smem);
+    for (int i = threadIdx.x; i < p.ngroups; i += blockDim.x) sG[i] = p.groups[i];
+    GR = sG;
+    if (p.stage == 2) {
+      unsigned long long *sF = reinterpret_cast<unsigned long long *>(sG + p.ngroups);
+      uint32_t *sE = reinterpret_cast<uint32_t *>(sF + (p.P + 1) * C);
+      for (int i = threadIdx.x; i < (p.P + 1) * C; i += blockDim.x) sF[i] = p.suffix[size_t(i / C) * p.R + i % C];
+      for (int i = threadIdx.x; i < p.P * 3 * kElemWords; i += blockDim.x) sE[i] = p.elems[i];
+      F = sF;
+      E = sE;
+      ld = C;
+    }
+    __syncthreads();
+  }
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   // Consecutive workgroups land on different XCDs; give each XCD a
@@ -121,54 +159,95 @@ __global__ __launch_bounds__(256) void qd_round_kernel(RoundParams p) {
   const unsigned long long g = p.tile_lo + static_cast<unsigned long long>(wg) * kWavesPerGroup + wave;
   if (g >= p.tile_hi) return;
   DevState *st = p.state;
-  unsigned long long key = uniform64(__hip_atomic_load(&st->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  // The key is read with plain loads: a stale (larger) U only delays the
+  // early exit or triggers a redundant witness search; the atomicMin below
+  // is what decides.
+  unsigned long long key = uniform64(*reinterpret_cast<volatile unsigned long long *>(&st->key));
   if (static_cast<int>(key >> 32) <= p.L_before) return;  // bound already met
 
-  int lo = 0, hi = p.ngroups;
+  int lo = 0, hi = p.nruns;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (p.groups[mid].tile0 <= g) lo = mid;
+    if (p.runs[mid].tile0 <= g) lo = mid;
     else hi = mid;
   }
-  const DevGroup &grp = p.groups[lo];
-  const unsigned long long local = g - grp.tile0;
-  const unsigned long long b = local % grp.nb, s = local / grp.nb;
+  const DevRun &run = p.runs[lo];
+  const unsigned long long local = g - run.tile0;
+  unsigned long long b, s;
+  if ((local >> 32) == 0 && (run.tps >> 32) == 0) {
+    const uint32_t l32 = static_cast<uint32_t>(local), t32 = static_cast<uint32_t>(run.tps);
+    b = l32 % t32;
+    s = run.s_begin + l32 / t32;
+  } else {
+    b = local % run.tps;
+    s = run.s_begin + local / run.tps;
+  }
   const unsigned long long k0 = s * p.seg;
-  const unsigned long long k1 = min(k0 + p.seg, grp.len);
+  const unsigned long long k1 = k0 + p.seg;
   const unsigned long long item = b * kWave + lane;
-  const bool active = item < grp.items;
+  const bool active = item < run.items;
 
   uint32_t ax[D], az[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) ax[d] = az[d] = 0;
-  if (active) unrank_top<D>(p, grp.h, item, ax, az);
-
+  unsigned long long lend = k1;  // this lane's end of the segment
+  if (active) {
+    int a = 0, z = static_cast<int>(run.e);
+    while (z - a > 1) {
+      const int mid = (a + z) >> 1;
+      if (GR[mid].cum <= item) a = mid;
+      else z = mid;
+    }
+    lend = min(k1, GR[a].len);
+    if (p.tops) {
+      const uint4 *tp = reinterpret_cast<const uint4 *>(p.tops + (GR[a].top0 + item - GR[a].cum) * kElemWords);
+      const uint4 tx = tp[0], tz = tp[1];
+      const uint32_t vx[4] = {tx.x, tx.y, tx.z, tx.w}, vz[4] = {tz.x, tz.y, tz.z, tz.w};
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        ax[d] = vx[d];
+        az[d] = vz[d];
+      }
+    } else {
+      unrank_top<D>(F, ld, E, p.csize, p.P, p.t - p.u - 1, static_cast<int>(GR[a].h), item - GR[a].cum, ax,
+                    az);
+    }
+  }
+  // Entries [k0, kfull) are valid for every lane; [kfull, kend) for some.
+  const uint32_t span = static_cast<uint32_t>(lend - k0);
+  const uint32_t sfull = __builtin_amdgcn_readfirstlane(wave_min(span));
+  const uint32_t send = __builtin_amdgcn_readfirstlane(wave_max(active ? span : 0u));
   uint32_t best = 0xFFFFFFFFu;
-  const uint32_t nfull = static_cast<uint32_t>((k1 - k0) / kBlock);
+  const uint32_t nfull = sfull / kBlock;
   const uint32_t *blk = p.table + (k0 / kBlock) * (2 * D * kBlock);
   for (uint32_t i = 0; i < nfull; ++i, blk += 2 * D * kBlock) best = block_min<D>(ax, az, blk, best);
-  for (unsigned long long k = k0 + static_cast<unsigned long long>(nfull) * kBlock; k < k1; ++k)
-    best = min(best, weight_at<D>(p.table, k, ax, az));
+  for (uint32_t i = nfull * kBlock; i < send; ++i) {
+    const uint32_t w = weight_at<D>(p.table, k0 + i, ax, az);
+    if (i < span) best = min(best, w);
+  }
   if (!active) best = 0xFFFFFFFFu;
   const uint32_t wmin = wave_min(best);
-  const unsigned long long nact = __popcll(__ballot(active));
-  if (lane == 0) atomicAdd(&st->count, nact * (k1 - k0));
+  const uint32_t visited = wave_sum(active ? span : 0u);
+  if (lane == 0)
+    atomicAdd(p.counters + static_cast<size_t>(wg % kCounters) * kCounterStride,
+              static_cast<unsigned long long>(visited));
 
-  key = uniform64(__hip_atomic_load(&st->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  key = uniform64(*reinterpret_cast<volatile unsigned long long *>(&st->key));
   if (wmin < static_cast<uint32_t>(key >> 32)) {
     // Rare: this tile improves U.  Find where, write the codeword to this
     // tile's own slot, then publish (U, slot) with one 64-bit atomicMin.
-    unsigned long long kf = ~0ull;
-    for (unsigned long long k = k0; k < k1; ++k) {
-      const uint32_t w = weight_at<D>(p.table, k, ax, az);
-      if (w == wmin && kf == ~0ull) kf = k;
+    uint32_t kf = 0xFFFFFFFFu;
+    for (uint32_t i = 0; i < send; ++i) {
+      const uint32_t w = weight_at<D>(p.table, k0 + i, ax, az);
+      if (i < span && w == wmin && kf == 0xFFFFFFFFu) kf = i;
     }
     const unsigned long long mask = __ballot(active && best == wmin);
     const int winner = __ffsll(static_cast<long long>(mask)) - 1;
     if (static_cast<int>(lane) == winner) {
       const uint32_t slot = static_cast<uint32_t>(g - p.tile_lo);
       uint32_t *out = p.slots + static_cast<size_t>(slot) * kElemWords;
-      const uint32_t *e = p.table + (kf / kBlock) * (2 * D * kBlock) + (kf % kBlock);
+      const unsigned long long kk = k0 + kf;
+      const uint32_t *e = p.table + (kk / kBlock) * (2 * D * kBlock) + (kk % kBlock);
 #pragma unroll
       for (int d = 0; d < 4; ++d) {
         out[d] = d < D ? (ax[d] ^ e[d * kBlock]) : 0u;
@@ -182,6 +261,9 @@ __global__ __launch_bounds__(256) void qd_round_kernel(RoundParams p) {
 // Saved table: entry k is the k-th bottom combination of u packages in the
 // order (largest package, its element, then the rest recursively), so the
 // combinations inside packages [0, h) are entries [0, e_u(c_0..c_{h-1})).
+// The tops table is the same construction over the packages in reverse
+// order: combinations whose smallest package is h are the entries
+// [e_u(c_{h+1}..), e_u(c_h..)).
 template <int D>
 __global__ __launch_bounds__(256) void qd_saved_kernel(SavedParams p) {
   const unsigned long long k = static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -189,31 +271,59 @@ __global__ __launch_bounds__(256) void qd_saved_kernel(SavedParams p) {
   uint32_t x[D], z[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) x[d] = z[d] = 0;
+  // E(h, r): combinations of r packages among the first h (in build order).
+  auto E = [&](int h, int r) {
+    return p.tops ? p.suffix[size_t(p.P - h) * p.R + r] : p.prefix[size_t(h) * p.R + r];
+  };
   if (k < p.nent) {
     unsigned long long rest = k;
     int hi = p.P;
     for (int r = p.u; r > 0; --r) {
       int h = hi - 1;
-      while (h > 0 && p.prefix[size_t(h) * p.R + r] > rest) --h;
-      rest -= p.prefix[size_t(h) * p.R + r];
-      const unsigned long long f = p.prefix[size_t(h) * p.R + r - 1];
+      while (h > 0 && E(h, r) > rest) --h;
+      rest -= E(h, r);
+      const unsigned long long f = E(h, r - 1);
       int c = 0;
       while (rest >= f && c < 2) { rest -= f; ++c; }
-      xor_elem<D>(p.elems, h, c, x, z);
+      xor_elem<D>(p.elems, p.tops ? p.P - 1 - h : h, c, x, z);
       hi = h;
     }
   }
-  uint32_t *b = p.table + (k / kBlock) * (2 * D * kBlock) + (k % kBlock);
+  if (p.tops) {
+    uint32_t *e = p.table + k * kElemWords;
 #pragma unroll
-  for (int d = 0; d < D; ++d) {
-    b[d * kBlock] = x[d];
-    b[(D + d) * kBlock] = z[d];
+    for (int d = 0; d < 4; ++d) {
+      e[d] = d < D ? x[d] : 0u;
+      e[4 + d] = d < D ? z[d] : 0u;
+    }
+  } else {
+    uint32_t *b = p.table + (k / kBlock) * (2 * D * kBlock) + (k % kBlock);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      b[d * kBlock] = x[d];
+      b[(D + d) * kBlock] = z[d];
+    }
   }
 }
 
-// Moves the codeword of the winning slot into the code's state.
-__global__ void qd_commit_kernel(DevState *st, const uint32_t *slots) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// After a launch: moves the codeword of the winning slot into the code's
+// state and folds the spread counters into its visited count.
+__global__ __launch_bounds__(256) void qd_commit_kernel(DevState *st, const uint32_t *slots,
+                                                        unsigned long long *counters) {
+  __shared__ unsigned long long part[256];
+  unsigned long long sum = 0;
+  for (int i = threadIdx.x; i < kCounters; i += blockDim.x) {
+    sum += counters[static_cast<size_t>(i) * kCounterStride];
+    counters[static_cast<size_t>(i) * kCounterStride] = 0;
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  st->count += part[0];
   const unsigned long long key = st->key;
   const uint32_t slot = static_cast<uint32_t>(key & 0xFFFFFFFFull);
   if (slot == kNoSlot) return;
@@ -249,11 +359,12 @@ hipError_t launch_round(int D, const RoundParams &p, hipStream_t s) {
   unsigned long long wgs = (tiles + kWavesPerGroup - 1) / kWavesPerGroup;
   wgs = (wgs + 7) / 8 * 8;
   dim3 grid(static_cast<uint32_t>(wgs)), block(kWave * kWavesPerGroup);
+  const unsigned int lds = round_lds_bytes(p.P, p.t, p.u, p.ngroups, p.stage);
   switch (D) {
-    case 1: hipLaunchKernelGGL(qd_round_kernel<1>, grid, block, 0, s, p); break;
-    case 2: hipLaunchKernelGGL(qd_round_kernel<2>, grid, block, 0, s, p); break;
-    case 3: hipLaunchKernelGGL(qd_round_kernel<3>, grid, block, 0, s, p); break;
-    case 4: hipLaunchKernelGGL(qd_round_kernel<4>, grid, block, 0, s, p); break;
+    case 1: hipLaunchKernelGGL(qd_round_kernel<1>, grid, block, lds, s, p); break;
+    case 2: hipLaunchKernelGGL(qd_round_kernel<2>, grid, block, lds, s, p); break;
+    case 3: hipLaunchKernelGGL(qd_round_kernel<3>, grid, block, lds, s, p); break;
+    case 4: hipLaunchKernelGGL(qd_round_kernel<4>, grid, block, lds, s, p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -261,7 +372,7 @@ hipError_t launch_round(int D, const RoundParams &p, hipStream_t s) {
 
 hipError_t launch_saved(int D, const SavedParams &p, hipStream_t s) {
   dim3 grid(static_cast<uint32_t>((p.nent_padded + 255) / 256)), block(256);
-  switch (D) {
+  switch (D) {  // one kernel builds both tables
     case 1: hipLaunchKernelGGL(qd_saved_kernel<1>, grid, block, 0, s, p); break;
     case 2: hipLaunchKernelGGL(qd_saved_kernel<2>, grid, block, 0, s, p); break;
     case 3: hipLaunchKernelGGL(qd_saved_kernel<3>, grid, block, 0, s, p); break;
@@ -271,8 +382,8 @@ hipError_t launch_saved(int D, const SavedParams &p, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_commit(DevState *st, const uint32_t *slots, hipStream_t s) {
-  hipLaunchKernelGGL(qd_commit_kernel, dim3(1), dim3(64), 0, s, st, slots);
+hipError_t launch_commit(DevState *st, const uint32_t *slots, unsigned long long *counters, hipStream_t s) {
+  hipLaunchKernelGGL(qd_commit_kernel, dim3(1), dim3(256), 0, s, st, slots, counters);
   return hipGetLastError();
 }
 

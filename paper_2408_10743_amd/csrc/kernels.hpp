@@ -15,17 +15,32 @@ constexpr int kWavesPerGroup = 4;
 constexpr int kBlock = 8;
 // Low 32 bits of the state key when no slot is pending.
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+// Visited-combination counters, spread over separate 128-byte lines so the
+// waves of a launch do not all update one address.
+constexpr int kCounters = 1024;
+constexpr int kCounterStride = 16;  // unsigned long longs per line
 
 // One group of a round: top combinations whose smallest package is h,
-// paired with the saved-table prefix of combinations below h.
+// paired with the saved-table prefix of combinations below h.  Groups are
+// sorted by len, longest first; cum = items of the groups before it.
 struct DevGroup {
   unsigned long long items;  // top combinations in the group
   unsigned long long len;    // usable saved-table entries
-  unsigned long long tile0;  // first tile of the group
-  unsigned long long nb;     // blocks of 64 items
-  unsigned long long ns;     // segments of the table prefix
-  int h;
-  int pad;
+  unsigned long long cum;    // items of the longer groups
+  unsigned long long top0;   // first entry of the group in the tops table
+  long long h;
+  long long pad;
+};
+
+// A run of table segments [s_begin, s_begin + nseg) that the same `e`
+// longest groups reach; each segment is split into `tps` tiles of 64 tops
+// taken from those groups' items in order.
+struct DevRun {
+  unsigned long long tile0;   // first tile of the run
+  unsigned long long s_begin;
+  unsigned long long items;   // items of the e groups
+  unsigned long long tps;     // tiles per segment
+  long long e;
 };
 
 // Per-code device state: key = (U << 32) | pending slot; count = visited
@@ -39,24 +54,42 @@ struct DevState {
 struct RoundParams {
   const uint32_t *elems;               // package i element e: (3i+e)*kElemWords
   const uint32_t *table;               // saved sums, blocks of kBlock entries
-  const DevGroup *groups;
+  const uint32_t *tops;                // top codewords, kElemWords each (NULL: unrank)
+  const DevGroup *groups;              // sorted by len, longest first
+  const DevRun *runs;
   const unsigned long long *suffix;    // (P+1) x R: e_r(c_h..c_{P-1})
   const unsigned char *csize;          // elements per package (1 or 3)
   DevState *state;
+  unsigned long long *counters;        // kCounters x kCounterStride
   uint32_t *slots;                     // one witness slot per tile of a launch
   unsigned long long tile_lo, tile_hi; // tiles of this launch
-  int ngroups, P, R, t, u;
+  int ngroups, nruns, P, R, t, u;
   unsigned int seg;                    // table entries per tile (multiple of kBlock)
   int L_before;                        // lower bound already certified
+  int stage;                           // 1: copy the groups to LDS; 2: also suffix
+                                       //    columns and elements (unranking path)
 };
 
+// LDS bytes a round kernel launch needs when it stages its tables.
+inline unsigned int round_lds_bytes(int P, int t, int u, int ngroups, int stage) {
+  if (stage == 0) return 0u;
+  unsigned int b = static_cast<unsigned int>(ngroups * sizeof(DevGroup));
+  if (stage == 2) b += static_cast<unsigned int>((P + 1) * (t - u) * 8 + P * 3 * kElemWords * 4);
+  return b;
+}
+
+// Saved table (bottoms: combinations ordered by their largest package,
+// structure of arrays in blocks of kBlock) or tops table (combinations
+// ordered by their smallest package, largest first; kElemWords per entry).
 struct SavedParams {
   const uint32_t *elems;
   const unsigned long long *prefix;    // (P+1) x R: e_r(c_0..c_{h-1})
+  const unsigned long long *suffix;    // (P+1) x R: e_r(c_h..c_{P-1})
   const unsigned char *csize;
   uint32_t *table;
   unsigned long long nent, nent_padded;
   int P, R, u;
+  int tops;                            // 1: build the tops table
 };
 
 }  // namespace qd

@@ -37,7 +37,7 @@ class qd_options(ctypes.Structure):
     _fields_ = [("diag", ctypes.c_int), ("max_gamma", ctypes.c_int),
                 ("budget", ctypes.c_ulonglong), ("cancel", ctypes.POINTER(ctypes.c_int)),
                 ("stream", ctypes.c_void_p), ("seg_len", ctypes.c_int),
-                ("saved_depth", ctypes.c_int), ("timing", ctypes.c_int)]
+                ("saved_depth", ctypes.c_int), ("timing", ctypes.c_int), ("tops_mode", ctypes.c_int)]
 
 
 class qd_round_log(ctypes.Structure):
@@ -142,7 +142,7 @@ def qd_distance(G, field=QD_FIELD_F2):
 def qd_distance_ex(G, field=QD_FIELD_F2, **opts):
     """Returns (status, d, witness, qd_stats).  Options: diag, max_gamma,
     budget, cancel (ctypes.c_int), stream (hipStream_t as int), seg_len,
-    saved_depth, timing."""
+    saved_depth, timing, tops_mode."""
     G, m, n = _matrix(G, field)
     o, _keep = _options(opts)
     d = ctypes.c_int(-1)

@@ -169,6 +169,19 @@ def test_tuning_overrides_do_not_change_results(Q):
         check_distance(Q, G, f, gold["config2"][1], seg_len=seg, saved_depth=depth)
 
 
+def test_tops_table_and_unranking_agree(Q):
+    gold = json.load(open(os.path.join(GOLD_DIR, "oracle_distances.json")))
+    for i in range(4):
+        G, f = W.config2(i)
+        for mode in (1, 2):
+            for depth in (1, 3):
+                check_distance(Q, G, f, gold["config2"][i], tops_mode=mode, saved_depth=depth)
+    for i in range(10):
+        G, f = W.config1(i)
+        d_ref, _ = O.brute(O.expand(G, f))
+        check_distance(Q, G, f, d_ref, tops_mode=2, diag=2)
+
+
 def test_budget_gives_bounds(Q):
     G, f = W.config2(0)
     gold = json.load(open(os.path.join(GOLD_DIR, "oracle_distances.json")))
