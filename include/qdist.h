@@ -72,7 +72,9 @@ typedef struct qd_options {
   const volatile int *cancel; /* host flag polled between rounds (NULL: none) */
   void *stream;               /* hipStream_t for all work (NULL: the library's own) */
   int seg_len;                /* tuning override: table entries per tile, multiple of 8 (0: auto) */
-  int saved_depth;            /* tuning override: max packages in the saved-sum table (0: auto) */
+  int saved_depth;            /* tuning override: max packages in the saved-sum table (0: auto;
+                                 -1: none, each lane forms its whole combination -- the
+                                 plain per-code path, for comparisons) */
   int timing;                 /* 1: time every enumeration launch with HIP events */
   int tops_mode;              /* tuning override: 0 auto, 1 tops from a table,
                                  2 tops unranked by each lane */
@@ -130,12 +132,14 @@ int qd_distance(const uint8_t *G, int m, int n, int field, int *d, uint8_t *witn
 int qd_distance_ex(const uint8_t *G, int m, int n, int field, const qd_options *opt,
                    int *d, uint8_t *witness, qd_stats *st);
 
-/* Distances of `count` independent codes in one persistent launch per
- * enumeration step, each code's rounds advancing on its own.  Arrays are
- * indexed by code; witness may be NULL or hold NULL entries; status[i]
- * receives the per-code status.  Returns QD_OK when every code finished,
- * else the first negative status.  opt may be NULL (budget and cancel apply
- * to every code). */
+/* Distances of `count` independent codes.  Every code's rounds advance on
+ * their own; each step of the batch launches the next round piece of every
+ * unfinished code together (one enumeration launch per word count D), so
+ * small codes fill the device jointly.  Arrays are indexed by code; witness
+ * may be NULL or hold NULL entries; status[i] receives the per-code status
+ * (as qd_distance).  Returns QD_OK when no code failed, else the first
+ * negative status.  opt may be NULL; its budget and cancel apply to every
+ * code.  Results equal those of qd_distance on each code alone. */
 int qd_distance_batch(int count, const uint8_t *const *G, const int *m, const int *n,
                       const int *field, int *d, uint8_t *const *witness, int *status);
 int qd_distance_batch_ex(int count, const uint8_t *const *G, const int *m, const int *n,
@@ -156,6 +160,52 @@ int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma,
  * (witness: 2n bytes or NULL) and the number of combinations visited. */
 int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int *wmin,
                  uint8_t *witness, unsigned long long *count);
+
+/* -- Serving: continuous batching of distance requests ------------------------
+ * A qd_engine owns a worker thread and a HIP stream.  Requests are checked
+ * and planned on the submitting thread, then wait until the worker admits
+ * them: first come first served, while fewer than max_active codes are on
+ * the device and their estimated device footprint (generator matrices,
+ * saved tables) fits mem_budget.  Every step of the worker launches the next
+ * round piece of every admitted code together, so requests that arrive
+ * while others run join the device work at the next step.  Results are
+ * identical to qd_distance on the same input (the enumeration, bounds and
+ * stopping rule do not depend on what else is in the step). */
+typedef struct qd_engine qd_engine;
+
+typedef struct qd_result {
+  unsigned long long tag;     /* caller's tag from qd_engine_submit */
+  int status;                 /* as qd_distance */
+  int d;                      /* distance (-1 on error) */
+  int L;                      /* certified lower bound (= d unless QD_INCOMPLETE) */
+  int n;
+  double latency_ms;          /* submit to completion */
+  double queue_ms;            /* submit to admission */
+  unsigned long long combinations;
+} qd_result;
+
+/* mem_budget: device bytes for admitted codes (0: 8 GiB); max_active: codes
+ * on the device at once (0: 512); stream: hipStream_t or NULL (own stream).
+ * Returns NULL without a usable gfx950 device. */
+qd_engine *qd_engine_create(size_t mem_budget, int max_active, void *stream);
+
+/* Copies G and queues it; opt may be NULL (its stream and timing fields are
+ * ignored).  Returns QD_OK, or a negative status for a rejected request
+ * (which is still reported by qd_engine_poll with that status). */
+int qd_engine_submit(qd_engine *e, const uint8_t *G, int m, int n, int field, unsigned long long tag,
+                     const qd_options *opt);
+
+/* Moves up to max finished results to out (and their witnesses to
+ * witness + i * 2 * QD_MAX_N when witness is not NULL), waiting up to
+ * wait_ms for the first one.  Returns the number of results. */
+int qd_engine_poll(qd_engine *e, qd_result *out, uint8_t *witness, int max, int wait_ms);
+
+/* Requests submitted and not yet returned by qd_engine_poll. */
+int qd_engine_outstanding(qd_engine *e);
+
+/* Stops the worker: queued and running requests end as QD_INCOMPLETE and
+ * are discarded.  The engine pointer is invalid afterwards. */
+void qd_engine_destroy(qd_engine *e);
 
 /* Human-readable status. */
 const char *qd_strerror(int status);

@@ -1,0 +1,612 @@
+// engine.cpp -- step executor: device memory, per-code rounds, batched
+// launches of the enumeration kernel, commit and readback.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+namespace qd {
+
+hipError_t launch_round(int D, const LaunchParams &lp, hipStream_t s);
+hipError_t launch_saved(int D, const SavedParams &p, hipStream_t s);
+hipError_t launch_commit(const LaunchParams &lp, hipStream_t s);
+
+namespace {
+
+constexpr int kDefaultSavedDepth = 4;                     // packages per saved-table entry
+constexpr unsigned long long kMaxTableBytes = 1ull << 29;
+constexpr unsigned long long kMaxTopEntries = 1ull << 24;  // 512 MB of tops
+constexpr unsigned long long kTilesPerLaunch = 1ull << 21;
+constexpr unsigned long long kTargetTiles = 1ull << 18;    // ~32 tiles per wave slot
+constexpr unsigned kMinSeg = 256, kMaxSeg = 16384;
+constexpr unsigned kStageMaxBytes = 32768;
+constexpr size_t kBigClass = size_t(64) << 20;
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+size_t size_class(size_t b) {
+  size_t c = 256;
+  while (c < b && c < kBigClass) c <<= 1;
+  if (b > c) c = (b + kBigClass - 1) / kBigClass * kBigClass;
+  return c;
+}
+
+void to_words(const BRow &r, uint32_t *w) {
+  w[0] = uint32_t(r.x[0]); w[1] = uint32_t(r.x[0] >> 32);
+  w[2] = uint32_t(r.x[1]); w[3] = uint32_t(r.x[1] >> 32);
+  w[4] = uint32_t(r.z[0]); w[5] = uint32_t(r.z[0] >> 32);
+  w[6] = uint32_t(r.z[1]); w[7] = uint32_t(r.z[1] >> 32);
+}
+
+BRow from_words(const uint32_t *w) {
+  BRow r;
+  r.x[0] = uint64_t(w[0]) | (uint64_t(w[1]) << 32);
+  r.x[1] = uint64_t(w[2]) | (uint64_t(w[3]) << 32);
+  r.z[0] = uint64_t(w[4]) | (uint64_t(w[5]) << 32);
+  r.z[1] = uint64_t(w[6]) | (uint64_t(w[7]) << 32);
+  return r;
+}
+
+bool in_span(const std::vector<BRow> &basis, int n, const BRow &v) {
+  std::vector<BRow> rows = basis;
+  const int k = make_basis(rows, n);
+  rows.push_back(v);
+  return make_basis(rows, n) == k;
+}
+
+// Saved-table depth for round t: u = t-2, so every top keeps two packages
+// (a group then fills many lanes), within the cap and the table-size limit.
+int saved_depth(const GammaDev &g, int D, int t, int cap) {
+  int u = std::min(std::max(t - 2, 0), cap);
+  while (u > 0 && g.prefix[size_t(g.P) * g.R + u] * 8ull * D > kMaxTableBytes) --u;
+  return u;
+}
+
+// Table entries per tile: long enough to amortize a tile's setup, short
+// enough for about kTargetTiles tiles per round.
+unsigned choose_seg(unsigned long long planned) {
+  const unsigned long long want = planned / (kWave * kTargetTiles);
+  unsigned seg = kMinSeg;
+  while (seg < want && seg < kMaxSeg) seg <<= 1;
+  return seg;
+}
+
+// Tiles of one round.  Group h pairs the tops whose smallest package is h
+// (c_h * e_{t-u-1}(c_{h+1}..)) with the first e_u(c_0..c_{h-1}) table
+// entries.  Segment s of the table is shared by every group reaching it,
+// so its tiles take 64 tops at a time from those groups together.
+unsigned long long plan_round(const GammaDev &g, int t, int u, unsigned seg, std::vector<DevGroup> &groups,
+                              std::vector<DevRun> &runs) {
+  groups.clear();
+  runs.clear();
+  const int R = g.R, r = t - u - 1;
+  for (int h = 0; h < g.P; ++h) {
+    const unsigned long long items = g.suffix[size_t(h + 1) * R + r] * g.sizes[h];
+    const unsigned long long len = g.prefix[size_t(h) * R + u];
+    if (!items || !len) continue;
+    DevGroup grp{};
+    grp.items = items;
+    grp.len = len;
+    grp.top0 = g.suffix[size_t(h + 1) * R + (t - u)];
+    grp.h = h;
+    groups.push_back(grp);
+  }
+  std::stable_sort(groups.begin(), groups.end(), [](const DevGroup &a, const DevGroup &b) { return a.len > b.len; });
+  unsigned long long cum = 0, tiles = 0;
+  std::vector<unsigned long long> ns(groups.size());
+  for (size_t i = 0; i < groups.size(); ++i) {
+    groups[i].cum = cum;
+    cum += groups[i].items;
+    ns[i] = (groups[i].len + seg - 1) / seg;
+  }
+  // Segments [ns[e], ns[e-1]) are reached by exactly the e longest groups.
+  const size_t G = groups.size();
+  for (size_t e = G; e >= 1; --e) {
+    const unsigned long long sa = e == G ? 0 : ns[e], sb = ns[e - 1];
+    if (sa >= sb) continue;
+    DevRun run{};
+    run.tile0 = tiles;
+    run.s_begin = sa;
+    run.e = static_cast<long long>(e);
+    run.items = e == G ? cum : groups[e].cum;
+    run.tps = (run.items + kWave - 1) / kWave;
+    tiles += (sb - sa) * run.tps;
+    runs.push_back(run);
+  }
+  return tiles;
+}
+
+}  // namespace
+
+// -- DevPool -------------------------------------------------------------------
+
+DevPool::~DevPool() {
+  for (void *p : all_) (void)hipFree(p);
+}
+
+void *DevPool::get(size_t bytes, size_t *cls) {
+  const size_t c = size_class(std::max<size_t>(bytes, 1));
+  auto &v = free_[c];
+  if (!v.empty()) {
+    void *p = v.back();
+    v.pop_back();
+    *cls = c;
+    return p;
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, c) != hipSuccess) {
+    // Give cached blocks back to the driver and try once more.
+    for (auto &kv : free_)
+      for (void *q : kv.second) {
+        (void)hipFree(q);
+        all_.erase(std::find(all_.begin(), all_.end(), q));
+        held_ -= kv.first;
+      }
+    free_.clear();
+    if (hipMalloc(&p, c) != hipSuccess) return nullptr;
+  }
+  all_.push_back(p);
+  held_ += c;
+  *cls = c;
+  return p;
+}
+
+void DevPool::put(void *p, size_t cls) {
+  if (p) free_[cls].push_back(p);
+}
+
+// -- Executor ------------------------------------------------------------------
+
+Executor::Executor(hipStream_t stream) {
+  int dev = 0, cnt = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceCount(&cnt) != hipSuccess || cnt <= 0 || hipGetDevice(&dev) != hipSuccess ||
+      hipGetDeviceProperties(&prop, dev) != hipSuccess || !std::strstr(prop.gcnArchName, "gfx950"))
+    return;
+  if (stream) {
+    stream_ = stream;
+  } else {
+    if (hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking) != hipSuccess) return;
+    own_stream_ = true;
+  }
+  ok_ = grow_states(64) == QD_OK;
+}
+
+Executor::~Executor() {
+  if (states_) (void)hipFree(states_);
+  if (hstates_) (void)hipHostFree(hstates_);
+  for (hipEvent_t e : events_) (void)hipEventDestroy(e);
+  if (own_stream_) (void)hipStreamDestroy(stream_);
+}
+
+bool Executor::alloc(PoolBuf &b, size_t bytes) {
+  if (b.p && b.cls >= bytes) {
+    b.bytes = bytes;
+    return true;
+  }
+  release(b);
+  b.p = pool_.get(bytes, &b.cls);
+  b.bytes = bytes;
+  return b.p != nullptr;
+}
+
+void Executor::release(PoolBuf &b) {
+  if (b.p) pool_.put(b.p, b.cls);
+  b = PoolBuf{};
+}
+
+int Executor::grow_states(int need) {
+  if (nstates_ >= need) return QD_OK;
+  const int cap = std::max(need, 2 * nstates_);
+  DevState *d = nullptr, *h = nullptr;
+  if (hipMalloc(reinterpret_cast<void **>(&d), sizeof(DevState) * cap) != hipSuccess) return QD_ERR_NOMEM;
+  if (hipHostMalloc(reinterpret_cast<void **>(&h), sizeof(DevState) * cap, hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(d);
+    return QD_ERR_NOMEM;
+  }
+  std::memset(h, 0, sizeof(DevState) * cap);
+  if (states_) {
+    if (hipStreamSynchronize(stream_) != hipSuccess ||
+        hipMemcpy(d, states_, sizeof(DevState) * nstates_, hipMemcpyDeviceToDevice) != hipSuccess)
+      return QD_ERR_DEVICE;
+    std::memcpy(h, hstates_, sizeof(DevState) * nstates_);
+    (void)hipFree(states_);
+    (void)hipHostFree(hstates_);
+  }
+  for (int i = cap - 1; i >= nstates_; --i) free_slots_.push_back(i);
+  states_ = d;
+  hstates_ = h;
+  nstates_ = cap;
+  return QD_OK;
+}
+
+void Executor::prepare(Job &job) {
+  job.t0 = now_ms();
+  qd_options &o = job.opt;
+  std::memset(&job.S, 0, sizeof(job.S));
+  if (o.diag != QD_DIAG_AUTO && o.diag != QD_DIAG_F2 && o.diag != QD_DIAG_F4) { job.status = QD_ERR_INVALID; return; }
+  if (o.seg_len < 0 || o.seg_len % kBlock || o.saved_depth < -1 || o.max_gamma < 0 || o.tops_mode < 0 ||
+      o.tops_mode > 2) {
+    job.status = QD_ERR_INVALID;
+    return;
+  }
+  int rc = load_rows(job.G.data(), job.m, job.n, job.field, job.basis);
+  if (rc) { job.status = rc; return; }
+  const int n = job.n;
+  job.rank = make_basis(job.basis, n);
+  if (job.rank == 0) { job.status = QD_ERR_ZERO_CODE; return; }
+  if (job.use.empty()) {
+    std::vector<Gamma> f4 = build_f4(job.basis, n, kMaxGamma);
+    Gamma f2 = build_f2(job.basis, n);
+    for (const Gamma &g : f4)
+      if (!check_gamma(g, n)) { job.status = QD_ERR_INTERNAL; return; }
+    if (!check_gamma(f2, n)) { job.status = QD_ERR_INTERNAL; return; }
+    job.pc = choose_plan(f4, f2, n, job.rank, o.diag, o.max_gamma);
+    if (job.pc.diag == QD_DIAG_F2) job.use.push_back(f2);
+    else job.use.assign(f4.begin(), f4.begin() + job.pc.h_used);
+  }
+  prepare_gammas(job);
+}
+
+void Executor::prepare_gammas(Job &job) {
+  const int n = job.n;
+  const int h = int(job.use.size());
+  job.D = (n + 31) / 32;
+  job.S.n = n; job.S.rank = job.rank; job.S.D = job.D; job.S.diag = job.pc.diag; job.S.h = h;
+  job.S.d_estimate = job.pc.d_est; job.S.predicted = job.pc.predicted;
+  job.tdone.assign(h, 0);
+  job.delta.resize(h);
+  for (int j = 0; j < h; ++j) {
+    job.S.P[j] = job.use[j].P();
+    job.S.delta[j] = job.delta[j] = job.use[j].delta;
+  }
+  job.L = lower_bound(job.tdone, job.delta);
+  job.U = n + 1;
+  job.gd.assign(h, GammaDev{});
+  for (int j = 0; j < h; ++j) {
+    GammaDev &g = job.gd[j];
+    const Gamma &gm = job.use[j];
+    g.P = gm.P();
+    g.R = std::min(g.P, kTMax) + 1;
+    g.h_elems.assign(size_t(g.P) * 3 * kElemWords, 0);
+    g.h_csize.assign(g.P, 0);
+    for (int i = 0; i < g.P; ++i) {
+      const Package &p = gm.pk[i];
+      to_words(p.r, &g.h_elems[size_t(3 * i) * kElemWords]);
+      if (p.dim == 2) {
+        BRow rs = p.r;
+        radd(rs, p.s);
+        to_words(p.s, &g.h_elems[size_t(3 * i + 1) * kElemWords]);
+        to_words(rs, &g.h_elems[size_t(3 * i + 2) * kElemWords]);
+      }
+      g.h_csize[i] = p.dim == 2 ? 3 : 1;
+      g.sizes.push_back(g.h_csize[i]);
+    }
+    esym_tables(g.sizes, g.R - 1, g.prefix, g.suffix);
+  }
+}
+
+size_t Executor::footprint(const Job &job) {
+  size_t b = size_t(kCountersPerCode) * kCounterStride * 8 + 64 * 1024;
+  for (const GammaDev &g : job.gd) {
+    b += g.h_elems.size() * 4 + g.prefix.size() * 16 + g.P;
+    for (int u = 0; u <= std::min(kDefaultSavedDepth, g.R - 1); ++u)
+      b += size_t(std::min<uint64_t>(g.prefix[size_t(g.P) * g.R + u] * 8ull * job.D, kMaxTableBytes));
+    for (int k = 1; k <= std::min(3, g.R - 1); ++k)
+      b += size_t(std::min<uint64_t>(g.suffix[k], kMaxTopEntries) * 32ull);
+  }
+  return b;
+}
+
+int Executor::admit(Job &job, hipStream_t s) {
+  if (job.status) return job.status;
+  if (free_slots_.empty() && grow_states(nstates_ + 64) != QD_OK) return QD_ERR_NOMEM;
+  job.state_slot = free_slots_.back();
+  free_slots_.pop_back();
+  DevState &hs = hstates_[job.state_slot];
+  std::memset(&hs, 0, sizeof(hs));
+  hs.key = (static_cast<unsigned long long>(job.n + 1) << 32) | kNoSlot;
+  if (hipMemcpyAsync(states_ + job.state_slot, &hs, sizeof(DevState), hipMemcpyHostToDevice, s) != hipSuccess)
+    return QD_ERR_DEVICE;
+  const size_t cb = size_t(kCountersPerCode) * kCounterStride * 8;
+  if (!alloc(job.counters, cb)) return QD_ERR_NOMEM;
+  if (hipMemsetAsync(job.counters.p, 0, cb, s) != hipSuccess) return QD_ERR_DEVICE;
+  for (GammaDev &g : job.gd) {
+    const size_t tb = g.prefix.size() * sizeof(uint64_t);
+    if (!alloc(g.elems, g.h_elems.size() * 4) || !alloc(g.csize, g.h_csize.size() + 1) || !alloc(g.dprefix, tb) ||
+        !alloc(g.dsuffix, tb))
+      return QD_ERR_NOMEM;
+    if (hipMemcpyAsync(g.elems.p, g.h_elems.data(), g.h_elems.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(g.csize.p, g.h_csize.data(), g.h_csize.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(g.dprefix.p, g.prefix.data(), tb, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(g.dsuffix.p, g.suffix.data(), tb, hipMemcpyHostToDevice, s) != hipSuccess)
+      return QD_ERR_DEVICE;
+  }
+  job.S.host_ms = now_ms() - job.t0;
+  return QD_OK;
+}
+
+int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops, hipStream_t s) {
+  PoolBuf &buf = tops ? g.tops[u] : g.table[u];
+  if (buf.p) return QD_OK;
+  const unsigned long long nent = tops ? g.suffix[u] : g.prefix[size_t(g.P) * g.R + u];
+  const unsigned long long padded = (nent + kBlock - 1) / kBlock * kBlock;
+  if (!alloc(buf, size_t(padded) * (tops ? kElemWords : 2 * job.D) * 4)) return QD_ERR_NOMEM;
+  SavedParams sp;
+  sp.elems = static_cast<const uint32_t *>(g.elems.p);
+  sp.prefix = static_cast<const unsigned long long *>(g.dprefix.p);
+  sp.suffix = static_cast<const unsigned long long *>(g.dsuffix.p);
+  sp.csize = static_cast<const unsigned char *>(g.csize.p);
+  sp.table = static_cast<uint32_t *>(buf.p);
+  sp.nent = nent;
+  sp.nent_padded = padded;
+  sp.P = g.P;
+  sp.R = g.R;
+  sp.u = u;
+  sp.tops = tops ? 1 : 0;
+  return launch_saved(job.D, sp, s) == hipSuccess ? QD_OK : QD_ERR_DEVICE;
+}
+
+int Executor::begin_round(Job &job, hipStream_t s) {
+  const int h = int(job.use.size());
+  if (!job.single_round) {
+    for (;;) {
+      if (job.j >= h) { job.j = 0; ++job.t; }
+      if (job.t > job.use[job.j].P()) {
+        bool any = false;
+        for (int j = 0; j < h; ++j) any = any || job.t <= job.use[j].P();
+        if (!any) { job.done = true; return QD_OK; }
+        ++job.j;
+        continue;
+      }
+      break;
+    }
+  }
+  GammaDev &g = job.gd[job.j];
+  const int t = job.t;
+  if (t > kTMax || (job.opt.cancel && *job.opt.cancel)) {
+    job.incomplete = job.done = true;
+    return QD_OK;
+  }
+  const uint64_t planned = g.prefix[size_t(g.P) * g.R + t];
+  if (planned >= kSat || (job.opt.budget && job.planned_total + planned > job.opt.budget)) {
+    job.incomplete = job.done = true;
+    return QD_OK;
+  }
+  const int cap = job.opt.saved_depth < 0 ? 0 : job.opt.saved_depth ? job.opt.saved_depth : kDefaultSavedDepth;
+  job.u = saved_depth(g, job.D, t, cap);
+  job.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : choose_seg(planned);
+  const int tm = job.opt.tops_mode;
+  job.use_tops = tm == 1 || (tm == 0 && g.suffix[t - job.u] <= kMaxTopEntries);
+  int rc = ensure_table(job, g, job.u, false, s);
+  if (!rc && job.use_tops) rc = ensure_table(job, g, t - job.u, true, s);
+  if (rc) return rc;
+  job.round_tiles = plan_round(g, t, job.u, job.seg, job.h_groups, job.h_runs);
+  const size_t gb = job.h_groups.size() * sizeof(DevGroup), rb = job.h_runs.size() * sizeof(DevRun);
+  if (!alloc(job.groups, gb) || !alloc(job.runs, rb)) return QD_ERR_NOMEM;
+  if (hipMemcpyAsync(job.groups.p, job.h_groups.data(), gb, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(job.runs.p, job.h_runs.data(), rb, hipMemcpyHostToDevice, s) != hipSuccess)
+    return QD_ERR_DEVICE;
+  job.tiles_sent = 0;
+  job.round_planned = planned;
+  job.round_launches = 0;
+  job.round_ms = 0.f;
+  job.in_round = true;
+  return QD_OK;
+}
+
+void Executor::end_round(Job &job) {
+  const DevState &hs = hstates_[job.state_slot];
+  const int Ud = int(hs.key >> 32);
+  if (Ud < job.U) {
+    job.U = Ud;
+    job.wit = from_words(hs.wit);
+  }
+  const unsigned long long this_round = hs.count - job.visited;
+  job.visited = hs.count;
+  job.planned_total += job.round_planned;
+  job.tdone[job.j] = job.t;
+  job.L = lower_bound(job.tdone, job.delta);
+  qd_stats &S = job.S;
+  S.kernel_ms += job.round_ms;
+  if (S.nlog < QD_MAX_LOG) {
+    qd_round_log &lg = S.log[S.nlog];
+    lg.t = job.t; lg.j = job.j; lg.L = job.L; lg.U = job.U; lg.saved_depth = job.u;
+    lg.launches = job.round_launches; lg.combinations = this_round; lg.planned = job.round_planned;
+    lg.kernel_ms = job.round_ms;
+  }
+  ++S.nlog;
+  job.in_round = false;
+  if (job.single_round || job.L >= job.U || job.t == job.use[job.j].P()) job.done = true;
+  ++job.j;
+}
+
+int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
+  for (Job *jp : jobs) {
+    if (jp->done || jp->in_round || jp->status) continue;
+    const int rc = begin_round(*jp, s);
+    if (rc) { jp->status = rc; jp->done = true; }
+  }
+  struct Launch {
+    int D;
+    size_t d0, d1;
+    unsigned long long tiles;
+    unsigned lds;
+    bool timed;
+  };
+  std::vector<Launch> launches;
+  std::vector<Job *> members;  // job of each descriptor
+  descs_.clear();
+  unsigned long long max_tiles = 0;
+  for (int D = 1; D <= 4; ++D) {
+    Launch L{D, descs_.size(), 0, 0, 0, false};
+    for (Job *jp : jobs) {
+      Job &job = *jp;
+      if (job.done || !job.in_round || job.D != D || job.status) continue;
+      const unsigned long long left = job.round_tiles - job.tiles_sent;
+      const unsigned long long take = std::min(left, kTilesPerLaunch - std::min(kTilesPerLaunch, L.tiles));
+      if (take == 0) continue;
+      GammaDev &g = job.gd[job.j];
+      RoundDesc d{};
+      d.elems = static_cast<const uint32_t *>(g.elems.p);
+      d.table = static_cast<const uint32_t *>(g.table[job.u].p);
+      d.tops = job.use_tops ? static_cast<const uint32_t *>(g.tops[job.t - job.u].p) : nullptr;
+      d.groups = static_cast<const DevGroup *>(job.groups.p);
+      d.runs = static_cast<const DevRun *>(job.runs.p);
+      d.suffix = static_cast<const unsigned long long *>(g.dsuffix.p);
+      d.csize = static_cast<const unsigned char *>(g.csize.p);
+      d.state = states_ + job.state_slot;
+      d.counters = static_cast<unsigned long long *>(job.counters.p);
+      d.tile_begin = L.tiles;
+      d.ntiles = take;
+      d.tile_lo = job.tiles_sent;
+      d.slot0 = L.tiles;
+      d.ngroups = int(job.h_groups.size());
+      d.nruns = int(job.h_runs.size());
+      d.P = g.P;
+      d.R = g.R;
+      d.t = job.t;
+      d.u = job.u;
+      d.seg = job.seg;
+      d.L_before = job.single_round ? -1 : job.L;
+      d.stage = job.use_tops ? 1 : 2;
+      unsigned lds = round_lds_bytes(d.P, d.t, d.u, d.ngroups, d.stage);
+      if (lds > kStageMaxBytes) { d.stage = 0; lds = 0; }
+      L.lds = std::max(L.lds, lds);
+      L.timed = L.timed || job.opt.timing;
+      L.tiles += (take + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
+      job.tiles_sent += take;
+      ++job.round_launches;
+      descs_.push_back(d);
+      members.push_back(jp);
+    }
+    L.d1 = descs_.size();
+    if (L.d1 > L.d0) {
+      launches.push_back(L);
+      max_tiles = std::max(max_tiles, L.tiles);
+    }
+  }
+  if (!launches.empty()) {
+    if (!alloc(desc_buf_, descs_.size() * sizeof(RoundDesc)) ||
+        !alloc(slots_, size_t(max_tiles) * kElemWords * 4))
+      return QD_ERR_NOMEM;
+    if (hipMemcpyAsync(desc_buf_.p, descs_.data(), descs_.size() * sizeof(RoundDesc), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+      return QD_ERR_DEVICE;
+    while (events_.size() < 2 * launches.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return QD_ERR_DEVICE;
+      events_.push_back(e);
+    }
+    for (size_t i = 0; i < launches.size(); ++i) {
+      const Launch &L = launches[i];
+      LaunchParams lp;
+      lp.desc = static_cast<const RoundDesc *>(desc_buf_.p) + L.d0;
+      lp.ndesc = int(L.d1 - L.d0);
+      lp.lds = L.lds;
+      lp.tiles = L.tiles;
+      lp.slots = static_cast<uint32_t *>(slots_.p);
+      if (L.timed && hipEventRecord(events_[2 * i], s) != hipSuccess) return QD_ERR_DEVICE;
+      if (launch_round(L.D, lp, s) != hipSuccess) return QD_ERR_DEVICE;
+      if (L.timed && hipEventRecord(events_[2 * i + 1], s) != hipSuccess) return QD_ERR_DEVICE;
+      if (launch_commit(lp, s) != hipSuccess) return QD_ERR_DEVICE;
+    }
+  }
+  if (hipMemcpyAsync(hstates_, states_, sizeof(DevState) * nstates_, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return QD_ERR_DEVICE;
+  for (size_t i = 0; i < launches.size(); ++i) {
+    const Launch &L = launches[i];
+    if (!L.timed) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, events_[2 * i], events_[2 * i + 1]) != hipSuccess) return QD_ERR_DEVICE;
+    for (size_t d = L.d0; d < L.d1; ++d) members[d]->round_ms += ms;
+  }
+  for (Job *jp : jobs) {
+    Job &job = *jp;
+    if (job.done || !job.in_round || job.status) continue;
+    if (job.tiles_sent == job.round_tiles) end_round(job);
+  }
+  return QD_OK;
+}
+
+void Executor::retire(Job &job) {
+  const double t1 = now_ms();
+  if (!job.status) {
+    qd_stats &S = job.S;
+    S.L = job.L;
+    S.U = job.U;
+    S.combinations = job.visited;
+    // The witness must have weight U and lie in the row space.
+    const bool wit_ok = job.U <= job.n && rweight(job.wit) == job.U && in_span(job.basis, job.n, job.wit);
+    if (job.single_round) {
+      // U is the round minimum (n + 1 if the round is empty), not a distance
+    } else if (job.incomplete) {
+      job.status = (job.U > job.n || wit_ok) ? QD_INCOMPLETE : QD_ERR_INTERNAL;
+    } else {
+      job.status = wit_ok ? QD_OK : QD_ERR_INTERNAL;
+    }
+    S.wall_ms = t1 - job.t0;
+  }
+  for (GammaDev &g : job.gd) {
+    release(g.elems); release(g.csize); release(g.dprefix); release(g.dsuffix);
+    for (int u = 0; u <= kTMax; ++u) { release(g.table[u]); release(g.tops[u]); }
+  }
+  release(job.counters);
+  release(job.groups);
+  release(job.runs);
+  if (job.state_slot >= 0) free_slots_.push_back(job.state_slot);
+  job.state_slot = -1;
+  job.t_done = t1;
+}
+
+int run_jobs(Executor &ex, std::vector<Job *> &jobs, hipStream_t s) {
+  for (Job *jp : jobs) {
+    if (jp->status) { jp->done = true; continue; }
+    const int rc = ex.admit(*jp, s);
+    if (rc) { jp->status = rc; jp->done = true; }
+  }
+  for (;;) {
+    bool any = false;
+    for (Job *jp : jobs) any = any || !jp->done;
+    if (!any) break;
+    const int rc = ex.step(jobs, s);
+    if (rc) {
+      for (Job *jp : jobs)
+        if (!jp->done) { jp->status = rc; jp->done = true; }
+      break;
+    }
+  }
+  for (Job *jp : jobs) ex.retire(*jp);
+  return QD_OK;
+}
+
+int default_executor(Executor **ex, std::unique_lock<std::mutex> *lock) {
+  static std::mutex mu;
+  static std::vector<std::unique_ptr<Executor>> per_dev;
+  static std::vector<std::unique_ptr<std::mutex>> locks;
+  int dev = 0, cnt = 0;
+  if (hipGetDeviceCount(&cnt) != hipSuccess || cnt <= 0 || hipGetDevice(&dev) != hipSuccess) return QD_ERR_DEVICE;
+  std::mutex *m = nullptr;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    if (int(per_dev.size()) <= dev) {
+      per_dev.resize(dev + 1);
+      locks.resize(dev + 1);
+    }
+    if (!per_dev[dev]) {
+      per_dev[dev] = std::make_unique<Executor>();
+      locks[dev] = std::make_unique<std::mutex>();
+    }
+    if (!per_dev[dev]->ok()) return QD_ERR_DEVICE;
+    *ex = per_dev[dev].get();
+    m = locks[dev].get();
+  }
+  *lock = std::unique_lock<std::mutex>(*m);
+  return QD_OK;
+}
+
+}  // namespace qd

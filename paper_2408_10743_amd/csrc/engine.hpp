@@ -1,0 +1,144 @@
+// engine.hpp -- the step executor shared by the single-code, batched and
+// serving entry points.  A step launches, for every active code, the next
+// piece of its current (t, Gamma_j) round; all pieces of codes with the
+// same word count D go into one kernel launch, followed by one commit
+// launch and one readback of every code's state.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "../../include/qdist.h"
+#include "host.hpp"
+#include "kernels.hpp"
+
+namespace qd {
+
+constexpr int kTMax = 48;  // deepest round supported
+
+// Grow-only caching allocator of device memory (size classes; blocks go
+// back to a free list and are reused by later codes).
+class DevPool {
+ public:
+  ~DevPool();
+  void *get(size_t bytes, size_t *cls);
+  void put(void *p, size_t cls);
+  size_t held() const { return held_; }
+
+ private:
+  std::map<size_t, std::vector<void *>> free_;
+  std::vector<void *> all_;
+  size_t held_ = 0;
+};
+
+struct PoolBuf {
+  void *p = nullptr;
+  size_t cls = 0;
+  size_t bytes = 0;
+};
+
+// Device copy of one generator matrix and its saved / tops tables.
+struct GammaDev {
+  int P = 0, R = 0;
+  std::vector<int> sizes;
+  std::vector<uint64_t> prefix, suffix;  // e_r tables (host copies)
+  std::vector<uint32_t> h_elems;
+  std::vector<unsigned char> h_csize;
+  PoolBuf elems, csize, dprefix, dsuffix;
+  PoolBuf table[kTMax + 1], tops[kTMax + 1];
+};
+
+// One code: request, plan, device data and progress through its rounds.
+struct Job {
+  // request
+  std::vector<uint8_t> G;
+  int m = 0, n = 0, field = 2;
+  qd_options opt{};
+  bool single_round = false;  // run exactly round t of use[0] (no early exit)
+  uint64_t tag = 0;
+  double t_submit = 0.0;
+  // plan
+  int status = QD_OK;
+  int D = 1, rank = 0;
+  std::vector<BRow> basis;
+  std::vector<Gamma> use;
+  PlanChoice pc;
+  std::vector<GammaDev> gd;
+  int state_slot = -1;
+  PoolBuf counters, groups, runs;
+  std::vector<DevGroup> h_groups;
+  std::vector<DevRun> h_runs;
+  // progress
+  std::vector<int> tdone, delta;
+  int L = 0, U = 0;
+  BRow wit;
+  unsigned long long visited = 0, planned_total = 0;
+  int t = 1, j = 0;
+  bool in_round = false, done = false, incomplete = false;
+  int u = 0;
+  unsigned seg = 0;
+  bool use_tops = true;
+  unsigned long long round_tiles = 0, tiles_sent = 0, round_planned = 0;
+  int round_launches = 0;
+  float round_ms = 0.f;
+  qd_stats S{};
+  double t0 = 0.0;
+  double t_done = 0.0;
+};
+
+class Executor {
+ public:
+  explicit Executor(hipStream_t stream = nullptr);
+  ~Executor();
+  bool ok() const { return ok_; }
+  hipStream_t stream() const { return stream_; }
+  size_t device_bytes() const { return pool_.held(); }
+
+  // Host-side preparation of a job (input check, basis, diagonalizations,
+  // plan).  Thread-safe; touches no device state.
+  static void prepare(Job &job);
+  // The part of prepare() after the generator matrices are chosen.
+  static void prepare_gammas(Job &job);
+  // Device upload of a prepared job (needs a free state slot).
+  int admit(Job &job, hipStream_t s);
+  // One step over the given jobs; finished jobs get done = true.
+  int step(std::vector<Job *> &jobs, hipStream_t s);
+  // Final checks, outputs and release of the job's device memory.
+  void retire(Job &job);
+  // Estimated device bytes of a prepared job (admission control).
+  static size_t footprint(const Job &job);
+
+ private:
+  int begin_round(Job &job, hipStream_t s);
+  void end_round(Job &job);
+  int ensure_table(Job &job, GammaDev &g, int u, bool tops, hipStream_t s);
+  bool alloc(PoolBuf &b, size_t bytes);
+  void release(PoolBuf &b);
+  int grow_states(int need);
+
+  bool ok_ = false;
+  bool own_stream_ = false;
+  hipStream_t stream_ = nullptr;
+  DevPool pool_;
+  // per-code states (device) and their pinned host mirror
+  DevState *states_ = nullptr;
+  DevState *hstates_ = nullptr;
+  int nstates_ = 0;
+  std::vector<int> free_slots_;
+  // launch resources
+  PoolBuf desc_buf_, slots_;
+  std::vector<RoundDesc> descs_;
+  std::vector<hipEvent_t> events_;
+};
+
+// The executor of the current device for the synchronous entry points.
+int default_executor(Executor **ex, std::unique_lock<std::mutex> *lock);
+
+// Runs a set of prepared jobs to completion on one executor.
+int run_jobs(Executor &ex, std::vector<Job *> &jobs, hipStream_t s);
+
+}  // namespace qd

@@ -124,12 +124,27 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 
 // One tile = one table segment [k0, k0 + seg) x 64 tops.  The tops of a
 // tile come from every group whose table prefix reaches the segment, so
-// lanes stay full; a lane stops at its own group's prefix length.
+// lanes stay full; a lane stops at its own group's prefix length.  A launch
+// holds pieces of the current rounds of several codes (RoundDesc).
 template <int D>
-__global__ __launch_bounds__(256) void qd_round_kernel(RoundParams p) {
+__global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
+  extern __shared__ unsigned long long smem[];
+  // Consecutive workgroups land on different XCDs; give each XCD a
+  // contiguous range of tiles so its L2 sees a contiguous table range.
+  const uint32_t per = gridDim.x / 8;
+  const uint32_t wg = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const unsigned long long wtile = static_cast<unsigned long long>(wg) * kWavesPerGroup;
+  if (wtile >= lp.tiles) return;  // whole workgroup: launch padding
+  int lo = 0, hi = lp.ndesc;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (lp.desc[mid].tile_begin <= wtile) lo = mid;
+    else hi = mid;
+  }
+  const RoundDesc &p = lp.desc[lo];
+
   // Unranking reads suffix columns, the group table and the elements with
   // data-dependent addresses: stage them in LDS once per workgroup.
-  extern __shared__ unsigned long long smem[];
   const int C = p.t - p.u;  // suffix columns 0..t-u-1
   const unsigned long long *F = p.suffix;
   const DevGroup *GR = p.groups;
@@ -152,12 +167,9 @@ __global__ __launch_bounds__(256) void qd_round_kernel(RoundParams p) {
   }
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  // Consecutive workgroups land on different XCDs; give each XCD a
-  // contiguous range of tiles so its L2 sees a contiguous table range.
-  const uint32_t per = gridDim.x / 8;
-  const uint32_t wg = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  const unsigned long long g = p.tile_lo + static_cast<unsigned long long>(wg) * kWavesPerGroup + wave;
-  if (g >= p.tile_hi) return;
+  const unsigned long long local = wtile + wave - p.tile_begin;  // tile within the piece
+  if (local >= p.ntiles) return;                                  // piece padding
+  const unsigned long long g = p.tile_lo + local;                 // tile within the round
   DevState *st = p.state;
   // The key is read with plain loads: a stale (larger) U only delays the
   // early exit or triggers a redundant witness search; the atomicMin below
@@ -165,22 +177,23 @@ __global__ __launch_bounds__(256) void qd_round_kernel(RoundParams p) {
   unsigned long long key = uniform64(*reinterpret_cast<volatile unsigned long long *>(&st->key));
   if (static_cast<int>(key >> 32) <= p.L_before) return;  // bound already met
 
-  int lo = 0, hi = p.nruns;
+  lo = 0;
+  hi = p.nruns;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (p.runs[mid].tile0 <= g) lo = mid;
     else hi = mid;
   }
   const DevRun &run = p.runs[lo];
-  const unsigned long long local = g - run.tile0;
+  const unsigned long long rl = g - run.tile0;
   unsigned long long b, s;
-  if ((local >> 32) == 0 && (run.tps >> 32) == 0) {
-    const uint32_t l32 = static_cast<uint32_t>(local), t32 = static_cast<uint32_t>(run.tps);
+  if ((rl >> 32) == 0 && (run.tps >> 32) == 0) {
+    const uint32_t l32 = static_cast<uint32_t>(rl), t32 = static_cast<uint32_t>(run.tps);
     b = l32 % t32;
     s = run.s_begin + l32 / t32;
   } else {
-    b = local % run.tps;
-    s = run.s_begin + local / run.tps;
+    b = rl % run.tps;
+    s = run.s_begin + rl / run.tps;
   }
   const unsigned long long k0 = s * p.seg;
   const unsigned long long k1 = k0 + p.seg;
@@ -213,7 +226,7 @@ __global__ __launch_bounds__(256) void qd_round_kernel(RoundParams p) {
                     az);
     }
   }
-  // Entries [k0, kfull) are valid for every lane; [kfull, kend) for some.
+  // Entries [k0, k0 + sfull) are valid for every lane; up to k0 + send for some.
   const uint32_t span = static_cast<uint32_t>(lend - k0);
   const uint32_t sfull = __builtin_amdgcn_readfirstlane(wave_min(span));
   const uint32_t send = __builtin_amdgcn_readfirstlane(wave_max(active ? span : 0u));
@@ -229,7 +242,7 @@ __global__ __launch_bounds__(256) void qd_round_kernel(RoundParams p) {
   const uint32_t wmin = wave_min(best);
   const uint32_t visited = wave_sum(active ? span : 0u);
   if (lane == 0)
-    atomicAdd(p.counters + static_cast<size_t>(wg % kCounters) * kCounterStride,
+    atomicAdd(p.counters + static_cast<size_t>(wg % kCountersPerCode) * kCounterStride,
               static_cast<unsigned long long>(visited));
 
   key = uniform64(*reinterpret_cast<volatile unsigned long long *>(&st->key));
@@ -244,8 +257,8 @@ __global__ __launch_bounds__(256) void qd_round_kernel(RoundParams p) {
     const unsigned long long mask = __ballot(active && best == wmin);
     const int winner = __ffsll(static_cast<long long>(mask)) - 1;
     if (static_cast<int>(lane) == winner) {
-      const uint32_t slot = static_cast<uint32_t>(g - p.tile_lo);
-      uint32_t *out = p.slots + static_cast<size_t>(slot) * kElemWords;
+      const uint32_t slot = static_cast<uint32_t>(local);
+      uint32_t *out = lp.slots + (p.slot0 + slot) * kElemWords;
       const unsigned long long kk = k0 + kf;
       const uint32_t *e = p.table + (kk / kBlock) * (2 * D * kBlock) + (kk % kBlock);
 #pragma unroll
@@ -306,15 +319,16 @@ __global__ __launch_bounds__(256) void qd_saved_kernel(SavedParams p) {
   }
 }
 
-// After a launch: moves the codeword of the winning slot into the code's
-// state and folds the spread counters into its visited count.
-__global__ __launch_bounds__(256) void qd_commit_kernel(DevState *st, const uint32_t *slots,
-                                                        unsigned long long *counters) {
+// After a launch, one workgroup per piece: moves the codeword of the
+// winning slot into the code's state and folds the code's spread counters
+// into its visited count.
+__global__ __launch_bounds__(256) void qd_commit_kernel(LaunchParams lp) {
   __shared__ unsigned long long part[256];
+  const RoundDesc &p = lp.desc[blockIdx.x];
   unsigned long long sum = 0;
-  for (int i = threadIdx.x; i < kCounters; i += blockDim.x) {
-    sum += counters[static_cast<size_t>(i) * kCounterStride];
-    counters[static_cast<size_t>(i) * kCounterStride] = 0;
+  for (int i = threadIdx.x; i < kCountersPerCode; i += blockDim.x) {
+    sum += p.counters[static_cast<size_t>(i) * kCounterStride];
+    p.counters[static_cast<size_t>(i) * kCounterStride] = 0;
   }
   part[threadIdx.x] = sum;
   __syncthreads();
@@ -323,12 +337,13 @@ __global__ __launch_bounds__(256) void qd_commit_kernel(DevState *st, const uint
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
+  DevState *st = p.state;
   st->count += part[0];
   const unsigned long long key = st->key;
   const uint32_t slot = static_cast<uint32_t>(key & 0xFFFFFFFFull);
   if (slot == kNoSlot) return;
 #pragma unroll
-  for (int w = 0; w < kElemWords; ++w) st->wit[w] = slots[static_cast<size_t>(slot) * kElemWords + w];
+  for (int w = 0; w < kElemWords; ++w) st->wit[w] = lp.slots[(p.slot0 + slot) * kElemWords + w];
   st->key = (key & ~0xFFFFFFFFull) | kNoSlot;
 }
 
@@ -354,17 +369,15 @@ __global__ __launch_bounds__(256) void qd_valu_kernel(uint32_t seed, uint32_t it
 
 // -- launch helpers (host) ---------------------------------------------------
 
-hipError_t launch_round(int D, const RoundParams &p, hipStream_t s) {
-  const unsigned long long tiles = p.tile_hi - p.tile_lo;
-  unsigned long long wgs = (tiles + kWavesPerGroup - 1) / kWavesPerGroup;
+hipError_t launch_round(int D, const LaunchParams &lp, hipStream_t s) {
+  unsigned long long wgs = lp.tiles / kWavesPerGroup;
   wgs = (wgs + 7) / 8 * 8;
   dim3 grid(static_cast<uint32_t>(wgs)), block(kWave * kWavesPerGroup);
-  const unsigned int lds = round_lds_bytes(p.P, p.t, p.u, p.ngroups, p.stage);
   switch (D) {
-    case 1: hipLaunchKernelGGL(qd_round_kernel<1>, grid, block, lds, s, p); break;
-    case 2: hipLaunchKernelGGL(qd_round_kernel<2>, grid, block, lds, s, p); break;
-    case 3: hipLaunchKernelGGL(qd_round_kernel<3>, grid, block, lds, s, p); break;
-    case 4: hipLaunchKernelGGL(qd_round_kernel<4>, grid, block, lds, s, p); break;
+    case 1: hipLaunchKernelGGL(qd_round_kernel<1>, grid, block, lp.lds, s, lp); break;
+    case 2: hipLaunchKernelGGL(qd_round_kernel<2>, grid, block, lp.lds, s, lp); break;
+    case 3: hipLaunchKernelGGL(qd_round_kernel<3>, grid, block, lp.lds, s, lp); break;
+    case 4: hipLaunchKernelGGL(qd_round_kernel<4>, grid, block, lp.lds, s, lp); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -382,8 +395,8 @@ hipError_t launch_saved(int D, const SavedParams &p, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_commit(DevState *st, const uint32_t *slots, unsigned long long *counters, hipStream_t s) {
-  hipLaunchKernelGGL(qd_commit_kernel, dim3(1), dim3(256), 0, s, st, slots, counters);
+hipError_t launch_commit(const LaunchParams &lp, hipStream_t s) {
+  hipLaunchKernelGGL(qd_commit_kernel, dim3(lp.ndesc), dim3(256), 0, s, lp);
   return hipGetLastError();
 }
 

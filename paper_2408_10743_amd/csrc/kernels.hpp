@@ -15,9 +15,8 @@ constexpr int kWavesPerGroup = 4;
 constexpr int kBlock = 8;
 // Low 32 bits of the state key when no slot is pending.
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
-// Visited-combination counters, spread over separate 128-byte lines so the
-// waves of a launch do not all update one address.
-constexpr int kCounters = 1024;
+// Visited-combination counters are spread over separate 128-byte lines so
+// the waves of a launch do not all update one address.
 constexpr int kCounterStride = 16;  // unsigned long longs per line
 
 // One group of a round: top combinations whose smallest package is h,
@@ -51,7 +50,13 @@ struct DevState {
   uint32_t wit[kElemWords];
 };
 
-struct RoundParams {
+// Visited counters per code (separate 128-byte lines).
+constexpr int kCountersPerCode = 256;
+
+// One piece of one (code, t, Gamma_j) round inside a launch.  A launch
+// covers several pieces (several codes); pieces start at multiples of
+// kWavesPerGroup tiles so a workgroup never spans two of them.
+struct RoundDesc {
   const uint32_t *elems;               // package i element e: (3i+e)*kElemWords
   const uint32_t *table;               // saved sums, blocks of kBlock entries
   const uint32_t *tops;                // top codewords, kElemWords each (NULL: unrank)
@@ -60,14 +65,25 @@ struct RoundParams {
   const unsigned long long *suffix;    // (P+1) x R: e_r(c_h..c_{P-1})
   const unsigned char *csize;          // elements per package (1 or 3)
   DevState *state;
-  unsigned long long *counters;        // kCounters x kCounterStride
-  uint32_t *slots;                     // one witness slot per tile of a launch
-  unsigned long long tile_lo, tile_hi; // tiles of this launch
+  unsigned long long *counters;        // kCountersPerCode x kCounterStride
+  unsigned long long tile_begin;       // first launch tile of the piece
+  unsigned long long ntiles;           // tiles of the piece
+  unsigned long long tile_lo;          // round tile of the piece's first tile
+  unsigned long long slot0;            // first witness slot of the piece
   int ngroups, nruns, P, R, t, u;
   unsigned int seg;                    // table entries per tile (multiple of kBlock)
   int L_before;                        // lower bound already certified
   int stage;                           // 1: copy the groups to LDS; 2: also suffix
                                        //    columns and elements (unranking path)
+  int pad;
+};
+
+struct LaunchParams {
+  const RoundDesc *desc;               // sorted by tile_begin
+  int ndesc;
+  unsigned int lds;                    // dynamic LDS bytes of the launch
+  unsigned long long tiles;            // multiple of kWavesPerGroup
+  uint32_t *slots;                     // one witness slot per launch tile
 };
 
 // LDS bytes a round kernel launch needs when it stages its tables.

@@ -71,6 +71,12 @@ class qd_stats(ctypes.Structure):
         return d
 
 
+class qd_result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_ulonglong), ("status", ctypes.c_int), ("d", ctypes.c_int), ("L", ctypes.c_int),
+                ("n", ctypes.c_int), ("latency_ms", ctypes.c_double), ("queue_ms", ctypes.c_double),
+                ("combinations", ctypes.c_ulonglong)]
+
+
 class qd_plan_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("rank", ctypes.c_int), ("diag", ctypes.c_int), ("h", ctypes.c_int),
                 ("h_used", ctypes.c_int), ("P", ctypes.c_int * QD_MAX_GAMMA),
@@ -95,6 +101,13 @@ _lib.qd_plan.argtypes = [_u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.
 _lib.qd_round_min.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _u8p,
                               ctypes.POINTER(ctypes.c_ulonglong)]
 _lib.qd_device_check.argtypes = [ctypes.c_char_p, ctypes.c_int]
+_lib.qd_engine_create.restype = ctypes.c_void_p
+_lib.qd_engine_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+_lib.qd_engine_submit.argtypes = [ctypes.c_void_p, _u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_ulonglong, ctypes.POINTER(qd_options)]
+_lib.qd_engine_poll.argtypes = [ctypes.c_void_p, ctypes.POINTER(qd_result), _u8p, ctypes.c_int, ctypes.c_int]
+_lib.qd_engine_outstanding.argtypes = [ctypes.c_void_p]
+_lib.qd_engine_destroy.argtypes = [ctypes.c_void_p]
 _lib.qd_valu_peak.argtypes = [ctypes.POINTER(ctypes.c_double)]
 
 
@@ -218,7 +231,38 @@ def qd_valu_peak():
     return st, v.value
 
 
+def qd_engine_create(mem_budget=0, max_active=0, stream=None):
+    """Returns an engine handle (int) or None."""
+    h = _lib.qd_engine_create(mem_budget, max_active, ctypes.c_void_p(int(stream)) if stream else None)
+    return h
+
+
+def qd_engine_submit(engine, G, field=QD_FIELD_F2, tag=0, **opts):
+    G, m, n = _matrix(G, field)
+    o, _keep = _options(opts)
+    return _lib.qd_engine_submit(engine, G.ctypes.data_as(_u8p), m, n, field, tag, ctypes.byref(o))
+
+
+def qd_engine_poll(engine, max_results=64, wait_ms=0):
+    """Returns a list of (qd_result, witness array of 2n bytes)."""
+    res = (qd_result * max_results)()
+    wit = np.zeros((max_results, 2 * QD_MAX_N), dtype=np.uint8)
+    k = _lib.qd_engine_poll(engine, res, wit.ctypes.data_as(_u8p), max_results, wait_ms)
+    if k < 0:
+        raise QdError(k)
+    return [(res[i], wit[i, : 2 * res[i].n].copy()) for i in range(k)]
+
+
+def qd_engine_outstanding(engine):
+    return _lib.qd_engine_outstanding(engine)
+
+
+def qd_engine_destroy(engine):
+    _lib.qd_engine_destroy(engine)
+
+
 def exported_symbols():
     """Names of the C ABI entry points declared in include/qdist.h."""
     return ["qd_distance", "qd_distance_ex", "qd_distance_batch", "qd_distance_batch_ex", "qd_plan",
-            "qd_round_min", "qd_strerror", "qd_device_check", "qd_valu_peak"]
+            "qd_round_min", "qd_strerror", "qd_device_check", "qd_valu_peak", "qd_engine_create",
+            "qd_engine_submit", "qd_engine_poll", "qd_engine_outstanding", "qd_engine_destroy"]
