@@ -22,8 +22,26 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X integer VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-ops/s.
-PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# MI355X vector ALU: 256 CUs x 128 32-bit lanes per clock x 2.4 GHz (the
+# issue capacity behind the chip's 157.3 TFLOP/s fp32 vector figure: 4 SIMDs
+# x 16 lanes x 2 VALU issues per cycle; single issue is half of it).
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
+
+
+# HBM bytes per launch of the round kernel on this workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE x2.0, WRITE_SIZE x1.0, factors from a
+# 1 GiB device copy in the same runs), valid only for the kernel source
+# with this fingerprint (sha256 prefixes of kernels.hip and kernels.hpp).
+TRAFFIC = {"fingerprint": "47c1ebd02fe3e638bab3c536b542baf8", "bytes_per_launch": 56213105}
+
+
+def kernel_fingerprint():
+    import hashlib
+    out = ""
+    for f in ("kernels.hip", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2408_10743_amd", "csrc", f), "rb") as fh:
+            out += hashlib.sha256(fh.read()).hexdigest()[:16]
+    return out
 
 
 def ops_per_codeword(D):
@@ -40,6 +58,13 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched, plain, serving and latency legs")
+    ap.add_argument("--batch-codes", type=int, default=512)
+    ap.add_argument("--batch-max-work", type=float, default=1e11)
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-rate", type=float, default=0.0, help="requests/s (0: 60%% of measured capacity)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run 3 device copies of 1 GiB (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -68,6 +93,121 @@ def cpu_baseline(G, field, budget_s):
                       f"{visited} codewords in {done:.2f} s wall on {cores} threads"}
 
 
+def predicted_work(Q, G, f):
+    p = Q.qd_plan(G, f)
+    cands = [x for x in (p["predicted_f2"], p["predicted_f4"]) if x >= 0]
+    return min(cands)
+
+
+def config4_codes(Q, W, count, max_work):
+    """Draws config-4 codes in order and keeps the first `count` whose
+    planner-predicted work is at most max_work (the stated distribution has
+    a tail far beyond any budget: 1e13..1e17 codewords)."""
+    kept, drawn = [], 0
+    pool = W.config4(count * 8)
+    for G, f in pool:
+        drawn += 1
+        if predicted_work(Q, G, f) <= max_work:
+            kept.append((G, f))
+            if len(kept) == count:
+                break
+    return kept, drawn
+
+
+def leg_batched(Q, W, a):
+    codes, drawn = config4_codes(Q, W, a.batch_codes, a.batch_max_work)
+    budget = int(a.batch_max_work * 4)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, ds, wits, sts, stats = Q.qd_distance_batch(codes, budget=budget)
+    t_batch = time.perf_counter() - t0
+    comb_b = sum(s.combinations for s in stats)
+    t0 = time.perf_counter()
+    comb_p, ds_p = 0, []
+    for G, f in codes:
+        st1, d1, _, s1 = Q.qd_distance_ex(G, f, budget=budget)
+        comb_p += s1.combinations
+        ds_p.append(d1)
+    t_plain = time.perf_counter() - t0
+    ns = [G.shape[1] // 2 if f == 2 else G.shape[1] for G, f in codes]
+    return {
+        "workload": f"config 4: first {len(codes)} of {drawn} drawn codes (n~U{{24..96}}, even additive m~U{{n-8..n+8}}, "
+                    f"odd F4-linear k=n/2) with planner-predicted work <= {a.batch_max_work:.0e}; budget {budget:.0e}",
+        "codes": len(codes), "drawn": drawn, "n_range": [min(ns), max(ns)],
+        "exact": sum(1 for x in sts if x == 0), "incomplete": sum(1 for x in sts if x == 1),
+        "same_d_as_per_code": ds == ds_p,
+        "batched_s": t_batch, "batched_codewords_per_s": comb_b / t_batch,
+        "per_code_s": t_plain, "per_code_codewords_per_s": comb_p / t_plain,
+        "speedup": t_plain / t_batch,
+    }
+
+
+def leg_plain(Q, G, field, engine_step_ms, engine_combos):
+    """The plain per-code GPU path on the same code: no saved sums, every
+    lane unranks and XORs its whole combination."""
+    st, d, wit, s = Q.qd_distance_ex(G, field, saved_depth=-1, tops_mode=2, timing=1)
+    assert st == 0
+    return {"ms_per_step": s.wall_ms, "codewords_per_s": s.combinations / (s.wall_ms * 1e-3),
+            "kernel_codewords_per_s": s.combinations / (s.kernel_ms * 1e-3), "d": d,
+            "engine_speedup": s.wall_ms / engine_step_ms}
+
+
+def leg_latency(Q, W):
+    out = {}
+    for name, fn in (("config1", W.config1), ("config2", W.config2)):
+        ts = []
+        for i in range(10):
+            G, f = fn(i)
+            Q.qd_distance(G, f)
+            t0 = time.perf_counter()
+            st, d, _ = Q.qd_distance(G, f)
+            ts.append((time.perf_counter() - t0) * 1e3)
+        ts.sort()
+        out[name] = {"median_ms": ts[len(ts) // 2], "max_ms": ts[-1], "codes": len(ts)}
+    return out
+
+
+def leg_serving(Q, W, a):
+    """Config 5: Poisson arrivals, n log-uniform in 16..96, alternately
+    additive (m = n) and F4-linear (k = n/2); requests whose predicted work
+    exceeds 1e10 are redrawn (stated in the output)."""
+    raw = W.config5(a.serve_requests * 4, 1.0)
+    reqs, drawn = [], 0
+    for _, G, f in raw:
+        drawn += 1
+        if predicted_work(Q, G, f) <= 1e10:
+            reqs.append((G, f))
+            if len(reqs) == a.serve_requests:
+                break
+    # service capacity: the same requests run back to back as one batch
+    t0 = time.perf_counter()
+    Q.qd_distance_batch(reqs)
+    t_all = time.perf_counter() - t0
+    rate = a.serve_rate or 0.6 * len(reqs) / t_all
+    gaps = [t for t, _, _ in W.config5(len(reqs), rate, index=1)]
+    e = Q.qd_engine_create()
+    lat, comb, statuses = [], 0, []
+    t_start = time.perf_counter()
+    for i, (G, f) in enumerate(reqs):
+        while time.perf_counter() - t_start < gaps[i]:
+            for r, w in Q.qd_engine_poll(e, 64, 0):
+                lat.append(r.latency_ms); comb += r.combinations; statuses.append(r.status)
+            time.sleep(0.0002)
+        Q.qd_engine_submit(e, G, f, i)
+    while len(lat) < len(reqs):
+        for r, w in Q.qd_engine_poll(e, 64, 100):
+            lat.append(r.latency_ms); comb += r.combinations; statuses.append(r.status)
+    t_total = time.perf_counter() - t_start
+    Q.qd_engine_destroy(e)
+    lat.sort()
+    return {"workload": f"config 5: {len(reqs)} requests of {drawn} drawn (predicted work <= 1e10), "
+                        f"Poisson rate {rate:.1f}/s (60% of back-to-back capacity)",
+            "rate_per_s": rate, "requests": len(reqs), "exact": sum(1 for x in statuses if x == 0),
+            "p50_ms": lat[len(lat) // 2], "p99_ms": lat[min(len(lat) - 1, int(0.99 * len(lat)))],
+            "codewords_per_s": comb / t_total, "window_s": t_total}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -86,7 +226,6 @@ def main():
         sys.exit(1)
     stream = torch.cuda.current_stream()
     G, field = W.config3(a.seed)
-    n = G.shape[1] // 2
 
     def step():
         st, d, wit, s = Q.qd_distance_ex(G, field, stream=stream.cuda_stream, timing=1)
@@ -108,8 +247,8 @@ def main():
     kernel_ms = sum(s.kernel_ms for _, s in stats)
     launches = sum(r["launches"] for _, s in stats for r in s.rounds())
     D = stats[0][1].D
-    alg_ops = combos * ops_per_codeword(D)
-    achieved = alg_ops / (kernel_ms * 1e-3)
+    achieved = combos * ops_per_codeword(D) / (kernel_ms * 1e-3)
+    achieved_survey = combos * (4 * D + 1) / (kernel_ms * 1e-3)
     s0 = stats[0][1]
     out = {
         "metric": "codewords/s (XOR+symplectic wt) & time-to-exact-d",
@@ -137,14 +276,27 @@ def main():
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "TOP/s",
             "frac": achieved / PEAK_LANE_OPS,
-            "traffic": None,
+            "traffic": TRAFFIC["bytes_per_launch"] if kernel_fingerprint() == TRAFFIC["fingerprint"] else None,
             "kernel": f"qd_round_kernel<{D}>",
             "ops_per_codeword": ops_per_codeword(D),
+            "frac_4D1_ops": achieved_survey / PEAK_LANE_OPS,
             "launches": launches,
             "avg_launch_ms": kernel_ms / max(launches, 1),
         },
         "device": name,
     }
+    if a.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 4
+    if not a.no_extra:
+        out["plain_per_code"] = leg_plain(Q, G, field, wall * 1e3 / a.steps, combos / a.steps)
+        out["batched"] = leg_batched(Q, W, a)
+        out["serving"] = leg_serving(Q, W, a)
+        out["latency"] = leg_latency(Q, W)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(G, field, a.cpu_seconds)
     print(json.dumps(out), flush=True)

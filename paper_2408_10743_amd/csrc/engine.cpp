@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace qd {
@@ -19,7 +21,7 @@ constexpr unsigned long long kMaxTableBytes = 1ull << 29;
 constexpr unsigned long long kMaxTopEntries = 1ull << 24;  // 512 MB of tops
 constexpr unsigned long long kTilesPerLaunch = 1ull << 21;
 constexpr unsigned long long kTargetTiles = 1ull << 18;    // ~32 tiles per wave slot
-constexpr unsigned kMinSeg = 256, kMaxSeg = 16384;
+constexpr unsigned kMinSeg = 256, kMaxSeg = 4096;
 constexpr unsigned kStageMaxBytes = 32768;
 constexpr size_t kBigClass = size_t(64) << 20;
 
@@ -66,10 +68,14 @@ int saved_depth(const GammaDev &g, int D, int t, int cap) {
 }
 
 // Table entries per tile: long enough to amortize a tile's setup, short
-// enough for about kTargetTiles tiles per round.
-unsigned choose_seg(unsigned long long planned) {
-  const unsigned long long want = planned / (kWave * kTargetTiles);
-  unsigned seg = kMinSeg;
+// enough that the round gives its share (1/sharing) of about kTargetTiles
+// tiles per step, where `sharing` codes run their rounds in the same steps.
+unsigned choose_seg(unsigned long long planned, int sharing) {
+  const unsigned long long target = std::max<unsigned long long>(kTargetTiles / std::max(sharing, 1), 1024);
+  const unsigned long long want = planned / (kWave * target);
+  // With many codes in a step the device is filled by their number, so
+  // tiles can stay long (the per-tile setup then costs under a few %).
+  unsigned seg = sharing > 8 ? 4 * kMinSeg : kMinSeg;
   while (seg < want && seg < kMaxSeg) seg <<= 1;
   return seg;
 }
@@ -350,7 +356,7 @@ int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops, hipStream_t 
   return launch_saved(job.D, sp, s) == hipSuccess ? QD_OK : QD_ERR_DEVICE;
 }
 
-int Executor::begin_round(Job &job, hipStream_t s) {
+int Executor::begin_round(Job &job, int sharing, hipStream_t s) {
   const int h = int(job.use.size());
   if (!job.single_round) {
     for (;;) {
@@ -378,7 +384,7 @@ int Executor::begin_round(Job &job, hipStream_t s) {
   }
   const int cap = job.opt.saved_depth < 0 ? 0 : job.opt.saved_depth ? job.opt.saved_depth : kDefaultSavedDepth;
   job.u = saved_depth(g, job.D, t, cap);
-  job.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : choose_seg(planned);
+  job.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : choose_seg(planned, sharing);
   const int tm = job.opt.tops_mode;
   job.use_tops = tm == 1 || (tm == 0 && g.suffix[t - job.u] <= kMaxTopEntries);
   int rc = ensure_table(job, g, job.u, false, s);
@@ -425,9 +431,15 @@ void Executor::end_round(Job &job) {
 }
 
 int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
+  // QD_TRACE=1 prints one line per step to stderr (launches, pieces,
+  // tiles, host and device time).
+  static const bool trace = std::getenv("QD_TRACE") && std::getenv("QD_TRACE")[0] == '1';
+  const double ts0 = trace ? now_ms() : 0.0;
+  int sharing = 0;
+  for (Job *jp : jobs) sharing += !jp->done && !jp->status;
   for (Job *jp : jobs) {
     if (jp->done || jp->in_round || jp->status) continue;
-    const int rc = begin_round(*jp, s);
+    const int rc = begin_round(*jp, sharing, s);
     if (rc) { jp->status = rc; jp->done = true; }
   }
   struct Launch {
@@ -515,9 +527,16 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
       if (launch_commit(lp, s) != hipSuccess) return QD_ERR_DEVICE;
     }
   }
+  const double ts1 = trace ? now_ms() : 0.0;
   if (hipMemcpyAsync(hstates_, states_, sizeof(DevState) * nstates_, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return QD_ERR_DEVICE;
+  if (trace) {
+    std::fprintf(stderr, "qd step: jobs %d host %.3f ms wait %.3f ms", sharing, ts1 - ts0, now_ms() - ts1);
+    for (const Launch &L : launches)
+      std::fprintf(stderr, " | D%d pieces %zu tiles %llu", L.D, L.d1 - L.d0, L.tiles);
+    std::fprintf(stderr, "\n");
+  }
   for (size_t i = 0; i < launches.size(); ++i) {
     const Launch &L = launches[i];
     if (!L.timed) continue;

@@ -113,7 +113,7 @@ class Executor {
   static size_t footprint(const Job &job);
 
  private:
-  int begin_round(Job &job, hipStream_t s);
+  int begin_round(Job &job, int sharing, hipStream_t s);
   void end_round(Job &job);
   int ensure_table(Job &job, GammaDev &g, int u, bool tops, hipStream_t s);
   bool alloc(PoolBuf &b, size_t bytes);
