@@ -23,6 +23,7 @@ constexpr unsigned long long kTilesPerLaunch = 1ull << 21;
 constexpr unsigned long long kTargetTiles = 1ull << 18;    // ~32 tiles per wave slot
 constexpr unsigned kMinSeg = 256, kMaxSeg = 4096;
 constexpr unsigned kStageMaxBytes = 32768;
+constexpr unsigned long long kSpecCombos = 1ull << 24;  // rounds grouped per step below this
 constexpr size_t kBigClass = size_t(64) << 20;
 
 double now_ms() {
@@ -356,78 +357,105 @@ int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops, hipStream_t 
   return launch_saved(job.D, sp, s) == hipSuccess ? QD_OK : QD_ERR_DEVICE;
 }
 
-int Executor::begin_round(Job &job, int sharing, hipStream_t s) {
+// Schedules the next rounds of a job with nothing in flight: consecutive
+// rounds are grouped into one step while their total work stays small
+// (about a microsecond of device time), so short codes need few steps.  A
+// round scheduled speculatively only adds codewords: the bounds are still
+// applied in round order when the step retires.
+int Executor::schedule(Job &job, int sharing, hipStream_t s) {
   const int h = int(job.use.size());
-  if (!job.single_round) {
-    for (;;) {
-      if (job.j >= h) { job.j = 0; ++job.t; }
-      if (job.t > job.use[job.j].P()) {
+  unsigned long long cum = 0;
+  // Speculation stops once the scheduled rounds would certify a bound that
+  // meets the current upper bound or the planner's distance estimate.
+  std::vector<int> tsim = job.tdone;
+  const int stop_at = std::min(job.U, std::max(job.pc.d_est, 1));
+  for (;;) {
+    if (!job.single_round) {
+      bool found = false;
+      for (;;) {
+        if (job.j >= h) { job.j = 0; ++job.t; }
         bool any = false;
         for (int j = 0; j < h; ++j) any = any || job.t <= job.use[j].P();
-        if (!any) { job.done = true; return QD_OK; }
-        ++job.j;
-        continue;
+        if (!any) break;
+        if (job.t > job.use[job.j].P()) { ++job.j; continue; }
+        found = true;
+        break;
       }
-      break;
+      if (!found) {
+        if (job.fl.empty()) job.done = true;  // every round ran: nothing left to certify
+        return QD_OK;
+      }
     }
+    GammaDev &g = job.gd[job.j];
+    const int t = job.t;
+    const uint64_t planned = g.prefix[size_t(g.P) * g.R + t];
+    if (t > kTMax || (job.opt.cancel && *job.opt.cancel) || planned >= kSat ||
+        (job.opt.budget && job.planned_total + cum + planned > job.opt.budget)) {
+      if (job.fl.empty()) job.incomplete = job.done = true;
+      return QD_OK;
+    }
+    Flight f;
+    f.t = t;
+    f.j = job.j;
+    f.L_before = job.single_round ? -1 : job.L;
+    const int cap = job.opt.saved_depth < 0 ? 0 : job.opt.saved_depth ? job.opt.saved_depth : kDefaultSavedDepth;
+    f.u = saved_depth(g, job.D, t, cap);
+    f.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : choose_seg(planned, sharing);
+    const int tm = job.opt.tops_mode;
+    f.use_tops = tm == 1 || (tm == 0 && g.suffix[t - f.u] <= kMaxTopEntries);
+    int rc = ensure_table(job, g, f.u, false, s);
+    if (!rc && f.use_tops) rc = ensure_table(job, g, t - f.u, true, s);
+    if (rc) return rc;
+    f.tiles = plan_round(g, t, f.u, f.seg, f.hg, f.hr);
+    f.planned = planned;
+    job.fl.push_back(std::move(f));
+    Flight &F = job.fl.back();
+    const size_t gb = F.hg.size() * sizeof(DevGroup), rb = F.hr.size() * sizeof(DevRun);
+    if (!alloc(F.groups, gb) || !alloc(F.runs, rb)) return QD_ERR_NOMEM;
+    if (hipMemcpyAsync(F.groups.p, F.hg.data(), gb, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(F.runs.p, F.hr.data(), rb, hipMemcpyHostToDevice, s) != hipSuccess)
+      return QD_ERR_DEVICE;
+    cum += planned;
+    ++job.j;
+    tsim[F.j] = t;
+    if (job.single_round || cum >= kSpecCombos || t == job.use[F.j].P() || lower_bound(tsim, job.delta) >= stop_at)
+      return QD_OK;
   }
-  GammaDev &g = job.gd[job.j];
-  const int t = job.t;
-  if (t > kTMax || (job.opt.cancel && *job.opt.cancel)) {
-    job.incomplete = job.done = true;
-    return QD_OK;
-  }
-  const uint64_t planned = g.prefix[size_t(g.P) * g.R + t];
-  if (planned >= kSat || (job.opt.budget && job.planned_total + planned > job.opt.budget)) {
-    job.incomplete = job.done = true;
-    return QD_OK;
-  }
-  const int cap = job.opt.saved_depth < 0 ? 0 : job.opt.saved_depth ? job.opt.saved_depth : kDefaultSavedDepth;
-  job.u = saved_depth(g, job.D, t, cap);
-  job.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : choose_seg(planned, sharing);
-  const int tm = job.opt.tops_mode;
-  job.use_tops = tm == 1 || (tm == 0 && g.suffix[t - job.u] <= kMaxTopEntries);
-  int rc = ensure_table(job, g, job.u, false, s);
-  if (!rc && job.use_tops) rc = ensure_table(job, g, t - job.u, true, s);
-  if (rc) return rc;
-  job.round_tiles = plan_round(g, t, job.u, job.seg, job.h_groups, job.h_runs);
-  const size_t gb = job.h_groups.size() * sizeof(DevGroup), rb = job.h_runs.size() * sizeof(DevRun);
-  if (!alloc(job.groups, gb) || !alloc(job.runs, rb)) return QD_ERR_NOMEM;
-  if (hipMemcpyAsync(job.groups.p, job.h_groups.data(), gb, hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(job.runs.p, job.h_runs.data(), rb, hipMemcpyHostToDevice, s) != hipSuccess)
-    return QD_ERR_DEVICE;
-  job.tiles_sent = 0;
-  job.round_planned = planned;
-  job.round_launches = 0;
-  job.round_ms = 0.f;
-  job.in_round = true;
-  return QD_OK;
 }
 
-void Executor::end_round(Job &job) {
+void Executor::drop_flights(Job &job) {
+  for (Flight &f : job.fl) {
+    release(f.groups);
+    release(f.runs);
+  }
+  job.fl.clear();
+}
+
+// Retires one finished round (in order): bounds, witness, log, stop test.
+void Executor::end_round(Job &job, Flight &f) {
   const DevState &hs = hstates_[job.state_slot];
   const int Ud = int(hs.key >> 32);
   if (Ud < job.U) {
     job.U = Ud;
     job.wit = from_words(hs.wit);
   }
-  const unsigned long long this_round = hs.count - job.visited;
-  job.visited = hs.count;
-  job.planned_total += job.round_planned;
-  job.tdone[job.j] = job.t;
+  // Visited combinations are counted per code; a step's count is given to
+  // its rounds in order, each at most its planned size.
+  const unsigned long long this_round = std::min<unsigned long long>(hs.count - job.visited, f.planned);
+  job.visited += this_round;
+  job.planned_total += f.planned;
+  job.tdone[f.j] = f.t;
   job.L = lower_bound(job.tdone, job.delta);
   qd_stats &S = job.S;
-  S.kernel_ms += job.round_ms;
+  S.kernel_ms += f.ms;
   if (S.nlog < QD_MAX_LOG) {
     qd_round_log &lg = S.log[S.nlog];
-    lg.t = job.t; lg.j = job.j; lg.L = job.L; lg.U = job.U; lg.saved_depth = job.u;
-    lg.launches = job.round_launches; lg.combinations = this_round; lg.planned = job.round_planned;
-    lg.kernel_ms = job.round_ms;
+    lg.t = f.t; lg.j = f.j; lg.L = job.L; lg.U = job.U; lg.saved_depth = f.u;
+    lg.launches = f.launches; lg.combinations = this_round; lg.planned = f.planned;
+    lg.kernel_ms = f.ms;
   }
   ++S.nlog;
-  job.in_round = false;
-  if (job.single_round || job.L >= job.U || job.t == job.use[job.j].P()) job.done = true;
-  ++job.j;
+  if (job.single_round || job.L >= job.U || f.t == job.use[f.j].P()) job.done = true;
 }
 
 int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
@@ -438,8 +466,8 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   int sharing = 0;
   for (Job *jp : jobs) sharing += !jp->done && !jp->status;
   for (Job *jp : jobs) {
-    if (jp->done || jp->in_round || jp->status) continue;
-    const int rc = begin_round(*jp, sharing, s);
+    if (jp->done || !jp->fl.empty() || jp->status) continue;
+    const int rc = schedule(*jp, sharing, s);
     if (rc) { jp->status = rc; jp->done = true; }
   }
   struct Launch {
@@ -449,51 +477,61 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
     unsigned lds;
     bool timed;
   };
+  struct Member {
+    Job *job;
+    size_t flight;
+  };
   std::vector<Launch> launches;
-  std::vector<Job *> members;  // job of each descriptor
+  std::vector<Member> members;  // job and flight of each descriptor
   descs_.clear();
   unsigned long long max_tiles = 0;
   for (int D = 1; D <= 4; ++D) {
     Launch L{D, descs_.size(), 0, 0, 0, false};
     for (Job *jp : jobs) {
       Job &job = *jp;
-      if (job.done || !job.in_round || job.D != D || job.status) continue;
-      const unsigned long long left = job.round_tiles - job.tiles_sent;
-      const unsigned long long take = std::min(left, kTilesPerLaunch - std::min(kTilesPerLaunch, L.tiles));
-      if (take == 0) continue;
-      GammaDev &g = job.gd[job.j];
-      RoundDesc d{};
-      d.elems = static_cast<const uint32_t *>(g.elems.p);
-      d.table = static_cast<const uint32_t *>(g.table[job.u].p);
-      d.tops = job.use_tops ? static_cast<const uint32_t *>(g.tops[job.t - job.u].p) : nullptr;
-      d.groups = static_cast<const DevGroup *>(job.groups.p);
-      d.runs = static_cast<const DevRun *>(job.runs.p);
-      d.suffix = static_cast<const unsigned long long *>(g.dsuffix.p);
-      d.csize = static_cast<const unsigned char *>(g.csize.p);
-      d.state = states_ + job.state_slot;
-      d.counters = static_cast<unsigned long long *>(job.counters.p);
-      d.tile_begin = L.tiles;
-      d.ntiles = take;
-      d.tile_lo = job.tiles_sent;
-      d.slot0 = L.tiles;
-      d.ngroups = int(job.h_groups.size());
-      d.nruns = int(job.h_runs.size());
-      d.P = g.P;
-      d.R = g.R;
-      d.t = job.t;
-      d.u = job.u;
-      d.seg = job.seg;
-      d.L_before = job.single_round ? -1 : job.L;
-      d.stage = job.use_tops ? 1 : 2;
-      unsigned lds = round_lds_bytes(d.P, d.t, d.u, d.ngroups, d.stage);
-      if (lds > kStageMaxBytes) { d.stage = 0; lds = 0; }
-      L.lds = std::max(L.lds, lds);
-      L.timed = L.timed || job.opt.timing;
-      L.tiles += (take + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
-      job.tiles_sent += take;
-      ++job.round_launches;
-      descs_.push_back(d);
-      members.push_back(jp);
+      if (job.done || job.D != D || job.status) continue;
+      bool first = true;  // the first piece of the code in this launch commits it
+      for (size_t fi = 0; fi < job.fl.size(); ++fi) {
+        Flight &f = job.fl[fi];
+        const unsigned long long left = f.tiles - f.sent;
+        const unsigned long long take = std::min(left, kTilesPerLaunch - std::min(kTilesPerLaunch, L.tiles));
+        if (take == 0) continue;
+        GammaDev &g = job.gd[f.j];
+        RoundDesc d{};
+        d.elems = static_cast<const uint32_t *>(g.elems.p);
+        d.table = static_cast<const uint32_t *>(g.table[f.u].p);
+        d.tops = f.use_tops ? static_cast<const uint32_t *>(g.tops[f.t - f.u].p) : nullptr;
+        d.groups = static_cast<const DevGroup *>(f.groups.p);
+        d.runs = static_cast<const DevRun *>(f.runs.p);
+        d.suffix = static_cast<const unsigned long long *>(g.dsuffix.p);
+        d.csize = static_cast<const unsigned char *>(g.csize.p);
+        d.state = states_ + job.state_slot;
+        d.counters = static_cast<unsigned long long *>(job.counters.p);
+        d.tile_begin = L.tiles;
+        d.ntiles = take;
+        d.tile_lo = f.sent;
+        d.slot0 = L.tiles;
+        d.ngroups = int(f.hg.size());
+        d.nruns = int(f.hr.size());
+        d.P = g.P;
+        d.R = g.R;
+        d.t = f.t;
+        d.u = f.u;
+        d.seg = f.seg;
+        d.L_before = f.L_before;
+        d.stage = f.use_tops ? 1 : 2;
+        d.commit = first ? 1 : 0;
+        first = false;
+        unsigned lds = round_lds_bytes(d.P, d.t, d.u, d.ngroups, d.stage);
+        if (lds > kStageMaxBytes) { d.stage = 0; lds = 0; }
+        L.lds = std::max(L.lds, lds);
+        L.timed = L.timed || job.opt.timing;
+        L.tiles += (take + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
+        f.sent += take;
+        ++f.launches;
+        descs_.push_back(d);
+        members.push_back({jp, fi});
+      }
     }
     L.d1 = descs_.size();
     if (L.d1 > L.d0) {
@@ -542,12 +580,24 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
     if (!L.timed) continue;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, events_[2 * i], events_[2 * i + 1]) != hipSuccess) return QD_ERR_DEVICE;
-    for (size_t d = L.d0; d < L.d1; ++d) members[d]->round_ms += ms;
+    // A launch's time is shared by its pieces in proportion to their tiles.
+    for (size_t d = L.d0; d < L.d1; ++d)
+      members[d].job->fl[members[d].flight].ms += ms * float(descs_[d].ntiles) / float(L.tiles);
   }
   for (Job *jp : jobs) {
     Job &job = *jp;
-    if (job.done || !job.in_round || job.status) continue;
-    if (job.tiles_sent == job.round_tiles) end_round(job);
+    if (job.done || job.status) continue;
+    size_t k = 0;
+    while (k < job.fl.size() && job.fl[k].sent == job.fl[k].tiles && !job.done) {
+      end_round(job, job.fl[k]);
+      ++k;
+    }
+    for (size_t i = 0; i < k; ++i) {
+      release(job.fl[i].groups);
+      release(job.fl[i].runs);
+    }
+    job.fl.erase(job.fl.begin(), job.fl.begin() + long(k));
+    if (job.done) drop_flights(job);
   }
   return QD_OK;
 }
@@ -575,8 +625,7 @@ void Executor::retire(Job &job) {
     for (int u = 0; u <= kTMax; ++u) { release(g.table[u]); release(g.tops[u]); }
   }
   release(job.counters);
-  release(job.groups);
-  release(job.runs);
+  drop_flights(job);
   if (job.state_slot >= 0) free_slots_.push_back(job.state_slot);
   job.state_slot = -1;
   job.t_done = t1;

@@ -52,6 +52,20 @@ struct GammaDev {
   PoolBuf table[kTMax + 1], tops[kTMax + 1];
 };
 
+// One scheduled (t, Gamma_j) round of a code and its tile plan.
+struct Flight {
+  int t = 0, j = 0, u = 0;
+  unsigned seg = 0;
+  bool use_tops = true;
+  int L_before = 0;  // bound certified before the step that scheduled it
+  PoolBuf groups, runs;
+  std::vector<DevGroup> hg;
+  std::vector<DevRun> hr;
+  unsigned long long tiles = 0, sent = 0, planned = 0;
+  int launches = 0;
+  float ms = 0.f;
+};
+
 // One code: request, plan, device data and progress through its rounds.
 struct Job {
   // request
@@ -69,22 +83,15 @@ struct Job {
   PlanChoice pc;
   std::vector<GammaDev> gd;
   int state_slot = -1;
-  PoolBuf counters, groups, runs;
-  std::vector<DevGroup> h_groups;
-  std::vector<DevRun> h_runs;
+  PoolBuf counters;
   // progress
   std::vector<int> tdone, delta;
   int L = 0, U = 0;
   BRow wit;
   unsigned long long visited = 0, planned_total = 0;
-  int t = 1, j = 0;
-  bool in_round = false, done = false, incomplete = false;
-  int u = 0;
-  unsigned seg = 0;
-  bool use_tops = true;
-  unsigned long long round_tiles = 0, tiles_sent = 0, round_planned = 0;
-  int round_launches = 0;
-  float round_ms = 0.f;
+  int t = 1, j = 0;          // next round to schedule
+  bool done = false, incomplete = false;
+  std::vector<Flight> fl;    // rounds in flight, in order
   qd_stats S{};
   double t0 = 0.0;
   double t_done = 0.0;
@@ -113,8 +120,9 @@ class Executor {
   static size_t footprint(const Job &job);
 
  private:
-  int begin_round(Job &job, int sharing, hipStream_t s);
-  void end_round(Job &job);
+  int schedule(Job &job, int sharing, hipStream_t s);
+  void end_round(Job &job, Flight &f);
+  void drop_flights(Job &job);
   int ensure_table(Job &job, GammaDev &g, int u, bool tops, hipStream_t s);
   bool alloc(PoolBuf &b, size_t bytes);
   void release(PoolBuf &b);

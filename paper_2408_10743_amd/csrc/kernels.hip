@@ -21,6 +21,12 @@ __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
   return r;
 }
 
+__device__ __forceinline__ uint32_t min3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_min3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 __device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
   uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
   uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
@@ -78,8 +84,9 @@ __device__ __forceinline__ uint32_t block_min(const uint32_t (&ax)[D], const uin
     }
     w[e] = acc;
   }
+  // One three-input min per pair of codewords.
 #pragma unroll
-  for (int e = 0; e < kBlock; e += 2) best = min(best, min(w[e], w[e + 1]));
+  for (int e = 0; e < kBlock; e += 2) best = min3(best, w[e], w[e + 1]);
   return best;
 }
 
@@ -257,8 +264,8 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
     const unsigned long long mask = __ballot(active && best == wmin);
     const int winner = __ffsll(static_cast<long long>(mask)) - 1;
     if (static_cast<int>(lane) == winner) {
-      const uint32_t slot = static_cast<uint32_t>(local);
-      uint32_t *out = lp.slots + (p.slot0 + slot) * kElemWords;
+      const uint32_t slot = static_cast<uint32_t>(p.slot0 + local);  // launch-wide slot
+      uint32_t *out = lp.slots + static_cast<size_t>(slot) * kElemWords;
       const unsigned long long kk = k0 + kf;
       const uint32_t *e = p.table + (kk / kBlock) * (2 * D * kBlock) + (kk % kBlock);
 #pragma unroll
@@ -319,12 +326,13 @@ __global__ __launch_bounds__(256) void qd_saved_kernel(SavedParams p) {
   }
 }
 
-// After a launch, one workgroup per piece: moves the codeword of the
-// winning slot into the code's state and folds the code's spread counters
-// into its visited count.
+// After a launch, one workgroup per code (its first piece): moves the
+// codeword of the winning slot into the code's state and folds the code's
+// spread counters into its visited count.
 __global__ __launch_bounds__(256) void qd_commit_kernel(LaunchParams lp) {
   __shared__ unsigned long long part[256];
   const RoundDesc &p = lp.desc[blockIdx.x];
+  if (!p.commit) return;  // another piece of the same code commits it
   unsigned long long sum = 0;
   for (int i = threadIdx.x; i < kCountersPerCode; i += blockDim.x) {
     sum += p.counters[static_cast<size_t>(i) * kCounterStride];
@@ -343,7 +351,7 @@ __global__ __launch_bounds__(256) void qd_commit_kernel(LaunchParams lp) {
   const uint32_t slot = static_cast<uint32_t>(key & 0xFFFFFFFFull);
   if (slot == kNoSlot) return;
 #pragma unroll
-  for (int w = 0; w < kElemWords; ++w) st->wit[w] = lp.slots[(p.slot0 + slot) * kElemWords + w];
+  for (int w = 0; w < kElemWords; ++w) st->wit[w] = lp.slots[static_cast<size_t>(slot) * kElemWords + w];
   st->key = (key & ~0xFFFFFFFFull) | kNoSlot;
 }
 

@@ -75,7 +75,7 @@ struct RoundDesc {
   int L_before;                        // lower bound already certified
   int stage;                           // 1: copy the groups to LDS; 2: also suffix
                                        //    columns and elements (unranking path)
-  int pad;
+  int commit;                          // 1 for the first piece of its code in the launch
 };
 
 struct LaunchParams {
