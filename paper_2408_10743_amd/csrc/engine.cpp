@@ -11,7 +11,7 @@
 namespace qd {
 
 hipError_t launch_round(int D, const LaunchParams &lp, hipStream_t s);
-hipError_t launch_saved(int D, const SavedParams &p, hipStream_t s);
+hipError_t launch_build(int D, const BuildParams &bp, hipStream_t s);
 hipError_t launch_commit(const LaunchParams &lp, hipStream_t s);
 
 namespace {
@@ -336,11 +336,15 @@ int Executor::admit(Job &job, hipStream_t s) {
   return QD_OK;
 }
 
+// Queues the build of a table (saved bottoms of u packages, or with
+// tops = true the u-package tops) for the next flush; the buffer is
+// allocated now.
 int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops, hipStream_t s) {
+  (void)s;
   PoolBuf &buf = tops ? g.tops[u] : g.table[u];
   if (buf.p) return QD_OK;
   const unsigned long long nent = tops ? g.suffix[u] : g.prefix[size_t(g.P) * g.R + u];
-  const unsigned long long padded = (nent + kBlock - 1) / kBlock * kBlock;
+  const unsigned long long padded = (nent + kBuildGroup - 1) / kBuildGroup * kBuildGroup;
   if (!alloc(buf, size_t(padded) * (tops ? kElemWords : 2 * job.D) * 4)) return QD_ERR_NOMEM;
   SavedParams sp;
   sp.elems = static_cast<const uint32_t *>(g.elems.p);
@@ -350,11 +354,53 @@ int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops, hipStream_t 
   sp.table = static_cast<uint32_t *>(buf.p);
   sp.nent = nent;
   sp.nent_padded = padded;
+  sp.first = 0;
   sp.P = g.P;
   sp.R = g.R;
   sp.u = u;
   sp.tops = tops ? 1 : 0;
-  return launch_saved(job.D, sp, s) == hipSuccess ? QD_OK : QD_ERR_DEVICE;
+  builds_[job.D].push_back(sp);
+  return QD_OK;
+}
+
+// Launches the queued table builds: one launch per word count D.
+int Executor::flush_builds(hipStream_t s) {
+  size_t total = 0;
+  for (int D = 1; D <= 4; ++D) total += builds_[D].size();
+  if (!total) return QD_OK;
+  build_host_.clear();
+  std::vector<std::pair<size_t, size_t>> ranges;
+  for (int D = 1; D <= 4; ++D) {
+    const size_t b0 = build_host_.size();
+    unsigned long long first = 0;
+    for (SavedParams &sp : builds_[D]) {
+      sp.first = first;
+      first += sp.nent_padded;
+      build_host_.push_back(sp);
+    }
+    ranges.push_back({b0, build_host_.size()});
+  }
+  if (!alloc(build_buf_, build_host_.size() * sizeof(SavedParams))) return QD_ERR_NOMEM;
+  if (hipMemcpyAsync(build_buf_.p, build_host_.data(), build_host_.size() * sizeof(SavedParams),
+                     hipMemcpyHostToDevice, s) != hipSuccess)
+    return QD_ERR_DEVICE;
+  for (int D = 1; D <= 4; ++D) {
+    const auto r = ranges[D - 1];
+    if (r.first == r.second) continue;
+    BuildParams bp;
+    bp.req = static_cast<const SavedParams *>(build_buf_.p) + r.first;
+    bp.nreq = int(r.second - r.first);
+    bp.threads = 0;
+    unsigned need = 0;
+    for (size_t i = r.first; i < r.second; ++i) {
+      bp.threads += build_host_[i].nent_padded;
+      need = std::max(need, build_lds_bytes(build_host_[i].P, build_host_[i].u));
+    }
+    bp.lds = need <= kStageMaxBytes ? need : 0u;
+    if (launch_build(D, bp, s) != hipSuccess) return QD_ERR_DEVICE;
+  }
+  for (int D = 1; D <= 4; ++D) builds_[D].clear();
+  return QD_OK;
 }
 
 // Schedules the next rounds of a job with nothing in flight: consecutive
@@ -539,6 +585,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
       max_tiles = std::max(max_tiles, L.tiles);
     }
   }
+  if (const int rc = flush_builds(s)) return rc;
   if (!launches.empty()) {
     if (!alloc(desc_buf_, descs_.size() * sizeof(RoundDesc)) ||
         !alloc(slots_, size_t(max_tiles) * kElemWords * 4))

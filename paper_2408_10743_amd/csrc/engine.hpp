@@ -124,6 +124,7 @@ class Executor {
   void end_round(Job &job, Flight &f);
   void drop_flights(Job &job);
   int ensure_table(Job &job, GammaDev &g, int u, bool tops, hipStream_t s);
+  int flush_builds(hipStream_t s);
   bool alloc(PoolBuf &b, size_t bytes);
   void release(PoolBuf &b);
   int grow_states(int need);
@@ -138,7 +139,9 @@ class Executor {
   int nstates_ = 0;
   std::vector<int> free_slots_;
   // launch resources
-  PoolBuf desc_buf_, slots_;
+  PoolBuf desc_buf_, slots_, build_buf_;
+  std::vector<SavedParams> builds_[5];  // queued table builds per word count
+  std::vector<SavedParams> build_host_;
   std::vector<RoundDesc> descs_;
   std::vector<hipEvent_t> events_;
 };

@@ -283,30 +283,57 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
 // combinations inside packages [0, h) are entries [0, e_u(c_0..c_{h-1})).
 // The tops table is the same construction over the packages in reverse
 // order: combinations whose smallest package is h are the entries
-// [e_u(c_{h+1}..), e_u(c_h..)).
+// [e_u(c_{h+1}..), e_u(c_h..)).  One launch builds several tables; the
+// counts E(h, r), r <= u, of a workgroup's table are staged in LDS.
 template <int D>
-__global__ __launch_bounds__(256) void qd_saved_kernel(SavedParams p) {
-  const unsigned long long k = static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
+  extern __shared__ unsigned long long ecnt[];
+  const unsigned long long wfirst = static_cast<unsigned long long>(blockIdx.x) * kBuildGroup;
+  if (wfirst >= bp.threads) return;
+  int lo = 0, hi = bp.nreq;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (bp.req[mid].first <= wfirst) lo = mid;
+    else hi = mid;
+  }
+  const SavedParams &p = bp.req[lo];
+  const int C = p.u + 1;
+  // E(h, r): combinations of r packages among the first h (in build order).
+  const bool staged = bp.lds >= build_lds_bytes(p.P, p.u);
+  if (staged) {
+    for (int i = threadIdx.x; i < (p.P + 1) * C; i += blockDim.x) {
+      const int h = i / C, r = i % C;
+      ecnt[i] = p.tops ? p.suffix[size_t(p.P - h) * p.R + r] : p.prefix[size_t(h) * p.R + r];
+    }
+    __syncthreads();
+  }
+  auto E = [&](int h, int r) {
+    if (staged) return ecnt[h * C + r];
+    return p.tops ? p.suffix[size_t(p.P - h) * p.R + r] : p.prefix[size_t(h) * p.R + r];
+  };
+  const unsigned long long k = wfirst + threadIdx.x - p.first;
   if (k >= p.nent_padded) return;
   uint32_t x[D], z[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) x[d] = z[d] = 0;
-  // E(h, r): combinations of r packages among the first h (in build order).
-  auto E = [&](int h, int r) {
-    return p.tops ? p.suffix[size_t(p.P - h) * p.R + r] : p.prefix[size_t(h) * p.R + r];
-  };
   if (k < p.nent) {
     unsigned long long rest = k;
-    int hi = p.P;
+    int hi2 = p.P;
     for (int r = p.u; r > 0; --r) {
-      int h = hi - 1;
-      while (h > 0 && E(h, r) > rest) --h;
+      // largest h < hi2 with E(h, r) <= rest (E is nondecreasing in h)
+      int a = r - 1, b = hi2 - 1;
+      while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (E(mid, r) <= rest) a = mid;
+        else b = mid - 1;
+      }
+      const int h = a;
       rest -= E(h, r);
       const unsigned long long f = E(h, r - 1);
       int c = 0;
       while (rest >= f && c < 2) { rest -= f; ++c; }
       xor_elem<D>(p.elems, p.tops ? p.P - 1 - h : h, c, x, z);
-      hi = h;
+      hi2 = h;
     }
   }
   if (p.tops) {
@@ -391,13 +418,13 @@ hipError_t launch_round(int D, const LaunchParams &lp, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_saved(int D, const SavedParams &p, hipStream_t s) {
-  dim3 grid(static_cast<uint32_t>((p.nent_padded + 255) / 256)), block(256);
-  switch (D) {  // one kernel builds both tables
-    case 1: hipLaunchKernelGGL(qd_saved_kernel<1>, grid, block, 0, s, p); break;
-    case 2: hipLaunchKernelGGL(qd_saved_kernel<2>, grid, block, 0, s, p); break;
-    case 3: hipLaunchKernelGGL(qd_saved_kernel<3>, grid, block, 0, s, p); break;
-    case 4: hipLaunchKernelGGL(qd_saved_kernel<4>, grid, block, 0, s, p); break;
+hipError_t launch_build(int D, const BuildParams &bp, hipStream_t s) {
+  dim3 grid(static_cast<uint32_t>(bp.threads / kBuildGroup)), block(kBuildGroup);
+  switch (D) {
+    case 1: hipLaunchKernelGGL(qd_build_kernel<1>, grid, block, bp.lds, s, bp); break;
+    case 2: hipLaunchKernelGGL(qd_build_kernel<2>, grid, block, bp.lds, s, bp); break;
+    case 3: hipLaunchKernelGGL(qd_build_kernel<3>, grid, block, bp.lds, s, bp); break;
+    case 4: hipLaunchKernelGGL(qd_build_kernel<4>, grid, block, bp.lds, s, bp); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -1,6 +1,8 @@
 // kernels.hpp -- device data layouts shared by the HIP kernels and their
 // host-side launch code.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace qd {
@@ -103,9 +105,24 @@ struct SavedParams {
   const unsigned long long *suffix;    // (P+1) x R: e_r(c_h..c_{P-1})
   const unsigned char *csize;
   uint32_t *table;
-  unsigned long long nent, nent_padded;
+  unsigned long long nent, nent_padded;  // nent_padded: multiple of kBuildGroup
+  unsigned long long first;            // first thread of this table in the launch
   int P, R, u;
   int tops;                            // 1: build the tops table
 };
+
+// Threads per workgroup of the table builder; a workgroup never spans two
+// tables of one launch.
+constexpr int kBuildGroup = 256;
+
+// One launch builds the pending tables of one word count D.
+struct BuildParams {
+  const SavedParams *req;              // sorted by first
+  int nreq;
+  unsigned int lds;                    // dynamic LDS bytes (0: read counts from memory)
+  unsigned long long threads;
+};
+
+__host__ __device__ inline unsigned int build_lds_bytes(int P, int u) { return static_cast<unsigned int>((P + 1) * (u + 1) * 8); }
 
 }  // namespace qd
