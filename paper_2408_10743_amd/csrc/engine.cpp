@@ -13,6 +13,7 @@ namespace qd {
 hipError_t launch_round(int D, const LaunchParams &lp, hipStream_t s);
 hipError_t launch_build(int D, const BuildParams &bp, hipStream_t s);
 hipError_t launch_commit(const LaunchParams &lp, hipStream_t s);
+hipError_t launch_scatter(const CopyRec *rec, int n, const unsigned char *base, hipStream_t s);
 
 namespace {
 
@@ -25,6 +26,12 @@ constexpr unsigned kMinSeg = 256, kMaxSeg = 4096;
 constexpr unsigned kStageMaxBytes = 32768;
 constexpr unsigned long long kSpecCombos = 1ull << 24;  // rounds grouped per step below this
 constexpr size_t kBigClass = size_t(64) << 20;
+constexpr size_t kSlabMax = size_t(16) << 20;   // largest class carved from slabs
+constexpr size_t kSlabBytes = size_t(64) << 20;
+
+static_assert(kEsymSat == kSat, "device e_r tables saturate like the host's");
+
+size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -134,35 +141,69 @@ DevPool::~DevPool() {
   for (void *p : all_) (void)hipFree(p);
 }
 
+// Classes up to kSlabMax are carved from slabs of kSlabBytes (or 8
+// blocks), so a batch of small codes costs few hipMalloc calls; larger
+// classes are allocations of their own.
 void *DevPool::get(size_t bytes, size_t *cls) {
   const size_t c = size_class(std::max<size_t>(bytes, 1));
   auto &v = free_[c];
-  if (!v.empty()) {
-    void *p = v.back();
-    v.pop_back();
-    *cls = c;
-    return p;
-  }
-  void *p = nullptr;
-  if (hipMalloc(&p, c) != hipSuccess) {
-    // Give cached blocks back to the driver and try once more.
-    for (auto &kv : free_)
-      for (void *q : kv.second) {
-        (void)hipFree(q);
-        all_.erase(std::find(all_.begin(), all_.end(), q));
-        held_ -= kv.first;
+  if (v.empty()) {
+    const size_t slab = c <= kSlabMax ? std::max(kSlabBytes, 8 * c) : c;
+    void *p = nullptr;
+    const double tm = now_ms();
+    ++mallocs_;
+    const hipError_t me = hipMalloc(&p, slab);
+    malloc_ms_ += now_ms() - tm;
+    if (me != hipSuccess) {
+      // Give cached blocks of the large classes back to the driver and try
+      // once more (slab blocks stay: their slab may be partly in use).
+      for (auto &kv : free_) {
+        if (kv.first <= kSlabMax) continue;
+        for (void *q : kv.second) {
+          (void)hipFree(q);
+          all_.erase(std::find(all_.begin(), all_.end(), q));
+          held_ -= kv.first;
+        }
+        kv.second.clear();
       }
-    free_.clear();
-    if (hipMalloc(&p, c) != hipSuccess) return nullptr;
+      if (hipMalloc(&p, slab) != hipSuccess) return nullptr;
+    }
+    all_.push_back(p);
+    held_ += slab;
+    for (size_t off = slab; off >= c; off -= c) v.push_back(static_cast<char *>(p) + (off - c));
   }
-  all_.push_back(p);
-  held_ += c;
+  void *p = v.back();
+  v.pop_back();
   *cls = c;
   return p;
 }
 
 void DevPool::put(void *p, size_t cls) {
   if (p) free_[cls].push_back(p);
+}
+
+// -- Staging -------------------------------------------------------------------
+
+Staging::~Staging() {
+  if (p_) (void)hipHostFree(p_);
+}
+
+size_t Staging::put(const void *src, size_t bytes) {
+  const size_t off = align16(n_), end = align16(off + bytes);
+  if (end > cap_) {
+    size_t cap = std::max<size_t>(cap_ ? 2 * cap_ : size_t(1) << 20, end);
+    unsigned char *q = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void **>(&q), cap, hipHostMallocDefault) != hipSuccess) return SIZE_MAX;
+    if (n_) std::memcpy(q, p_, n_);
+    if (p_) (void)hipHostFree(p_);
+    p_ = q;
+    cap_ = cap;
+  }
+  std::memset(p_ + n_, 0, off - n_);
+  if (bytes) std::memcpy(p_ + off, src, bytes);
+  std::memset(p_ + off + bytes, 0, end - off - bytes);
+  n_ = end;
+  return off;
 }
 
 // -- Executor ------------------------------------------------------------------
@@ -308,30 +349,55 @@ size_t Executor::footprint(const Job &job) {
   return b;
 }
 
+// Waits for the last flush's copy so the staging buffer can be reused.
+int Executor::settle() {
+  if (!inflight_) return QD_OK;
+  inflight_ = false;
+  staging_.clear();
+  return hipStreamSynchronize(inflight_stream_) == hipSuccess ? QD_OK : QD_ERR_DEVICE;
+}
+
+// Takes a state slot and one data block for the job and stages their
+// contents; they reach the device with the next step's flush.
 int Executor::admit(Job &job, hipStream_t s) {
+  (void)s;
   if (job.status) return job.status;
+  if (const int rc = settle()) return rc;
   if (free_slots_.empty() && grow_states(nstates_ + 64) != QD_OK) return QD_ERR_NOMEM;
   job.state_slot = free_slots_.back();
   free_slots_.pop_back();
   DevState &hs = hstates_[job.state_slot];
   std::memset(&hs, 0, sizeof(hs));
   hs.key = (static_cast<unsigned long long>(job.n + 1) << 32) | kNoSlot;
-  if (hipMemcpyAsync(states_ + job.state_slot, &hs, sizeof(DevState), hipMemcpyHostToDevice, s) != hipSuccess)
-    return QD_ERR_DEVICE;
+  dirty_slots_.push_back(job.state_slot);
+  // Block layout: counters | per Gamma_j elements and sizes, each 16-byte
+  // aligned as Staging::put places them | per Gamma_j prefix and suffix
+  // tables, which the device computes from the sizes.
   const size_t cb = size_t(kCountersPerCode) * kCounterStride * 8;
-  if (!alloc(job.counters, cb)) return QD_ERR_NOMEM;
-  if (hipMemsetAsync(job.counters.p, 0, cb, s) != hipSuccess) return QD_ERR_DEVICE;
-  for (GammaDev &g : job.gd) {
-    const size_t tb = g.prefix.size() * sizeof(uint64_t);
-    if (!alloc(g.elems, g.h_elems.size() * 4) || !alloc(g.csize, g.h_csize.size() + 1) || !alloc(g.dprefix, tb) ||
-        !alloc(g.dsuffix, tb))
-      return QD_ERR_NOMEM;
-    if (hipMemcpyAsync(g.elems.p, g.h_elems.data(), g.h_elems.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(g.csize.p, g.h_csize.data(), g.h_csize.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(g.dprefix.p, g.prefix.data(), tb, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(g.dsuffix.p, g.suffix.data(), tb, hipMemcpyHostToDevice, s) != hipSuccess)
-      return QD_ERR_DEVICE;
+  size_t a_bytes = 0, total = cb;
+  for (const GammaDev &g : job.gd) {
+    if (g.R > 64) return QD_ERR_INTERNAL;
+    a_bytes += align16(g.h_elems.size() * 4) + align16(g.h_csize.size());
+    total += align16(g.h_elems.size() * 4) + align16(g.h_csize.size()) + 2 * g.prefix.size() * 8;
   }
+  if (!alloc(job.data, total)) return QD_ERR_NOMEM;
+  unsigned char *dev = static_cast<unsigned char *>(job.data.p);
+  recs_.push_back({dev, kZeroFill, cb, 0, 0, 0});
+  const size_t o0 = align16(staging_.size());
+  unsigned char *a0 = dev + cb, *b = dev + cb + a_bytes;
+  for (GammaDev &g : job.gd) {
+    const size_t oe = staging_.put(g.h_elems.data(), g.h_elems.size() * 4);
+    const size_t oc = staging_.put(g.h_csize.data(), g.h_csize.size());
+    if (oe == SIZE_MAX || oc == SIZE_MAX) return QD_ERR_NOMEM;
+    g.elems = reinterpret_cast<const uint32_t *>(a0 + (oe - o0));
+    g.csize = a0 + (oc - o0);
+    g.dprefix = reinterpret_cast<const unsigned long long *>(b);
+    g.dsuffix = g.dprefix + g.prefix.size();
+    recs_.push_back({b, kEsymTables, 0, oc, g.P, g.R});
+    b += 2 * g.prefix.size() * 8;
+  }
+  if (staging_.size() - o0 != a_bytes || size_t(b - dev) != total) return QD_ERR_INTERNAL;
+  if (a_bytes) recs_.push_back({a0, o0, a_bytes, 0, 0, 0});
   job.S.host_ms = now_ms() - job.t0;
   return QD_OK;
 }
@@ -339,18 +405,17 @@ int Executor::admit(Job &job, hipStream_t s) {
 // Queues the build of a table (saved bottoms of u packages, or with
 // tops = true the u-package tops) for the next flush; the buffer is
 // allocated now.
-int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops, hipStream_t s) {
-  (void)s;
+int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops) {
   PoolBuf &buf = tops ? g.tops[u] : g.table[u];
   if (buf.p) return QD_OK;
   const unsigned long long nent = tops ? g.suffix[u] : g.prefix[size_t(g.P) * g.R + u];
   const unsigned long long padded = (nent + kBuildGroup - 1) / kBuildGroup * kBuildGroup;
   if (!alloc(buf, size_t(padded) * (tops ? kElemWords : 2 * job.D) * 4)) return QD_ERR_NOMEM;
   SavedParams sp;
-  sp.elems = static_cast<const uint32_t *>(g.elems.p);
-  sp.prefix = static_cast<const unsigned long long *>(g.dprefix.p);
-  sp.suffix = static_cast<const unsigned long long *>(g.dsuffix.p);
-  sp.csize = static_cast<const unsigned char *>(g.csize.p);
+  sp.elems = g.elems;
+  sp.prefix = g.dprefix;
+  sp.suffix = g.dsuffix;
+  sp.csize = g.csize;
   sp.table = static_cast<uint32_t *>(buf.p);
   sp.nent = nent;
   sp.nent_padded = padded;
@@ -363,43 +428,71 @@ int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops, hipStream_t 
   return QD_OK;
 }
 
-// Launches the queued table builds: one launch per word count D.
-int Executor::flush_builds(hipStream_t s) {
-  size_t total = 0;
-  for (int D = 1; D <= 4; ++D) total += builds_[D].size();
-  if (!total) return QD_OK;
-  build_host_.clear();
+// Sends everything staged since the last step to the device in one copy:
+// state resets and job data (applied by one scatter launch), each piece's
+// groups and runs, the round descriptors (read in place; *desc_off is
+// their offset) and the queued table builds, which it launches, one
+// launch per word count D.  *base is the device copy of the staged bytes.
+int Executor::flush(hipStream_t s, const unsigned char **base, size_t *desc_off) {
+  *base = nullptr;
+  for (int slot : dirty_slots_) {
+    const size_t off = staging_.put(&hstates_[slot], sizeof(DevState));
+    if (off == SIZE_MAX) return QD_ERR_NOMEM;
+    recs_.push_back({states_ + slot, off, sizeof(DevState), 0, 0, 0});
+  }
+  dirty_slots_.clear();
+  std::vector<SavedParams> bl;
   std::vector<std::pair<size_t, size_t>> ranges;
   for (int D = 1; D <= 4; ++D) {
-    const size_t b0 = build_host_.size();
+    const size_t b0 = bl.size();
     unsigned long long first = 0;
     for (SavedParams &sp : builds_[D]) {
       sp.first = first;
       first += sp.nent_padded;
-      build_host_.push_back(sp);
+      bl.push_back(sp);
     }
-    ranges.push_back({b0, build_host_.size()});
+    ranges.push_back({b0, bl.size()});
+    builds_[D].clear();
   }
-  if (!alloc(build_buf_, build_host_.size() * sizeof(SavedParams))) return QD_ERR_NOMEM;
-  if (hipMemcpyAsync(build_buf_.p, build_host_.data(), build_host_.size() * sizeof(SavedParams),
-                     hipMemcpyHostToDevice, s) != hipSuccess)
+  if (staging_.size() == 0 && descs_.empty() && bl.empty() && recs_.empty()) return QD_OK;
+  const size_t need = staging_.size() + align16(descs_.size() * sizeof(RoundDesc)) +
+                      align16(bl.size() * sizeof(SavedParams)) + align16(recs_.size() * sizeof(CopyRec));
+  if (!alloc(stage_dev_, need)) return QD_ERR_NOMEM;
+  const unsigned char *dev = static_cast<const unsigned char *>(stage_dev_.p);
+  for (size_t i = 0; i < descs_.size(); ++i) {
+    descs_[i].groups = reinterpret_cast<const DevGroup *>(dev + desc_groups_[2 * i]);
+    descs_[i].runs = reinterpret_cast<const DevRun *>(dev + desc_groups_[2 * i + 1]);
+  }
+  const size_t doff = staging_.put(descs_.data(), descs_.size() * sizeof(RoundDesc));
+  const size_t boff = staging_.put(bl.data(), bl.size() * sizeof(SavedParams));
+  const size_t roff = staging_.put(recs_.data(), recs_.size() * sizeof(CopyRec));
+  if (doff == SIZE_MAX || boff == SIZE_MAX || roff == SIZE_MAX) return QD_ERR_NOMEM;
+  if (staging_.size() != need) return QD_ERR_INTERNAL;
+  if (hipMemcpyAsync(stage_dev_.p, staging_.data(), need, hipMemcpyHostToDevice, s) != hipSuccess)
     return QD_ERR_DEVICE;
+  inflight_ = true;
+  inflight_stream_ = s;
+  if (!recs_.empty() &&
+      launch_scatter(reinterpret_cast<const CopyRec *>(dev + roff), int(recs_.size()), dev, s) != hipSuccess)
+    return QD_ERR_DEVICE;
+  recs_.clear();
   for (int D = 1; D <= 4; ++D) {
     const auto r = ranges[D - 1];
     if (r.first == r.second) continue;
     BuildParams bp;
-    bp.req = static_cast<const SavedParams *>(build_buf_.p) + r.first;
+    bp.req = reinterpret_cast<const SavedParams *>(dev + boff) + r.first;
     bp.nreq = int(r.second - r.first);
     bp.threads = 0;
-    unsigned need = 0;
+    unsigned lds = 0;
     for (size_t i = r.first; i < r.second; ++i) {
-      bp.threads += build_host_[i].nent_padded;
-      need = std::max(need, build_lds_bytes(build_host_[i].P, build_host_[i].u));
+      bp.threads += bl[i].nent_padded;
+      lds = std::max(lds, build_lds_bytes(bl[i].P, bl[i].u));
     }
-    bp.lds = need <= kStageMaxBytes ? need : 0u;
+    bp.lds = lds <= kStageMaxBytes ? lds : 0u;
     if (launch_build(D, bp, s) != hipSuccess) return QD_ERR_DEVICE;
   }
-  for (int D = 1; D <= 4; ++D) builds_[D].clear();
+  *base = dev;
+  *desc_off = doff;
   return QD_OK;
 }
 
@@ -408,7 +501,7 @@ int Executor::flush_builds(hipStream_t s) {
 // (about a microsecond of device time), so short codes need few steps.  A
 // round scheduled speculatively only adds codewords: the bounds are still
 // applied in round order when the step retires.
-int Executor::schedule(Job &job, int sharing, hipStream_t s) {
+int Executor::schedule(Job &job, int sharing) {
   const int h = int(job.use.size());
   unsigned long long cum = 0;
   // Speculation stops once the scheduled rounds would certify a bound that
@@ -449,33 +542,22 @@ int Executor::schedule(Job &job, int sharing, hipStream_t s) {
     f.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : choose_seg(planned, sharing);
     const int tm = job.opt.tops_mode;
     f.use_tops = tm == 1 || (tm == 0 && g.suffix[t - f.u] <= kMaxTopEntries);
-    int rc = ensure_table(job, g, f.u, false, s);
-    if (!rc && f.use_tops) rc = ensure_table(job, g, t - f.u, true, s);
+    int rc = ensure_table(job, g, f.u, false);
+    if (!rc && f.use_tops) rc = ensure_table(job, g, t - f.u, true);
     if (rc) return rc;
     f.tiles = plan_round(g, t, f.u, f.seg, f.hg, f.hr);
     f.planned = planned;
+    const int fj = f.j;
     job.fl.push_back(std::move(f));
-    Flight &F = job.fl.back();
-    const size_t gb = F.hg.size() * sizeof(DevGroup), rb = F.hr.size() * sizeof(DevRun);
-    if (!alloc(F.groups, gb) || !alloc(F.runs, rb)) return QD_ERR_NOMEM;
-    if (hipMemcpyAsync(F.groups.p, F.hg.data(), gb, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(F.runs.p, F.hr.data(), rb, hipMemcpyHostToDevice, s) != hipSuccess)
-      return QD_ERR_DEVICE;
     cum += planned;
     ++job.j;
-    tsim[F.j] = t;
-    if (job.single_round || cum >= kSpecCombos || t == job.use[F.j].P() || lower_bound(tsim, job.delta) >= stop_at)
+    tsim[fj] = t;
+    if (job.single_round || cum >= kSpecCombos || t == job.use[fj].P() || lower_bound(tsim, job.delta) >= stop_at)
       return QD_OK;
   }
 }
 
-void Executor::drop_flights(Job &job) {
-  for (Flight &f : job.fl) {
-    release(f.groups);
-    release(f.runs);
-  }
-  job.fl.clear();
-}
+void Executor::drop_flights(Job &job) { job.fl.clear(); }
 
 // Retires one finished round (in order): bounds, witness, log, stop test.
 void Executor::end_round(Job &job, Flight &f) {
@@ -509,13 +591,15 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   // tiles, host and device time).
   static const bool trace = std::getenv("QD_TRACE") && std::getenv("QD_TRACE")[0] == '1';
   const double ts0 = trace ? now_ms() : 0.0;
+  if (const int rc = settle()) return rc;
   int sharing = 0;
   for (Job *jp : jobs) sharing += !jp->done && !jp->status;
   for (Job *jp : jobs) {
     if (jp->done || !jp->fl.empty() || jp->status) continue;
-    const int rc = schedule(*jp, sharing, s);
+    const int rc = schedule(*jp, sharing);
     if (rc) { jp->status = rc; jp->done = true; }
   }
+  const double ts_sched = trace ? now_ms() : 0.0;
   struct Launch {
     int D;
     size_t d0, d1;
@@ -530,6 +614,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   std::vector<Launch> launches;
   std::vector<Member> members;  // job and flight of each descriptor
   descs_.clear();
+  desc_groups_.clear();
   unsigned long long max_tiles = 0;
   for (int D = 1; D <= 4; ++D) {
     Launch L{D, descs_.size(), 0, 0, 0, false};
@@ -544,15 +629,19 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         if (take == 0) continue;
         GammaDev &g = job.gd[f.j];
         RoundDesc d{};
-        d.elems = static_cast<const uint32_t *>(g.elems.p);
+        d.elems = g.elems;
         d.table = static_cast<const uint32_t *>(g.table[f.u].p);
         d.tops = f.use_tops ? static_cast<const uint32_t *>(g.tops[f.t - f.u].p) : nullptr;
-        d.groups = static_cast<const DevGroup *>(f.groups.p);
-        d.runs = static_cast<const DevRun *>(f.runs.p);
-        d.suffix = static_cast<const unsigned long long *>(g.dsuffix.p);
-        d.csize = static_cast<const unsigned char *>(g.csize.p);
+        // groups and runs travel with this step's upload (set by flush)
+        const size_t go = staging_.put(f.hg.data(), f.hg.size() * sizeof(DevGroup));
+        const size_t ro = staging_.put(f.hr.data(), f.hr.size() * sizeof(DevRun));
+        if (go == SIZE_MAX || ro == SIZE_MAX) return QD_ERR_NOMEM;
+        desc_groups_.push_back(go);
+        desc_groups_.push_back(ro);
+        d.suffix = g.dsuffix;
+        d.csize = g.csize;
         d.state = states_ + job.state_slot;
-        d.counters = static_cast<unsigned long long *>(job.counters.p);
+        d.counters = static_cast<unsigned long long *>(job.data.p);
         d.tile_begin = L.tiles;
         d.ntiles = take;
         d.tile_lo = f.sent;
@@ -585,14 +674,13 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
       max_tiles = std::max(max_tiles, L.tiles);
     }
   }
-  if (const int rc = flush_builds(s)) return rc;
+  const unsigned char *base = nullptr;
+  size_t desc_off = 0;
+  const double ts_desc = trace ? now_ms() : 0.0;
+  if (const int rc = flush(s, &base, &desc_off)) return rc;
+  const double ts_flush = trace ? now_ms() : 0.0;
   if (!launches.empty()) {
-    if (!alloc(desc_buf_, descs_.size() * sizeof(RoundDesc)) ||
-        !alloc(slots_, size_t(max_tiles) * kElemWords * 4))
-      return QD_ERR_NOMEM;
-    if (hipMemcpyAsync(desc_buf_.p, descs_.data(), descs_.size() * sizeof(RoundDesc), hipMemcpyHostToDevice, s) !=
-        hipSuccess)
-      return QD_ERR_DEVICE;
+    if (!alloc(slots_, size_t(max_tiles) * kElemWords * 4)) return QD_ERR_NOMEM;
     while (events_.size() < 2 * launches.size()) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return QD_ERR_DEVICE;
@@ -601,7 +689,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
     for (size_t i = 0; i < launches.size(); ++i) {
       const Launch &L = launches[i];
       LaunchParams lp;
-      lp.desc = static_cast<const RoundDesc *>(desc_buf_.p) + L.d0;
+      lp.desc = reinterpret_cast<const RoundDesc *>(base + desc_off) + L.d0;
       lp.ndesc = int(L.d1 - L.d0);
       lp.lds = L.lds;
       lp.tiles = L.tiles;
@@ -616,8 +704,14 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   if (hipMemcpyAsync(hstates_, states_, sizeof(DevState) * nstates_, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return QD_ERR_DEVICE;
+  inflight_ = false;
+  staging_.clear();
   if (trace) {
-    std::fprintf(stderr, "qd step: jobs %d host %.3f ms wait %.3f ms", sharing, ts1 - ts0, now_ms() - ts1);
+    std::fprintf(stderr,
+                 "qd step: jobs %d host %.3f ms (schedule %.3f pieces %.3f flush %.3f launch %.3f; hipMalloc %d in "
+                 "%.3f ms so far) wait %.3f ms",
+                 sharing, ts1 - ts0, ts_sched - ts0, ts_desc - ts_sched, ts_flush - ts_desc, ts1 - ts_flush,
+                 pool_.mallocs(), pool_.malloc_ms(), now_ms() - ts1);
     for (const Launch &L : launches)
       std::fprintf(stderr, " | D%d pieces %zu tiles %llu", L.D, L.d1 - L.d0, L.tiles);
     std::fprintf(stderr, "\n");
@@ -639,10 +733,6 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
       end_round(job, job.fl[k]);
       ++k;
     }
-    for (size_t i = 0; i < k; ++i) {
-      release(job.fl[i].groups);
-      release(job.fl[i].runs);
-    }
     job.fl.erase(job.fl.begin(), job.fl.begin() + long(k));
     if (job.done) drop_flights(job);
   }
@@ -651,6 +741,15 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
 
 void Executor::retire(Job &job) {
   const double t1 = now_ms();
+  // Uploads staged for a job that never reached a step still target its
+  // memory: apply them before that memory can be handed to another job.
+  if (!recs_.empty() || !dirty_slots_.empty()) {
+    const unsigned char *base = nullptr;
+    size_t off = 0;
+    descs_.clear();
+    desc_groups_.clear();
+    if (settle() || flush(stream_, &base, &off) || settle()) job.status = job.status ? job.status : QD_ERR_DEVICE;
+  }
   if (!job.status) {
     qd_stats &S = job.S;
     S.L = job.L;
@@ -668,10 +767,10 @@ void Executor::retire(Job &job) {
     S.wall_ms = t1 - job.t0;
   }
   for (GammaDev &g : job.gd) {
-    release(g.elems); release(g.csize); release(g.dprefix); release(g.dsuffix);
+    g.elems = nullptr; g.csize = nullptr; g.dprefix = g.dsuffix = nullptr;
     for (int u = 0; u <= kTMax; ++u) { release(g.table[u]); release(g.tops[u]); }
   }
-  release(job.counters);
+  release(job.data);
   drop_flights(job);
   if (job.state_slot >= 0) free_slots_.push_back(job.state_slot);
   job.state_slot = -1;
@@ -679,11 +778,14 @@ void Executor::retire(Job &job) {
 }
 
 int run_jobs(Executor &ex, std::vector<Job *> &jobs, hipStream_t s) {
+  static const bool trace = std::getenv("QD_TRACE") && std::getenv("QD_TRACE")[0] == '1';
+  const double t0 = trace ? now_ms() : 0.0;
   for (Job *jp : jobs) {
     if (jp->status) { jp->done = true; continue; }
     const int rc = ex.admit(*jp, s);
     if (rc) { jp->status = rc; jp->done = true; }
   }
+  const double t1 = trace ? now_ms() : 0.0;
   for (;;) {
     bool any = false;
     for (Job *jp : jobs) any = any || !jp->done;
@@ -695,7 +797,11 @@ int run_jobs(Executor &ex, std::vector<Job *> &jobs, hipStream_t s) {
       break;
     }
   }
+  const double t2 = trace ? now_ms() : 0.0;
   for (Job *jp : jobs) ex.retire(*jp);
+  if (trace)
+    std::fprintf(stderr, "qd run: jobs %zu admit %.3f ms steps %.3f ms retire %.3f ms\n", jobs.size(), t1 - t0,
+                 t2 - t1, now_ms() - t2);
   return QD_OK;
 }
 

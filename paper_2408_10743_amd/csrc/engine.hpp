@@ -28,8 +28,12 @@ class DevPool {
   void *get(size_t bytes, size_t *cls);
   void put(void *p, size_t cls);
   size_t held() const { return held_; }
+  int mallocs() const { return mallocs_; }
+  double malloc_ms() const { return malloc_ms_; }
 
  private:
+  int mallocs_ = 0;
+  double malloc_ms_ = 0.0;
   std::map<size_t, std::vector<void *>> free_;
   std::vector<void *> all_;
   size_t held_ = 0;
@@ -41,15 +45,34 @@ struct PoolBuf {
   size_t bytes = 0;
 };
 
-// Device copy of one generator matrix and its saved / tops tables.
+// Device copy of one generator matrix and its saved / tops tables.  The
+// elements, sizes and e_r tables live in the job's data block.
 struct GammaDev {
   int P = 0, R = 0;
   std::vector<int> sizes;
   std::vector<uint64_t> prefix, suffix;  // e_r tables (host copies)
   std::vector<uint32_t> h_elems;
   std::vector<unsigned char> h_csize;
-  PoolBuf elems, csize, dprefix, dsuffix;
+  const uint32_t *elems = nullptr;
+  const unsigned char *csize = nullptr;
+  const unsigned long long *dprefix = nullptr, *dsuffix = nullptr;
   PoolBuf table[kTMax + 1], tops[kTMax + 1];
+};
+
+// Pinned host bytes gathered between device steps and sent in one copy.
+class Staging {
+ public:
+  ~Staging();
+  // Appends bytes at a 16-byte aligned offset, which it returns; SIZE_MAX
+  // if pinned memory runs out.
+  size_t put(const void *src, size_t bytes);
+  size_t size() const { return n_; }
+  const unsigned char *data() const { return p_; }
+  void clear() { n_ = 0; }
+
+ private:
+  unsigned char *p_ = nullptr;
+  size_t n_ = 0, cap_ = 0;
 };
 
 // One scheduled (t, Gamma_j) round of a code and its tile plan.
@@ -58,7 +81,6 @@ struct Flight {
   unsigned seg = 0;
   bool use_tops = true;
   int L_before = 0;  // bound certified before the step that scheduled it
-  PoolBuf groups, runs;
   std::vector<DevGroup> hg;
   std::vector<DevRun> hr;
   unsigned long long tiles = 0, sent = 0, planned = 0;
@@ -83,7 +105,7 @@ struct Job {
   PlanChoice pc;
   std::vector<GammaDev> gd;
   int state_slot = -1;
-  PoolBuf counters;
+  PoolBuf data;  // visited counters, then every Gamma_j's elements and tables
   // progress
   std::vector<int> tdone, delta;
   int L = 0, U = 0;
@@ -120,11 +142,12 @@ class Executor {
   static size_t footprint(const Job &job);
 
  private:
-  int schedule(Job &job, int sharing, hipStream_t s);
+  int schedule(Job &job, int sharing);
   void end_round(Job &job, Flight &f);
   void drop_flights(Job &job);
-  int ensure_table(Job &job, GammaDev &g, int u, bool tops, hipStream_t s);
-  int flush_builds(hipStream_t s);
+  int ensure_table(Job &job, GammaDev &g, int u, bool tops);
+  int flush(hipStream_t s, const unsigned char **base, size_t *desc_off);
+  int settle();
   bool alloc(PoolBuf &b, size_t bytes);
   void release(PoolBuf &b);
   int grow_states(int need);
@@ -138,11 +161,21 @@ class Executor {
   DevState *hstates_ = nullptr;
   int nstates_ = 0;
   std::vector<int> free_slots_;
+  std::vector<int> dirty_slots_;  // states to upload at the next flush
+  // Uploads: staged host bytes, block moves of persistent data, and the
+  // device buffer the staged bytes go to (transient launch data is read
+  // from there directly).  After a flush the staged bytes stay in use
+  // until the stream is synchronized (inflight_).
+  Staging staging_;
+  std::vector<CopyRec> recs_;
+  PoolBuf stage_dev_;
+  bool inflight_ = false;
+  hipStream_t inflight_stream_ = nullptr;
   // launch resources
-  PoolBuf desc_buf_, slots_, build_buf_;
+  PoolBuf slots_;
   std::vector<SavedParams> builds_[5];  // queued table builds per word count
-  std::vector<SavedParams> build_host_;
   std::vector<RoundDesc> descs_;
+  std::vector<size_t> desc_groups_;  // staged offsets of each piece's groups and runs
   std::vector<hipEvent_t> events_;
 };
 

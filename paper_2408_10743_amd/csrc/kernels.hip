@@ -382,6 +382,50 @@ __global__ __launch_bounds__(256) void qd_commit_kernel(LaunchParams lp) {
   st->key = (key & ~0xFFFFFFFFull) | kNoSlot;
 }
 
+__device__ inline unsigned long long esym_step(unsigned long long a, unsigned long long b, unsigned c) {
+  // a + c*b, saturating at kEsymSat (c <= 3)
+  const unsigned long long cb = b > kEsymSat / 3 ? kEsymSat : min(b * c, kEsymSat);
+  return a + cb > kEsymSat ? kEsymSat : a + cb;
+}
+
+// Applies a step's block moves: workgroup i handles record i, copying from
+// the staging buffer or zero-filling in 16-byte vector stores, or building
+// e_r tables (thread r owns column r; one step per package).
+__global__ __launch_bounds__(256) void qd_scatter_kernel(const CopyRec *rec, const unsigned char *base) {
+  const CopyRec r = rec[blockIdx.x];
+  if (r.src == kEsymTables) {
+    __shared__ unsigned long long col[64];
+    unsigned long long *prefix = static_cast<unsigned long long *>(r.dst);
+    unsigned long long *suffix = prefix + static_cast<size_t>(r.P + 1) * r.R;
+    const int c = threadIdx.x;
+    const bool own = c < r.R;
+    for (int pass = 0; pass < 2; ++pass) {
+      unsigned long long v = c == 0 ? 1ull : 0ull;
+      unsigned long long *out = pass == 0 ? prefix : suffix;
+      const int h0 = pass == 0 ? 0 : r.P;
+      if (own) out[static_cast<size_t>(h0) * r.R + c] = v;
+      for (int i = 0; i < r.P; ++i) {
+        if (c < 64) col[c] = v;
+        __syncthreads();
+        const int h = pass == 0 ? i : r.P - 1 - i;       // package added
+        const int row = pass == 0 ? i + 1 : r.P - 1 - i;  // row written
+        if (own && c > 0) v = esym_step(v, col[c - 1], base[r.sizes + h]);
+        if (own) out[static_cast<size_t>(row) * r.R + c] = v;
+        __syncthreads();
+      }
+    }
+    return;
+  }
+  uint4 *dst = static_cast<uint4 *>(r.dst);
+  const unsigned long long n = r.bytes / 16;
+  if (r.src == kZeroFill) {
+    for (unsigned long long i = threadIdx.x; i < n; i += blockDim.x) dst[i] = make_uint4(0u, 0u, 0u, 0u);
+  } else {
+    const uint4 *src = reinterpret_cast<const uint4 *>(base + r.src);
+    for (unsigned long long i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  }
+}
+
 // Integer VALU rate probe: 8 independent XOR / OR / popcount chains per lane.
 __global__ __launch_bounds__(256) void qd_valu_kernel(uint32_t seed, uint32_t iters, uint32_t *out) {
   uint32_t a[8], c = seed * 2654435761u + threadIdx.x;
@@ -432,6 +476,11 @@ hipError_t launch_build(int D, const BuildParams &bp, hipStream_t s) {
 
 hipError_t launch_commit(const LaunchParams &lp, hipStream_t s) {
   hipLaunchKernelGGL(qd_commit_kernel, dim3(lp.ndesc), dim3(256), 0, s, lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const CopyRec *rec, int n, const unsigned char *base, hipStream_t s) {
+  hipLaunchKernelGGL(qd_scatter_kernel, dim3(static_cast<uint32_t>(n)), dim3(256), 0, s, rec, base);
   return hipGetLastError();
 }
 

@@ -123,6 +123,24 @@ struct BuildParams {
   unsigned long long threads;
 };
 
+// One block move of a step's upload: `bytes` (a multiple of 16) from the
+// step's device staging buffer at byte offset `src`, or zeros when src is
+// kZeroFill, to `dst`.  With src == kEsymTables it instead writes the
+// prefix and suffix tables e_r(c_0..c_{h-1}) and e_r(c_h..c_{P-1}),
+// (P+1) x R each, saturating at kEsymSat, of the P package sizes found in
+// the staging buffer at byte offset `sizes`.  The records of one launch
+// never overlap and read only the staging buffer.
+struct CopyRec {
+  void *dst;
+  unsigned long long src;
+  unsigned long long bytes;
+  unsigned long long sizes;
+  int P, R;
+};
+constexpr unsigned long long kZeroFill = ~0ull;
+constexpr unsigned long long kEsymTables = ~0ull - 1;
+constexpr unsigned long long kEsymSat = 1ull << 62;
+
 __host__ __device__ inline unsigned int build_lds_bytes(int P, int u) { return static_cast<unsigned int>((P + 1) * (u + 1) * 8); }
 
 }  // namespace qd
