@@ -31,14 +31,15 @@ PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # HBM bytes per launch of the round kernel on this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE x2.0, WRITE_SIZE x1.0, factors from a
 # 1 GiB device copy in the same runs), valid only for the kernel source
-# with this fingerprint (sha256 prefixes of kernels.hip and kernels.hpp).
-TRAFFIC = {"fingerprint": "47c1ebd02fe3e638bab3c536b542baf8", "bytes_per_launch": 56213105}
+# with this fingerprint (sha256 prefixes of round.hip and kernels.hpp, the
+# enumeration kernel and its data layouts).
+TRAFFIC = {"fingerprint": "ca192e1280e68766fcda00647f7b65da", "bytes_per_launch": 130898638}
 
 
 def kernel_fingerprint():
     import hashlib
     out = ""
-    for f in ("kernels.hip", "kernels.hpp"):
+    for f in ("round.hip", "kernels.hpp"):
         with open(os.path.join(ROOT, "paper_2408_10743_amd", "csrc", f), "rb") as fh:
             out += hashlib.sha256(fh.read()).hexdigest()[:16]
     return out
@@ -65,6 +66,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=0.0, help="requests/s (0: 60%% of measured capacity)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 3 device copies of 1 GiB (reference for HBM byte counters)")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only time the VALU instruction mixes of qd_valu_mix and print their rates")
     return ap.parse_args()
 
 
@@ -224,6 +227,15 @@ def main():
     if st != 0:
         print(f"device check failed: {Q.qd_strerror(st)} ({name})", file=sys.stderr)
         sys.exit(1)
+    if a.valu_probe:
+        rates = {}
+        for name_, mix in Q.QD_MIXES.items():
+            st, v = Q.qd_valu_mix(mix)
+            if st != 0:
+                raise RuntimeError(Q.qd_strerror(st))
+            rates[name_] = v
+        print(json.dumps({"valu_mix_lane_ops_per_s": rates, "peak_lane_ops_per_s": PEAK_LANE_OPS}))
+        return
     stream = torch.cuda.current_stream()
     G, field = W.config3(a.seed)
 
@@ -245,7 +257,7 @@ def main():
     assert all(x[0] == d for x in stats)
     combos = sum(s.combinations for _, s in stats)
     kernel_ms = sum(s.kernel_ms for _, s in stats)
-    launches = sum(r["launches"] for _, s in stats for r in s.rounds())
+    launches = sum(s.launches for _, s in stats)
     D = stats[0][1].D
     achieved = combos * ops_per_codeword(D) / (kernel_ms * 1e-3)
     achieved_survey = combos * (4 * D + 1) / (kernel_ms * 1e-3)

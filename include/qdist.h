@@ -105,6 +105,8 @@ typedef struct qd_stats {
   double host_ms;             /* input check, basis, diagonalization, planning */
   double kernel_ms;           /* summed enumeration-kernel time (timing = 1) */
   double wall_ms;             /* whole call */
+  int launches;               /* enumeration-kernel launches that carried its rounds
+                                 (one launch may carry several consecutive rounds) */
   int nlog;                   /* rounds run (entries in log, capped at QD_MAX_LOG) */
   qd_round_log log[QD_MAX_LOG];
 } qd_stats;
@@ -217,6 +219,26 @@ int qd_device_check(char *name, int len);
 /* Sustained integer-VALU rate on the current device, measured by a chain of
  * independent 32-bit XOR/OR/popcount operations: lane-ops per second. */
 int qd_valu_peak(double *lane_ops_per_s);
+
+/* Integer-VALU issue rate of one fixed instruction mix, for reading the
+ * round kernel's roofline: 8 independent chains per lane, 3 operations per
+ * chain step, 16 workgroups of 256 lanes per CU.  Profiling counters of the
+ * launch (SQ_ACTIVE_INST_VALU2 and the like) show which mixes dual-issue.
+ *   QD_MIX_HOTLOOP_SGPR  XOR (SGPR operand), XOR-OR v_bitop3 (SGPR operand),
+ *                        v_bcnt: the hot loop's per-word sequence
+ *   QD_MIX_HOTLOOP_VGPR  the same with every operand in VGPRs
+ *   QD_MIX_BCNT          v_bcnt only
+ *   QD_MIX_XOR_VGPR      XOR only, VGPR operands
+ *   QD_MIX_XOR_SGPR      XOR only, one SGPR operand
+ * Writes lane-ops per second; QD_ERR_INVALID for an unknown mix. */
+enum {
+  QD_MIX_HOTLOOP_SGPR = 0,
+  QD_MIX_HOTLOOP_VGPR = 1,
+  QD_MIX_BCNT = 2,
+  QD_MIX_XOR_VGPR = 3,
+  QD_MIX_XOR_SGPR = 4
+};
+int qd_valu_mix(int mix, double *lane_ops_per_s);
 
 #ifdef __cplusplus
 }

@@ -14,6 +14,7 @@
 
 namespace qd {
 hipError_t launch_valu(uint32_t blocks, uint32_t iters, uint32_t *out, hipStream_t s);
+hipError_t launch_mix(int mix, uint32_t blocks, uint32_t iters, uint32_t *out, hipStream_t s);
 }  // namespace qd
 
 using namespace qd;
@@ -70,6 +71,40 @@ int finish(Job &job, int *d, uint8_t *witness, qd_stats *st) {
   return job.status;
 }
 
+}  // namespace
+
+namespace {
+// Times `launch(blocks, iters)` after a short warm-up; lane-ops per second
+// for `ops_per_iter` lane-ops per thread per iteration.
+template <class F>
+int time_probe(F launch, double ops_per_iter, double *lane_ops_per_s) {
+  Executor *ex = nullptr;
+  std::unique_lock<std::mutex> lk;
+  int rc = default_executor(&ex, &lk);
+  if (rc) return rc;
+  hipStream_t s = ex->stream();
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return QD_ERR_DEVICE;
+  const uint32_t blocks = uint32_t(cus) * 16, iters = 4096;
+  uint32_t *out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = 0.f;
+  rc = QD_ERR_DEVICE;
+  if (hipMalloc(reinterpret_cast<void **>(&out), size_t(blocks) * 256 * 4) == hipSuccess &&
+      hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+      launch(blocks, 64u, out, s) == hipSuccess && hipEventRecord(e0, s) == hipSuccess &&
+      launch(blocks, iters, out, s) == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
+      hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+    *lane_ops_per_s = double(blocks) * 256.0 * double(iters) * ops_per_iter / (double(ms) * 1e-3);
+    rc = QD_OK;
+  }
+  if (out) (void)hipFree(out);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return rc;
+}
 }  // namespace
 
 extern "C" {
@@ -241,33 +276,13 @@ int qd_device_check(char *name, int len) {
 
 int qd_valu_peak(double *lane_ops_per_s) {
   if (!lane_ops_per_s) return QD_ERR_INVALID;
-  Executor *ex = nullptr;
-  std::unique_lock<std::mutex> lk;
-  int rc = default_executor(&ex, &lk);
-  if (rc) return rc;
-  hipStream_t s = ex->stream();
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return QD_ERR_DEVICE;
-  const uint32_t blocks = uint32_t(cus) * 8, iters = 20000;
-  uint32_t *out = nullptr;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  float ms = 0.f;
-  rc = QD_ERR_DEVICE;
-  if (hipMalloc(reinterpret_cast<void **>(&out), size_t(blocks) * 256 * 4) == hipSuccess &&
-      hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
-      launch_valu(blocks, 100, out, s) == hipSuccess && hipEventRecord(e0, s) == hipSuccess &&
-      launch_valu(blocks, iters, out, s) == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
-      hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
-    const double ops = double(blocks) * 256.0 * double(iters) * 32.0;  // 8 chains x 4 ops
-    *lane_ops_per_s = ops / (double(ms) * 1e-3);
-    rc = QD_OK;
-  }
-  if (out) (void)hipFree(out);
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
-  return rc;
+  return time_probe(launch_valu, 32.0, lane_ops_per_s);  // 8 chains x 4 ops
+}
+
+int qd_valu_mix(int mix, double *lane_ops_per_s) {
+  if (!lane_ops_per_s || mix < 0 || mix > QD_MIX_XOR_SGPR) return QD_ERR_INVALID;
+  return time_probe([mix](uint32_t b, uint32_t it, uint32_t *o, hipStream_t s) { return launch_mix(mix, b, it, o, s); },
+                    24.0, lane_ops_per_s);  // 8 chains x 3 ops
 }
 
 }  // extern "C"

@@ -376,7 +376,7 @@ int Executor::admit(Job &job, hipStream_t s) {
   const size_t cb = size_t(kCountersPerCode) * kCounterStride * 8;
   size_t a_bytes = 0, total = cb;
   for (const GammaDev &g : job.gd) {
-    if (g.R > 64) return QD_ERR_INTERNAL;
+    if (g.R > kWave || g.P > kMaxEsymPackages) return QD_ERR_INTERNAL;
     a_bytes += align16(g.h_elems.size() * 4) + align16(g.h_csize.size());
     total += align16(g.h_elems.size() * 4) + align16(g.h_csize.size()) + 2 * g.prefix.size() * 8;
   }
@@ -656,6 +656,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         d.L_before = f.L_before;
         d.stage = f.use_tops ? 1 : 2;
         d.commit = first ? 1 : 0;
+        if (first) ++job.S.launches;
         first = false;
         unsigned lds = round_lds_bytes(d.P, d.t, d.u, d.ngroups, d.stage);
         if (lds > kStageMaxBytes) { d.stage = 0; lds = 0; }

@@ -15,6 +15,7 @@
 #include "../../include/qdist.h"
 #include "host.hpp"
 #include "kernels.hpp"
+#include "support.hpp"
 
 namespace qd {
 

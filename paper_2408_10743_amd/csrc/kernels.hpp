@@ -1,5 +1,5 @@
-// kernels.hpp -- device data layouts shared by the HIP kernels and their
-// host-side launch code.
+// kernels.hpp -- device data layouts of the enumeration kernel (round.hip),
+// shared with its host-side launch code.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -96,51 +96,16 @@ inline unsigned int round_lds_bytes(int P, int t, int u, int ngroups, int stage)
   return b;
 }
 
-// Saved table (bottoms: combinations ordered by their largest package,
-// structure of arrays in blocks of kBlock) or tops table (combinations
-// ordered by their smallest package, largest first; kElemWords per entry).
-struct SavedParams {
-  const uint32_t *elems;
-  const unsigned long long *prefix;    // (P+1) x R: e_r(c_0..c_{h-1})
-  const unsigned long long *suffix;    // (P+1) x R: e_r(c_h..c_{P-1})
-  const unsigned char *csize;
-  uint32_t *table;
-  unsigned long long nent, nent_padded;  // nent_padded: multiple of kBuildGroup
-  unsigned long long first;            // first thread of this table in the launch
-  int P, R, u;
-  int tops;                            // 1: build the tops table
-};
-
-// Threads per workgroup of the table builder; a workgroup never spans two
-// tables of one launch.
-constexpr int kBuildGroup = 256;
-
-// One launch builds the pending tables of one word count D.
-struct BuildParams {
-  const SavedParams *req;              // sorted by first
-  int nreq;
-  unsigned int lds;                    // dynamic LDS bytes (0: read counts from memory)
-  unsigned long long threads;
-};
-
-// One block move of a step's upload: `bytes` (a multiple of 16) from the
-// step's device staging buffer at byte offset `src`, or zeros when src is
-// kZeroFill, to `dst`.  With src == kEsymTables it instead writes the
-// prefix and suffix tables e_r(c_0..c_{h-1}) and e_r(c_h..c_{P-1}),
-// (P+1) x R each, saturating at kEsymSat, of the P package sizes found in
-// the staging buffer at byte offset `sizes`.  The records of one launch
-// never overlap and read only the staging buffer.
-struct CopyRec {
-  void *dst;
-  unsigned long long src;
-  unsigned long long bytes;
-  unsigned long long sizes;
-  int P, R;
-};
-constexpr unsigned long long kZeroFill = ~0ull;
-constexpr unsigned long long kEsymTables = ~0ull - 1;
-constexpr unsigned long long kEsymSat = 1ull << 62;
-
-__host__ __device__ inline unsigned int build_lds_bytes(int P, int u) { return static_cast<unsigned int>((P + 1) * (u + 1) * 8); }
+// XOR of element e of package pkg into a codeword of D words per half.
+template <int D>
+__device__ __forceinline__ void xor_elem(const uint32_t *__restrict__ elems, int pkg, int e,
+                                         uint32_t (&ax)[D], uint32_t (&az)[D]) {
+  const uint32_t *p = elems + (size_t(3) * pkg + e) * kElemWords;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    ax[d] ^= p[d];
+    az[d] ^= p[4 + d];
+  }
+}
 
 }  // namespace qd

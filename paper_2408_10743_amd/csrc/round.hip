@@ -1,4 +1,4 @@
-// kernels.hip -- gfx950 kernels of libqdist.
+// round.hip -- the enumeration kernel of libqdist (gfx950).
 //
 // Enumeration scheme for one round (t packages of one generator matrix):
 // a combination is split into its u lowest packages ("bottom") and the
@@ -37,17 +37,6 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = min(v, static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), off)));
   return v;
-}
-
-template <int D>
-__device__ __forceinline__ void xor_elem(const uint32_t *__restrict__ elems, int pkg, int e,
-                                         uint32_t (&ax)[D], uint32_t (&az)[D]) {
-  const uint32_t *p = elems + (size_t(3) * pkg + e) * kElemWords;
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-    ax[d] ^= p[d];
-    az[d] ^= p[4 + d];
-  }
 }
 
 // Weight of (lane codeword) ^ (table entry k); k is wavefront-uniform.
@@ -278,175 +267,7 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   }
 }
 
-// Saved table: entry k is the k-th bottom combination of u packages in the
-// order (largest package, its element, then the rest recursively), so the
-// combinations inside packages [0, h) are entries [0, e_u(c_0..c_{h-1})).
-// The tops table is the same construction over the packages in reverse
-// order: combinations whose smallest package is h are the entries
-// [e_u(c_{h+1}..), e_u(c_h..)).  One launch builds several tables; the
-// counts E(h, r), r <= u, of a workgroup's table are staged in LDS.
-template <int D>
-__global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
-  extern __shared__ unsigned long long ecnt[];
-  const unsigned long long wfirst = static_cast<unsigned long long>(blockIdx.x) * kBuildGroup;
-  if (wfirst >= bp.threads) return;
-  int lo = 0, hi = bp.nreq;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (bp.req[mid].first <= wfirst) lo = mid;
-    else hi = mid;
-  }
-  const SavedParams &p = bp.req[lo];
-  const int C = p.u + 1;
-  // E(h, r): combinations of r packages among the first h (in build order).
-  const bool staged = bp.lds >= build_lds_bytes(p.P, p.u);
-  if (staged) {
-    for (int i = threadIdx.x; i < (p.P + 1) * C; i += blockDim.x) {
-      const int h = i / C, r = i % C;
-      ecnt[i] = p.tops ? p.suffix[size_t(p.P - h) * p.R + r] : p.prefix[size_t(h) * p.R + r];
-    }
-    __syncthreads();
-  }
-  auto E = [&](int h, int r) {
-    if (staged) return ecnt[h * C + r];
-    return p.tops ? p.suffix[size_t(p.P - h) * p.R + r] : p.prefix[size_t(h) * p.R + r];
-  };
-  const unsigned long long k = wfirst + threadIdx.x - p.first;
-  if (k >= p.nent_padded) return;
-  uint32_t x[D], z[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) x[d] = z[d] = 0;
-  if (k < p.nent) {
-    unsigned long long rest = k;
-    int hi2 = p.P;
-    for (int r = p.u; r > 0; --r) {
-      // largest h < hi2 with E(h, r) <= rest (E is nondecreasing in h)
-      int a = r - 1, b = hi2 - 1;
-      while (a < b) {
-        const int mid = (a + b + 1) >> 1;
-        if (E(mid, r) <= rest) a = mid;
-        else b = mid - 1;
-      }
-      const int h = a;
-      rest -= E(h, r);
-      const unsigned long long f = E(h, r - 1);
-      int c = 0;
-      while (rest >= f && c < 2) { rest -= f; ++c; }
-      xor_elem<D>(p.elems, p.tops ? p.P - 1 - h : h, c, x, z);
-      hi2 = h;
-    }
-  }
-  if (p.tops) {
-    uint32_t *e = p.table + k * kElemWords;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      e[d] = d < D ? x[d] : 0u;
-      e[4 + d] = d < D ? z[d] : 0u;
-    }
-  } else {
-    uint32_t *b = p.table + (k / kBlock) * (2 * D * kBlock) + (k % kBlock);
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      b[d * kBlock] = x[d];
-      b[(D + d) * kBlock] = z[d];
-    }
-  }
-}
-
-// After a launch, one workgroup per code (its first piece): moves the
-// codeword of the winning slot into the code's state and folds the code's
-// spread counters into its visited count.
-__global__ __launch_bounds__(256) void qd_commit_kernel(LaunchParams lp) {
-  __shared__ unsigned long long part[256];
-  const RoundDesc &p = lp.desc[blockIdx.x];
-  if (!p.commit) return;  // another piece of the same code commits it
-  unsigned long long sum = 0;
-  for (int i = threadIdx.x; i < kCountersPerCode; i += blockDim.x) {
-    sum += p.counters[static_cast<size_t>(i) * kCounterStride];
-    p.counters[static_cast<size_t>(i) * kCounterStride] = 0;
-  }
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (static_cast<int>(threadIdx.x) < w) part[threadIdx.x] += part[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  DevState *st = p.state;
-  st->count += part[0];
-  const unsigned long long key = st->key;
-  const uint32_t slot = static_cast<uint32_t>(key & 0xFFFFFFFFull);
-  if (slot == kNoSlot) return;
-#pragma unroll
-  for (int w = 0; w < kElemWords; ++w) st->wit[w] = lp.slots[static_cast<size_t>(slot) * kElemWords + w];
-  st->key = (key & ~0xFFFFFFFFull) | kNoSlot;
-}
-
-__device__ inline unsigned long long esym_step(unsigned long long a, unsigned long long b, unsigned c) {
-  // a + c*b, saturating at kEsymSat (c <= 3)
-  const unsigned long long cb = b > kEsymSat / 3 ? kEsymSat : min(b * c, kEsymSat);
-  return a + cb > kEsymSat ? kEsymSat : a + cb;
-}
-
-// Applies a step's block moves: workgroup i handles record i, copying from
-// the staging buffer or zero-filling in 16-byte vector stores, or building
-// e_r tables (thread r owns column r; one step per package).
-__global__ __launch_bounds__(256) void qd_scatter_kernel(const CopyRec *rec, const unsigned char *base) {
-  const CopyRec r = rec[blockIdx.x];
-  if (r.src == kEsymTables) {
-    __shared__ unsigned long long col[64];
-    unsigned long long *prefix = static_cast<unsigned long long *>(r.dst);
-    unsigned long long *suffix = prefix + static_cast<size_t>(r.P + 1) * r.R;
-    const int c = threadIdx.x;
-    const bool own = c < r.R;
-    for (int pass = 0; pass < 2; ++pass) {
-      unsigned long long v = c == 0 ? 1ull : 0ull;
-      unsigned long long *out = pass == 0 ? prefix : suffix;
-      const int h0 = pass == 0 ? 0 : r.P;
-      if (own) out[static_cast<size_t>(h0) * r.R + c] = v;
-      for (int i = 0; i < r.P; ++i) {
-        if (c < 64) col[c] = v;
-        __syncthreads();
-        const int h = pass == 0 ? i : r.P - 1 - i;       // package added
-        const int row = pass == 0 ? i + 1 : r.P - 1 - i;  // row written
-        if (own && c > 0) v = esym_step(v, col[c - 1], base[r.sizes + h]);
-        if (own) out[static_cast<size_t>(row) * r.R + c] = v;
-        __syncthreads();
-      }
-    }
-    return;
-  }
-  uint4 *dst = static_cast<uint4 *>(r.dst);
-  const unsigned long long n = r.bytes / 16;
-  if (r.src == kZeroFill) {
-    for (unsigned long long i = threadIdx.x; i < n; i += blockDim.x) dst[i] = make_uint4(0u, 0u, 0u, 0u);
-  } else {
-    const uint4 *src = reinterpret_cast<const uint4 *>(base + r.src);
-    for (unsigned long long i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
-  }
-}
-
-// Integer VALU rate probe: 8 independent XOR / OR / popcount chains per lane.
-__global__ __launch_bounds__(256) void qd_valu_kernel(uint32_t seed, uint32_t iters, uint32_t *out) {
-  uint32_t a[8], c = seed * 2654435761u + threadIdx.x;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) a[i] = c + i * 0x9E3779B9u;
-  for (uint32_t it = 0; it < iters; ++it) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      asm volatile("v_xor_b32 %0, %1, %0" : "+v"(a[i]) : "v"(c));
-      asm volatile("v_or_b32 %0, %1, %0" : "+v"(a[i]) : "v"(c));
-      asm volatile("v_bcnt_u32_b32 %0, %0, %0" : "+v"(a[i]));
-      asm volatile("v_xor_b32 %0, %1, %0" : "+v"(a[i]) : "v"(c));
-    }
-  }
-  uint32_t s = 0;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) s ^= a[i];
-  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
-}
-
-// -- launch helpers (host) ---------------------------------------------------
+// -- launch (host) -------------------------------------------------------------
 
 hipError_t launch_round(int D, const LaunchParams &lp, hipStream_t s) {
   unsigned long long wgs = lp.tiles / kWavesPerGroup;
@@ -459,33 +280,6 @@ hipError_t launch_round(int D, const LaunchParams &lp, hipStream_t s) {
     case 4: hipLaunchKernelGGL(qd_round_kernel<4>, grid, block, lp.lds, s, lp); break;
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_build(int D, const BuildParams &bp, hipStream_t s) {
-  dim3 grid(static_cast<uint32_t>(bp.threads / kBuildGroup)), block(kBuildGroup);
-  switch (D) {
-    case 1: hipLaunchKernelGGL(qd_build_kernel<1>, grid, block, bp.lds, s, bp); break;
-    case 2: hipLaunchKernelGGL(qd_build_kernel<2>, grid, block, bp.lds, s, bp); break;
-    case 3: hipLaunchKernelGGL(qd_build_kernel<3>, grid, block, bp.lds, s, bp); break;
-    case 4: hipLaunchKernelGGL(qd_build_kernel<4>, grid, block, bp.lds, s, bp); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_commit(const LaunchParams &lp, hipStream_t s) {
-  hipLaunchKernelGGL(qd_commit_kernel, dim3(lp.ndesc), dim3(256), 0, s, lp);
-  return hipGetLastError();
-}
-
-hipError_t launch_scatter(const CopyRec *rec, int n, const unsigned char *base, hipStream_t s) {
-  hipLaunchKernelGGL(qd_scatter_kernel, dim3(static_cast<uint32_t>(n)), dim3(256), 0, s, rec, base);
-  return hipGetLastError();
-}
-
-hipError_t launch_valu(uint32_t blocks, uint32_t iters, uint32_t *out, hipStream_t s) {
-  hipLaunchKernelGGL(qd_valu_kernel, dim3(blocks), dim3(256), 0, s, 12345u, iters, out);
   return hipGetLastError();
 }
 

@@ -53,7 +53,8 @@ class qd_stats(ctypes.Structure):
                 ("delta", ctypes.c_int * QD_MAX_GAMMA), ("L", ctypes.c_int), ("U", ctypes.c_int),
                 ("d_estimate", ctypes.c_int), ("predicted", ctypes.c_double),
                 ("combinations", ctypes.c_ulonglong), ("host_ms", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double), ("wall_ms", ctypes.c_double), ("nlog", ctypes.c_int),
+                ("kernel_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
+                ("launches", ctypes.c_int), ("nlog", ctypes.c_int),
                 ("log", qd_round_log * QD_MAX_LOG)]
 
     def rounds(self):
@@ -109,6 +110,7 @@ _lib.qd_engine_poll.argtypes = [ctypes.c_void_p, ctypes.POINTER(qd_result), _u8p
 _lib.qd_engine_outstanding.argtypes = [ctypes.c_void_p]
 _lib.qd_engine_destroy.argtypes = [ctypes.c_void_p]
 _lib.qd_valu_peak.argtypes = [ctypes.POINTER(ctypes.c_double)]
+_lib.qd_valu_mix.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
 
 
 def qd_strerror(status):
@@ -231,6 +233,16 @@ def qd_valu_peak():
     return st, v.value
 
 
+QD_MIXES = {"hotloop_sgpr": 0, "hotloop_vgpr": 1, "bcnt": 2, "xor_vgpr": 3, "xor_sgpr": 4}
+
+
+def qd_valu_mix(mix):
+    """(status, lane-ops/s) of one QD_MIX_* instruction mix."""
+    v = ctypes.c_double(0)
+    st = _lib.qd_valu_mix(int(mix), ctypes.byref(v))
+    return st, v.value
+
+
 def qd_engine_create(mem_budget=0, max_active=0, stream=None):
     """Returns an engine handle (int) or None."""
     h = _lib.qd_engine_create(mem_budget, max_active, ctypes.c_void_p(int(stream)) if stream else None)
@@ -264,5 +276,5 @@ def qd_engine_destroy(engine):
 def exported_symbols():
     """Names of the C ABI entry points declared in include/qdist.h."""
     return ["qd_distance", "qd_distance_ex", "qd_distance_batch", "qd_distance_batch_ex", "qd_plan",
-            "qd_round_min", "qd_strerror", "qd_device_check", "qd_valu_peak", "qd_engine_create",
+            "qd_round_min", "qd_strerror", "qd_device_check", "qd_valu_peak", "qd_valu_mix", "qd_engine_create",
             "qd_engine_submit", "qd_engine_poll", "qd_engine_outstanding", "qd_engine_destroy"]

@@ -213,3 +213,11 @@ def test_batch_equals_single(Q):
         st1, d1, _ = Q.qd_distance(G, f)
         assert st1 == 0 and d1 == d
         assert swt(w) == d
+
+
+def test_valu_probes_run(Q):
+    st, peak = Q.qd_valu_peak()
+    assert st == 0 and peak > 1e12
+    for name, mix in Q.QD_MIXES.items():
+        st, v = Q.qd_valu_mix(mix)
+        assert st == 0 and v > 1e12, name

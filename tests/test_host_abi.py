@@ -115,3 +115,9 @@ def test_engine_needs_gpu(Q):
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert not Q.qd_engine_create()
+
+
+def test_valu_mix_validation(Q):
+    # an unknown mix is rejected before any device work
+    assert Q.qd_valu_mix(-1)[0] == Q.QD_ERR_INVALID
+    assert Q.qd_valu_mix(len(Q.QD_MIXES))[0] == Q.QD_ERR_INVALID
