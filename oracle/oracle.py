@@ -197,3 +197,37 @@ def distance(G, field=2, nthreads=0):
         return brute(B, nthreads)
     d, w, _ = bz(B, DIAG_F4, 8, nthreads)
     return d, w
+
+
+def gamma_iso(B, max_gamma=8, with_rows=False):
+    """Information-set matrices of the isometric image (Sec. 2.4): returns
+    (rank, [ (k_j, pivot columns per row (-1: none), rows or None) ])."""
+    B, p = _u8(B)
+    m, n = B.shape[0], B.shape[1] // 2
+    h = ctypes.c_int(0)
+    k = np.zeros(max_gamma, dtype=np.int32)
+    piv = np.zeros(max_gamma * m, dtype=np.int32)
+    rows = np.zeros((max_gamma * m, 3 * n), dtype=np.uint8) if with_rows else None
+    r = lib().qdo_gamma_iso(p, m, n, max_gamma, ctypes.byref(h), k.ctypes.data_as(_ip),
+                            piv.ctypes.data_as(_ip), rows.ctypes.data_as(_u8p) if with_rows else None)
+    _check(r, "gamma_iso")
+    out = []
+    for j in range(h.value):
+        out.append((int(k[j]), piv[j * r:(j + 1) * r].copy(),
+                    rows[j * r:(j + 1) * r].copy() if with_rows else None))
+    return r, out
+
+
+def bz_iso(B, max_gamma=8, nthreads=0, log_cap=4096):
+    """Saved_isometry: (d, witness (a|b), log[(t, j, L_H, U_H, combinations)])."""
+    B, p = _u8(B)
+    n = B.shape[1] // 2
+    d = ctypes.c_int(-1)
+    wit = np.zeros(2 * n, dtype=np.uint8)
+    log = np.zeros((log_cap, 5), dtype=np.int64)
+    nl = ctypes.c_int(0)
+    _check(lib().qdo_bz_iso(p, B.shape[0], n, max_gamma, nthreads, ctypes.byref(d),
+                            wit.ctypes.data_as(_u8p),
+                            log.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), log_cap,
+                            ctypes.byref(nl)), "bz_iso")
+    return d.value, wit, _log_records(log, nl.value)

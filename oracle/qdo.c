@@ -681,3 +681,198 @@ int qdo_bz(const uint8_t *B, int m, int n, int diag, int max_gamma,
   free(P); free(off); free(delta); free(dims); free(piv); free(rows);
   return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Saved_isometry (Sec. 2.4): Brouwer-Zimmermann for the Hamming weight of  */
+/* the isometric image (a, b, a+b), a binary linear code of length 3n.      */
+
+static void iso_image(const uint8_t *row, int n, uint8_t *out) {
+  for (int q = 0; q < n; ++q) {
+    out[q] = row[q];
+    out[n + q] = row[n + q];
+    out[2 * n + q] = row[q] ^ row[n + q];
+  }
+}
+
+int qdo_gamma_iso(const uint8_t *B, int m, int n, int max_gamma, int *h_out,
+                  int *k, int *pivcol, uint8_t *rows) {
+  if (!B || m <= 0 || n <= 0 || max_gamma <= 0 || !h_out || !k || !pivcol)
+    return QDO_ERR_INVALID;
+  int len = 3 * n;
+  uint8_t *basis = (uint8_t *)malloc((size_t)m * 2 * n);
+  uint8_t *R = (uint8_t *)malloc((size_t)m * len);
+  int *used = (int *)calloc(len, sizeof(int));   /* column in an earlier set */
+  int *piv = (int *)malloc(sizeof(int) * m);     /* pivot column of each row */
+  if (!basis || !R || !used || !piv) {
+    free(basis); free(R); free(used); free(piv);
+    return QDO_ERR_NOMEM;
+  }
+  int r = reduce_basis(B, m, n, basis);
+  if (r == 0) { free(basis); free(R); free(used); free(piv); return QDO_ERR_ZERO_CODE; }
+  int h = 0;
+  while (h < max_gamma) {
+    /* Gamma_{h+1}: the basis rows, reduced row echelon form on the columns
+     * outside the earlier information sets, scanned left to right. */
+    for (int i = 0; i < r; ++i) iso_image(basis + (size_t)i * 2 * n, n, R + (size_t)i * len);
+    for (int i = 0; i < r; ++i) piv[i] = -1;
+    int kk = 0;
+    for (int c = 0; c < len && kk < r; ++c) {
+      if (used[c]) continue;
+      int p = -1;
+      for (int i = 0; i < r; ++i)
+        if (piv[i] < 0 && R[(size_t)i * len + c]) { p = i; break; }
+      if (p < 0) continue;
+      piv[p] = c;
+      ++kk;
+      for (int i = 0; i < r; ++i)
+        if (i != p && R[(size_t)i * len + c]) row_add(R + (size_t)i * len, R + (size_t)p * len, len);
+    }
+    if (kk == 0) break;  /* no column left that carries information */
+    for (int i = 0; i < r; ++i) {
+      pivcol[h * r + i] = piv[i];
+      if (piv[i] >= 0) used[piv[i]] = 1;
+      if (rows) memcpy(rows + (size_t)(h * r + i) * len, R + (size_t)i * len, len);
+    }
+    k[h] = kk;
+    ++h;
+  }
+  *h_out = h;
+  free(basis); free(R); free(used); free(piv);
+  return r;
+}
+
+typedef struct {
+  int m, t, W;
+  const uint64_t *el;  /* row i at i*W */
+  int best;
+  unsigned long long count;
+  uint64_t bestc[8];
+} hround_ctx;
+
+static int packed_hw(const uint64_t *c, int W) {
+  int w = 0;
+  for (int i = 0; i < W; ++i) w += __builtin_popcountll(c[i]);
+  return w;
+}
+
+static void hround_rec(hround_ctx *c, int start, int depth, const uint64_t *cur) {
+  if (depth == c->t) {
+    int w = packed_hw(cur, c->W);
+    ++c->count;
+    if (w < c->best) {
+      c->best = w;
+      memcpy(c->bestc, cur, sizeof(uint64_t) * c->W);
+    }
+    return;
+  }
+  uint64_t nxt[8];
+  for (int i = start; i <= c->m - (c->t - depth); ++i) {
+    const uint64_t *x = c->el + (size_t)i * c->W;
+    for (int k = 0; k < c->W; ++k) nxt[k] = cur[k] ^ x[k];
+    hround_rec(c, i + 1, depth + 1, nxt);
+  }
+}
+
+/* Minimum Hamming weight over all sums of t distinct rows of one matrix
+ * (m rows of len bytes). */
+static int hamming_round(const uint8_t *rows, int m, int len, int t, int nthreads,
+                         int *wmin, uint8_t *witness, unsigned long long *count) {
+  int W = (len + 63) / 64;
+  uint64_t *el = (uint64_t *)calloc((size_t)m * W + 1, sizeof(uint64_t));
+  if (!el) return QDO_ERR_NOMEM;
+  for (int i = 0; i < m; ++i)
+    for (int b = 0; b < len; ++b)
+      if (rows[(size_t)i * len + b]) el[(size_t)i * W + b / 64] |= 1ull << (b % 64);
+  int best = len + 1, best_i = m;
+  unsigned long long total = 0;
+  uint64_t bestc[8] = {0};
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic)
+  for (int i0 = 0; i0 < m; ++i0) {
+    if (i0 > m - t) continue;
+    hround_ctx c;
+    c.m = m; c.t = t; c.W = W; c.el = el; c.best = len + 1; c.count = 0;
+    memset(c.bestc, 0, sizeof(c.bestc));
+    hround_rec(&c, i0 + 1, 1, el + (size_t)i0 * W);
+#pragma omp critical
+    {
+      total += c.count;
+      if (c.best < best || (c.best == best && i0 < best_i)) {
+        best = c.best;
+        best_i = i0;
+        memcpy(bestc, c.bestc, sizeof(bestc));
+      }
+    }
+  }
+  *wmin = best;
+  *count = total;
+  if (witness)
+    for (int b = 0; b < len; ++b) witness[b] = (uint8_t)((bestc[b / 64] >> (b % 64)) & 1);
+  free(el);
+  return QDO_OK;
+}
+
+int qdo_bz_iso(const uint8_t *B, int m, int n, int max_gamma, int nthreads,
+               int *d, uint8_t *witness, long long *log, int log_cap, int *nlog) {
+  if (!B || m <= 0 || n <= 0 || !d) return m == 0 ? QDO_ERR_ZERO_CODE : QDO_ERR_INVALID;
+  if (3 * n > 512) return QDO_ERR_TOO_LARGE;
+  int len = 3 * n;
+  int G = max_gamma > 0 ? max_gamma : 1;
+  int *k = (int *)calloc(G, sizeof(int));
+  int *pivcol = (int *)calloc((size_t)G * m, sizeof(int));
+  uint8_t *rows = (uint8_t *)calloc((size_t)G * m * len, 1);
+  uint8_t *wit = (uint8_t *)calloc(len, 1);
+  uint8_t *cand = (uint8_t *)calloc(len, 1);
+  int *tdone = (int *)calloc(G, sizeof(int));
+  if (!k || !pivcol || !rows || !wit || !cand || !tdone) {
+    free(k); free(pivcol); free(rows); free(wit); free(cand); free(tdone);
+    return QDO_ERR_NOMEM;
+  }
+  int h = 0;
+  int r = qdo_gamma_iso(B, m, n, G, &h, k, pivcol, rows);
+  if (r < 0) {
+    *d = -1;
+    free(k); free(pivcol); free(rows); free(wit); free(cand); free(tdone);
+    return r;
+  }
+  /* Sec. 2.1 over the Hamming weight: U = least weight seen; a codeword not
+   * seen after Gamma_j's round t_j sums at least t_j + 1 of its rows, at
+   * least t_j + 1 - (r - k_j) of them pivot rows, each with its own 1 on
+   * Gamma_j's information set; the sets are disjoint. */
+  int U = len + 1, nl = 0, finished = 0;
+  for (int t = 1; !finished; ++t) {
+    if (t > r) break;
+    for (int j = 0; j < h && !finished; ++j) {
+      int w;
+      unsigned long long cnt;
+      int rc = hamming_round(rows + (size_t)j * r * len, r, len, t, nthreads, &w, cand, &cnt);
+      if (rc) { free(k); free(pivcol); free(rows); free(wit); free(cand); free(tdone); return rc; }
+      if (w < U) {
+        U = w;
+        memcpy(wit, cand, len);
+      }
+      tdone[j] = t;
+      int L = 0;
+      for (int i = 0; i < h; ++i) {
+        int c = tdone[i] + 1 - (r - k[i]);
+        L += c > 0 ? c : 0;
+      }
+      if (log && nl < log_cap) {
+        long long *e = log + 5 * nl;
+        e[0] = t; e[1] = j; e[2] = L; e[3] = U; e[4] = (long long)cnt;
+      }
+      ++nl;
+      if (L >= U || t == r) finished = 1; /* bound met, or every codeword seen */
+    }
+  }
+  if (nlog) *nlog = nl;
+  /* d = d_H / 2 (Sec. 2.4); the witness is the (a|b) part of the image. */
+  *d = U <= len ? U / 2 : -1;
+  if (witness) memcpy(witness, wit, 2 * n);
+  free(k); free(pivcol); free(rows); free(wit); free(cand); free(tdone);
+  return U <= len ? QDO_OK : QDO_ERR_ZERO_CODE;
+}

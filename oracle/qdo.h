@@ -11,7 +11,8 @@
  *   - Diagonalization_over_F2 with the appended rows: Sec. 2.2 (Alg. 1);
  *   - Diagonalization_over_F4, packages, principal columns and the lower
  *     bound contributed by a second generator matrix: Sec. 2.3 (Alg. 2);
- *   - the isometry (a,b) -> (a,b,a+b): Sec. 2.4 (Alg. 3).
+ *   - the isometry (a,b) -> (a,b,a+b) and Saved_isometry, Brouwer-
+ *     Zimmermann for the Hamming weight of the image: Sec. 2.4 (Alg. 3).
  *
  * Layout of a binary row: 2n bytes in {0,1}, x_1..x_n then z_1..z_n
  * (the paper's (a|b)).  F4 input: n bytes in {0,1,2,3}, code a+2b for the
@@ -96,6 +97,28 @@ int qdo_bz_gamma(int h, const int *P, const int *off, const int *delta,
 int qdo_bz(const uint8_t *B, int m, int n, int diag, int max_gamma,
            int nthreads, int *d, uint8_t *witness, long long *log,
            int log_cap, int *nlog);
+
+/* Saved_isometry (Sec. 2.4).  The image of each basis row (a|b) is
+ * (a, b, a+b): a binary linear code of length 3n whose Hamming weights are
+ * twice the symplectic weights.  Gamma_j is the reduced row echelon form of
+ * the basis images on the columns outside the information sets of
+ * Gamma_1..Gamma_{j-1}, scanned left to right (a-block, b-block,
+ * (a+b)-block); its k[j] pivot columns form its information set.  Stops at
+ * max_gamma matrices or when no column carries information.
+ *   pivcol[j*r+i] pivot column of row i of Gamma_j, or -1
+ *   rows          optional: (j*r+i) -> 3n bytes
+ * where r is the rank (the return value; < 0 on error). */
+int qdo_gamma_iso(const uint8_t *B, int m, int n, int max_gamma, int *h_out,
+                  int *k, int *pivcol, uint8_t *rows);
+
+/* Brouwer-Zimmermann for the Hamming weight (Sec. 2.1) over the matrices of
+ * qdo_gamma_iso: round t sums t distinct rows of Gamma_j; after each round
+ * L = sum_j max(0, t_j + 1 - (r - k_j)); stop when L >= U or a matrix has
+ * run all r rows.  d = d_H / 2; witness: the 2n bytes (a|b) of the
+ * codeword reaching d_H.  log records (t, j, L, U, combinations), with L
+ * and U in Hamming units. */
+int qdo_bz_iso(const uint8_t *B, int m, int n, int max_gamma, int nthreads,
+               int *d, uint8_t *witness, long long *log, int log_cap, int *nlog);
 
 #ifdef __cplusplus
 }

@@ -6,6 +6,7 @@ temporary library; the pin checks below must fail for every one of them and
 pass for the unmodified source.
 """
 import ctypes
+import math
 import os
 import subprocess
 
@@ -22,7 +23,8 @@ SRC = os.path.join(os.path.dirname(O.__file__), "qdo.c")
 MUTANTS = {
     "f2_no_full_clearing": ("      if (v != r && R[(size_t)v * len + col])\n        row_add(R + (size_t)v * len, R + (size_t)r * len, len);\n    rem[r] = 0;\n    second[q] = r;",
                             "      if (v != r && rem[v] && R[(size_t)v * len + col])\n        row_add(R + (size_t)v * len, R + (size_t)r * len, len);\n    rem[r] = 0;\n    second[q] = r;"),
-    "bound_abs_not_max": ("L += c > 0 ? c : 0;", "L += c > 0 ? c : -c;"),
+    "bound_abs_not_max": ("int c = tdone[i] + 1 - delta[i];\n        L += c > 0 ? c : 0;",
+                          "int c = tdone[i] + 1 - delta[i];\n        L += c > 0 ? c : -c;"),
     "bound_ignores_delta": ("int c = tdone[i] + 1 - delta[i];", "int c = tdone[i] + 1;"),
     "bound_off_by_one": ("int c = tdone[i] + 1 - delta[i];", "int c = tdone[i] + 2 - delta[i];"),
     "alpha_times_row_wrong": ("ag[n + q] = (uint8_t)(a ^ b);", "ag[n + q] = (uint8_t)a;"),
@@ -34,6 +36,13 @@ MUTANTS = {
     "stop_one_early": ("if (L >= U || t == P[j]) finished = 1;", "if (L + 1 >= U || t == P[j]) finished = 1;"),
     "two_dim_clears_with_wrong_row": ("        } else if (sv == ss) {\n          row_add(R + (size_t)v * len, R + (size_t)s * len, len);",
                                       "        } else if (sv == ss) {\n          row_add(R + (size_t)v * len, R + (size_t)r * len, len);"),
+    "iso_third_block_or": ("    out[2 * n + q] = row[q] ^ row[n + q];", "    out[2 * n + q] = row[q] | row[n + q];"),
+    "iso_bound_ignores_delta": ("int c = tdone[i] + 1 - (r - k[i]);", "int c = tdone[i] + 1;"),
+    "iso_echelon_not_reduced": ("        if (i != p && R[(size_t)i * len + c]) row_add(R + (size_t)i * len, R + (size_t)p * len, len);",
+                                "        if (i > p && R[(size_t)i * len + c]) row_add(R + (size_t)i * len, R + (size_t)p * len, len);"),
+    "iso_sets_not_disjoint": ("      if (piv[i] >= 0) used[piv[i]] = 1;", "      (void)used;"),
+    "iso_round_skips_last_row": ("  for (int i = start; i <= c->m - (c->t - depth); ++i) {",
+                                 "  for (int i = start; i < c->m - (c->t - depth); ++i) {"),
 }
 
 
@@ -62,11 +71,27 @@ def quick_pins():
             for diag in (O.DIAG_F2, O.DIAG_F4):
                 if O.bz(B, diag, 8)[0] != d0:
                     return False
+            if O.bz_iso(B, 8)[0] != d0:
+                return False
         for s in range(10):
             G = W.f4_linear(5, 2, W.config_seed(14, s))
             B = O.expand(G, 4)
             ref = py_exhaustive(np.concatenate([f4_to_bin(G), f4_to_bin(np.array([[[0, 2, 3, 1][c] for c in r] for r in G]))]))
             if O.brute(B)[0] != ref:
+                return False
+        for s in range(40):
+            B = W.tiny_code(91000 + s)
+            if not B.any():
+                continue
+            r, gs = O.gamma_iso(B, 8, with_rows=True)
+            for k, piv, rows in gs:
+                for i, c in enumerate(piv):
+                    if c >= 0 and (rows[i, c] != 1 or rows[:, c].sum() != 1):
+                        return False
+        for s in range(4):
+            B = O.expand(*W.config1(s))
+            _, _, log = O.bz_iso(B, 8)
+            if max(t for t, *_ in log) < 2 or any(cnt != math.comb(20, t) for t, j, L, U, cnt in log):
                 return False
         rows, dims = W.random_packages(6, 20, W.config_seed(15, 0), 0.5)
         sizes = [3 if d == 2 else 1 for d in dims]
