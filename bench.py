@@ -156,6 +156,33 @@ def leg_plain(Q, G, field, engine_step_ms, engine_combos):
             "engine_speedup": s.wall_ms / engine_step_ms}
 
 
+def leg_constructions(Q, W):
+    """Time to exact d per construction -- the paper's Saved_1_Gamma (F2),
+    Saved_2_Gamma generalized (F4) and Saved_isometry -- on config 2 seeds
+    0..4 and config 3 seed 0; a construction is skipped where its planned
+    work exceeds 1e12 combinations."""
+    out = {}
+    for name, cases in (("config2", [W.config2(i) for i in range(5)]), ("config3", [W.config3(0)])):
+        res = {}
+        for label, diag in (("F2", Q.QD_DIAG_F2), ("F4", Q.QD_DIAG_F4), ("isometry", Q.QD_DIAG_ISO)):
+            if any(Q.qd_plan(G, f, diag)["predicted_" + ("iso" if diag == Q.QD_DIAG_ISO else label.lower())] > 1e12
+                   for G, f in cases):
+                res[label] = "skipped (planned work > 1e12)"
+                continue
+            ms, comb, ds = [], 0, []
+            for G, f in cases:
+                Q.qd_distance_ex(G, f, diag=diag)
+                t0 = time.perf_counter()
+                st, d, _, s = Q.qd_distance_ex(G, f, diag=diag)
+                ms.append((time.perf_counter() - t0) * 1e3)
+                assert st == 0
+                comb += s.combinations
+                ds.append(d)
+            res[label] = {"mean_ms": sum(ms) / len(ms), "codewords": comb, "d": ds}
+        out[name] = res
+    return out
+
+
 def leg_latency(Q, W):
     out = {}
     for name, fn in (("config1", W.config1), ("config2", W.config2)):
@@ -309,6 +336,7 @@ def main():
         out["batched"] = leg_batched(Q, W, a)
         out["serving"] = leg_serving(Q, W, a)
         out["latency"] = leg_latency(Q, W)
+        out["constructions"] = leg_constructions(Q, W)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(G, field, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -49,6 +49,8 @@ extern "C" {
 #define QD_DIAG_AUTO 0
 #define QD_DIAG_F2 2
 #define QD_DIAG_F4 4
+#define QD_DIAG_ISO 3 /* Saved_isometry (Sec. 2.4): binary information sets of the
+                         image (x, z, x^z), bound on Hamming weight, d = d_H / 2 */
 
 #define QD_OK 0
 #define QD_INCOMPLETE 1 /* budget or cancel: *d = U, stats hold L <= d <= U */
@@ -65,7 +67,7 @@ extern "C" {
 
 /* Options of qd_distance_ex.  Zero-initialized means "library defaults". */
 typedef struct qd_options {
-  int diag;                   /* QD_DIAG_AUTO, QD_DIAG_F2 or QD_DIAG_F4 */
+  int diag;                   /* QD_DIAG_AUTO, QD_DIAG_F2, QD_DIAG_F4 or QD_DIAG_ISO */
   int max_gamma;              /* 0: planner decides; else at most this many matrices */
   unsigned long long budget;  /* stop before a round that would exceed this many
                                  combinations in total (0: no limit) -> QD_INCOMPLETE */
@@ -120,9 +122,12 @@ typedef struct qd_plan_info {
   int P[QD_MAX_GAMMA];
   int delta[QD_MAX_GAMMA];
   int dims[QD_MAX_GAMMA][2 * QD_MAX_N];   /* 1 or 2 per package */
-  int pivot[QD_MAX_GAMMA][2 * QD_MAX_N];  /* qubit, or -1 for delta packages */
+  int pivot[QD_MAX_GAMMA][2 * QD_MAX_N];  /* qubit, or -1 for delta packages; for
+                                             QD_DIAG_ISO the image column: q, n+q, 2n+q
+                                             for x, z, x^z of qubit q */
   int d_estimate;
   double predicted_f2, predicted_f4;      /* predicted combinations per construction */
+  double predicted_iso;
 } qd_plan_info;
 
 /* Symplectic minimum distance of the code spanned by G (Sec. 2 definition,
@@ -148,8 +153,8 @@ int qd_distance_batch_ex(int count, const uint8_t *const *G, const int *m, const
                          const int *field, const qd_options *opt, int *d,
                          uint8_t *const *witness, int *status, qd_stats *st);
 
-/* Host-only: the generator matrices (Sec. 2.2 / Sec. 2.3 diagonalizations)
- * and the planner's choice for one code.  diag = QD_DIAG_AUTO reports the
+/* Host-only: the generator matrices (Sec. 2.2 / Sec. 2.3 diagonalizations,
+ * Sec. 2.4 information sets) and the planner's choice for one code.  diag = QD_DIAG_AUTO reports the
  * construction the planner picks.  No GPU is touched. */
 int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma,
             qd_plan_info *out);

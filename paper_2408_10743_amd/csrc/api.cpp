@@ -167,7 +167,8 @@ int qd_distance_batch(int count, const uint8_t *const *G, const int *m, const in
 int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma, qd_plan_info *out) {
   if (!out) return QD_ERR_INVALID;
   std::memset(out, 0, sizeof(*out));
-  if (diag != QD_DIAG_AUTO && diag != QD_DIAG_F2 && diag != QD_DIAG_F4) return QD_ERR_INVALID;
+  if (diag != QD_DIAG_AUTO && diag != QD_DIAG_F2 && diag != QD_DIAG_F4 && diag != QD_DIAG_ISO)
+    return QD_ERR_INVALID;
   if (max_gamma < 0) return QD_ERR_INVALID;
   std::vector<BRow> rows;
   int rc = load_rows(G, m, n, field, rows);
@@ -180,16 +181,21 @@ int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma, 
   for (const Gamma &g : f4)
     if (!check_gamma(g, n)) return QD_ERR_INTERNAL;
   if (!check_gamma(f2, n)) return QD_ERR_INTERNAL;
-  PlanChoice pc = choose_plan(f4, f2, n, k, diag, max_gamma);
+  std::vector<Gamma> iso = build_iso(rows, n, hmax);
+  for (const Gamma &g : iso)
+    if (!check_gamma_iso(g, n)) return QD_ERR_INTERNAL;
+  PlanChoice pc = choose_plan(f4, f2, iso, n, k, diag, max_gamma);
   out->n = n;
   out->rank = k;
   out->d_estimate = pc.d_est;
   out->predicted_f2 = pc.predicted_f2;
   out->predicted_f4 = pc.predicted_f4;
+  out->predicted_iso = pc.predicted_iso;
   const int show = diag == QD_DIAG_AUTO ? pc.diag : diag;
   out->diag = show;
   std::vector<Gamma> gs;
   if (show == QD_DIAG_F2) gs.push_back(f2);
+  else if (show == QD_DIAG_ISO) gs = iso;
   else gs = f4;
   out->h = int(gs.size());
   out->h_used = show == pc.diag ? pc.h_used : out->h;

@@ -275,7 +275,10 @@ void Executor::prepare(Job &job) {
   job.t0 = now_ms();
   qd_options &o = job.opt;
   std::memset(&job.S, 0, sizeof(job.S));
-  if (o.diag != QD_DIAG_AUTO && o.diag != QD_DIAG_F2 && o.diag != QD_DIAG_F4) { job.status = QD_ERR_INVALID; return; }
+  if (o.diag != QD_DIAG_AUTO && o.diag != QD_DIAG_F2 && o.diag != QD_DIAG_F4 && o.diag != QD_DIAG_ISO) {
+    job.status = QD_ERR_INVALID;
+    return;
+  }
   if (o.seg_len < 0 || o.seg_len % kBlock || o.saved_depth < -1 || o.max_gamma < 0 || o.tops_mode < 0 ||
       o.tops_mode > 2) {
     job.status = QD_ERR_INVALID;
@@ -292,9 +295,22 @@ void Executor::prepare(Job &job) {
     for (const Gamma &g : f4)
       if (!check_gamma(g, n)) { job.status = QD_ERR_INTERNAL; return; }
     if (!check_gamma(f2, n)) { job.status = QD_ERR_INTERNAL; return; }
-    job.pc = choose_plan(f4, f2, n, job.rank, o.diag, o.max_gamma);
+    std::vector<Gamma> iso;
+    job.pc = choose_plan(f4, f2, iso, n, job.rank, o.diag == QD_DIAG_ISO ? QD_DIAG_AUTO : o.diag, o.max_gamma);
+    // The isometry matrices are built only when asked for, or when they
+    // might beat the other constructions' predicted work.
+    if (o.diag == QD_DIAG_ISO ||
+        (o.diag == QD_DIAG_AUTO && job.pc.predicted >= kIsoMinWork &&
+         iso_work_floor(n, job.rank, job.pc.d_est) < kIsoMargin * job.pc.predicted)) {
+      iso = build_iso(job.basis, n, kMaxGamma);
+      for (const Gamma &g : iso)
+        if (!check_gamma_iso(g, n)) { job.status = QD_ERR_INTERNAL; return; }
+      job.pc = choose_plan(f4, f2, iso, n, job.rank, o.diag, o.max_gamma);
+    }
     if (job.pc.diag == QD_DIAG_F2) job.use.push_back(f2);
+    else if (job.pc.diag == QD_DIAG_ISO) job.use.assign(iso.begin(), iso.begin() + job.pc.h_used);
     else job.use.assign(f4.begin(), f4.begin() + job.pc.h_used);
+    job.halve = job.pc.diag == QD_DIAG_ISO;
   }
   prepare_gammas(job);
 }
@@ -311,7 +327,7 @@ void Executor::prepare_gammas(Job &job) {
     job.S.P[j] = job.use[j].P();
     job.S.delta[j] = job.delta[j] = job.use[j].delta;
   }
-  job.L = lower_bound(job.tdone, job.delta);
+  job.L = lower_bound(job.tdone, job.delta, job.halve);
   job.U = n + 1;
   job.gd.assign(h, GammaDev{});
   for (int j = 0; j < h; ++j) {
@@ -552,7 +568,7 @@ int Executor::schedule(Job &job, int sharing) {
     cum += planned;
     ++job.j;
     tsim[fj] = t;
-    if (job.single_round || cum >= kSpecCombos || t == job.use[fj].P() || lower_bound(tsim, job.delta) >= stop_at)
+    if (job.single_round || cum >= kSpecCombos || t == job.use[fj].P() || lower_bound(tsim, job.delta, job.halve) >= stop_at)
       return QD_OK;
   }
 }
@@ -573,7 +589,7 @@ void Executor::end_round(Job &job, Flight &f) {
   job.visited += this_round;
   job.planned_total += f.planned;
   job.tdone[f.j] = f.t;
-  job.L = lower_bound(job.tdone, job.delta);
+  job.L = lower_bound(job.tdone, job.delta, job.halve);
   qd_stats &S = job.S;
   S.kernel_ms += f.ms;
   if (S.nlog < QD_MAX_LOG) {

@@ -104,6 +104,7 @@ struct Job {
   std::vector<BRow> basis;
   std::vector<Gamma> use;
   PlanChoice pc;
+  bool halve = false;  // isometry matrices: bounds count Hamming weight
   std::vector<GammaDev> gd;
   int state_slot = -1;
   PoolBuf data;  // visited counters, then every Gamma_j's elements and tables

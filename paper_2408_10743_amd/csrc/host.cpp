@@ -12,7 +12,6 @@ int rweight(const BRow &a) {
   return __builtin_popcountll(a.x[0] | a.z[0]) + __builtin_popcountll(a.x[1] | a.z[1]);
 }
 
-static inline void setbit(uint64_t *w, int q) { w[q >> 6] |= uint64_t(1) << (q & 63); }
 
 int load_rows(const uint8_t *G, int m, int n, int field, std::vector<BRow> &rows) {
   if (n <= 0 || m < 0 || (m > 0 && !G)) return QD_ERR_INVALID;
@@ -20,31 +19,34 @@ int load_rows(const uint8_t *G, int m, int n, int field, std::vector<BRow> &rows
   rows.clear();
   if (field == QD_FIELD_F2) {
     rows.resize(m);
+    unsigned bad = 0;  // any byte above 1
     for (int i = 0; i < m; ++i) {
       const uint8_t *g = G + size_t(i) * 2 * n;
       for (int q = 0; q < n; ++q) {
-        if (g[q] > 1 || g[n + q] > 1) return QD_ERR_INVALID;
-        if (g[q]) setbit(rows[i].x, q);
-        if (g[n + q]) setbit(rows[i].z, q);
+        bad |= unsigned(g[q] | g[n + q]);
+        rows[i].x[q >> 6] |= uint64_t(g[q] & 1) << (q & 63);
+        rows[i].z[q >> 6] |= uint64_t(g[n + q] & 1) << (q & 63);
       }
     }
-    return QD_OK;
+    return bad > 1 ? QD_ERR_INVALID : QD_OK;
   }
   if (field != QD_FIELD_F4) return QD_ERR_INVALID;
   // a + alpha b and alpha (a + alpha b) = b + alpha (a + b).
   rows.resize(size_t(2) * m);
+  unsigned bad = 0;  // any byte above 3
   for (int i = 0; i < m; ++i) {
     const uint8_t *g = G + size_t(i) * n;
     BRow &u = rows[2 * i], &v = rows[2 * i + 1];
     for (int q = 0; q < n; ++q) {
-      if (g[q] > 3) return QD_ERR_INVALID;
-      bool a = g[q] & 1, b = (g[q] >> 1) & 1;
-      if (a) setbit(u.x, q);
-      if (b) { setbit(u.z, q); setbit(v.x, q); }
-      if (a != b) setbit(v.z, q);
+      bad |= g[q];
+      const uint64_t a = g[q] & 1, b = (g[q] >> 1) & 1, bit = uint64_t(1) << (q & 63);
+      u.x[q >> 6] |= a ? bit : 0;
+      u.z[q >> 6] |= b ? bit : 0;
+      v.x[q >> 6] |= b ? bit : 0;
+      v.z[q >> 6] |= (a ^ b) ? bit : 0;
     }
   }
-  return QD_OK;
+  return bad > 3 ? QD_ERR_INVALID : QD_OK;
 }
 
 // Bit c of the 2n-bit row: c < n is x_c, else z_{c-n}.
@@ -72,17 +74,6 @@ int make_basis(std::vector<BRow> &rows, int n) {
 
 namespace {
 
-// Kind of column q over the candidate rows: 2 if two different nonzero
-// symbols occur, 1 if exactly one, 0 if none.
-int column_kind(const std::vector<BRow> &w, const std::vector<char> &cand, int q) {
-  unsigned seen = 0;
-  for (size_t v = 0; v < w.size(); ++v)
-    if (cand[v]) seen |= 1u << qsym(w[v], q);
-  seen &= 0xEu;
-  int c = __builtin_popcount(seen);
-  return c >= 2 ? 2 : c;
-}
-
 struct PkIdx {
   int dim, pivot, r, s;
 };
@@ -92,19 +83,33 @@ struct PkIdx {
 // `scope` (to 0 for a two-row package, to {0, beta} for a one-row one).
 void greedy_pass(std::vector<BRow> &w, std::vector<char> &cand, const std::vector<char> &scope,
                  const std::vector<char> &cols, int n, bool outside, std::vector<PkIdx> &out) {
-  std::vector<char> done(n, 0), used(w.size(), 0);
+  std::vector<char> used(w.size(), 0);
+  uint64_t avail[2] = {0, 0};  // allowed qubits not pivoted yet
+  for (int q = 0; q < n; ++q)
+    if (cols[q]) avail[q >> 6] |= uint64_t(1) << (q & 63);
   for (;;) {
-    int q1 = -1, q2 = -1;
-    for (int q = 0; q < n && q2 < 0; ++q) {
-      if (!cols[q] || done[q]) continue;
-      int k = column_kind(w, cand, q);
-      if (k == 2) q2 = q;
-      else if (k == 1 && q1 < 0) q1 = q;
+    // Per qubit, which nonzero symbols (x only, z only, both) the candidate
+    // rows show; two different ones make a two-row column.
+    uint64_t sx[2] = {0, 0}, sz[2] = {0, 0}, sy[2] = {0, 0};
+    for (size_t v = 0; v < w.size(); ++v) {
+      if (!cand[v]) continue;
+      for (int i = 0; i < 2; ++i) {
+        sx[i] |= w[v].x[i] & ~w[v].z[i];
+        sz[i] |= w[v].z[i] & ~w[v].x[i];
+        sy[i] |= w[v].x[i] & w[v].z[i];
+      }
     }
-    const int q = q2 >= 0 ? q2 : q1;
+    uint64_t k2[2], k1[2];
+    for (int i = 0; i < 2; ++i) {
+      const uint64_t two = (sx[i] & sz[i]) | (sx[i] & sy[i]) | (sz[i] & sy[i]);
+      k2[i] = two & avail[i];
+      k1[i] = (sx[i] | sz[i] | sy[i]) & ~two & avail[i];
+    }
+    auto first = [](const uint64_t *a) { return a[0] ? __builtin_ctzll(a[0]) : a[1] ? 64 + __builtin_ctzll(a[1]) : -1; };
+    const int q2 = first(k2), q = q2 >= 0 ? q2 : first(k1);
     if (q < 0) break;
     const int dim = q2 >= 0 ? 2 : 1;
-    done[q] = 1;
+    avail[q >> 6] &= ~(uint64_t(1) << (q & 63));
     int r = -1, s = -1;
     for (size_t v = 0; v < w.size() && r < 0; ++v)
       if (cand[v] && qsym(w[v], q)) r = int(v);
@@ -252,6 +257,90 @@ bool check_gamma(const Gamma &g, int n) {
   return true;
 }
 
+int iso_bit(const BRow &r, int c, int n) {
+  if (c < 2 * n) return rbit(r, c, n);
+  return rbit(r, c - 2 * n, n) ^ rbit(r, c - n, n);
+}
+
+std::vector<Gamma> build_iso(const std::vector<BRow> &basis, int n, int max_gamma) {
+  const int k = int(basis.size()), KW = (k + 63) / 64, C = 3 * n;
+  std::vector<char> used(C, 0);
+  std::vector<Gamma> out;
+  // Image columns of a row, as (column, ...) callbacks: x bits at q, z bits
+  // at n + q, x^z bits at 2n + q.
+  auto for_image_bits = [n](const BRow &r, auto &&f) {
+    for (int b = 0; b < 3; ++b)
+      for (int i = 0; i < 2; ++i) {
+        uint64_t v = b == 0 ? r.x[i] : b == 1 ? r.z[i] : (r.x[i] ^ r.z[i]);
+        while (v) {
+          const int q = 64 * i + __builtin_ctzll(v);
+          v &= v - 1;
+          if (q < n) f(b * n + q);
+        }
+      }
+  };
+  while (int(out.size()) < max_gamma) {
+    std::vector<BRow> w = basis;
+    std::vector<int> piv(k, -1);
+    // col[c * KW + i]: the rows whose image has a 1 in column c.
+    std::vector<uint64_t> col(size_t(C) * KW, 0), pivoted(KW, 0), S(KW);
+    for (int v = 0; v < k; ++v)
+      for_image_bits(w[v], [&](int c) { col[size_t(c) * KW + (v >> 6)] |= uint64_t(1) << (v & 63); });
+    int pivots = 0;
+    for (int c = 0; c < C && pivots < k; ++c) {
+      if (used[c]) continue;
+      int p = -1;
+      for (int i = 0; i < KW && p < 0; ++i) {
+        const uint64_t f = col[size_t(c) * KW + i] & ~pivoted[i];
+        if (f) p = 64 * i + __builtin_ctzll(f);
+      }
+      if (p < 0) continue;
+      piv[p] = c;
+      pivoted[p >> 6] |= uint64_t(1) << (p & 63);
+      ++pivots;
+      // Clear column c in every other row; their images change by row p's.
+      bool any = false;
+      for (int i = 0; i < KW; ++i) {
+        S[i] = col[size_t(c) * KW + i] & ~(i == (p >> 6) ? uint64_t(1) << (p & 63) : 0);
+        any = any || S[i];
+      }
+      if (!any) continue;
+      for (int i = 0; i < KW; ++i)
+        for (uint64_t v = S[i]; v; v &= v - 1) radd(w[64 * i + __builtin_ctzll(v)], w[p]);
+      for_image_bits(w[p], [&](int c2) {
+        for (int i = 0; i < KW; ++i) col[size_t(c2) * KW + i] ^= S[i];
+      });
+    }
+    if (pivots == 0) break;
+    Gamma g;
+    for (int v = 0; v < k; ++v) {
+      Package pk;
+      pk.pivot = piv[v];
+      pk.r = w[v];
+      g.pk.push_back(pk);
+      if (piv[v] >= 0) used[piv[v]] = 1;
+      else ++g.delta;
+    }
+    out.push_back(g);
+  }
+  return out;
+}
+
+bool check_gamma_iso(const Gamma &g, int n) {
+  std::vector<char> seen(3 * kMaxN, 0);
+  int delta = 0;
+  for (size_t i = 0; i < g.pk.size(); ++i) {
+    const Package &p = g.pk[i];
+    if (p.dim != 1) return false;
+    if (p.pivot < 0) { ++delta; continue; }
+    if (p.pivot >= 3 * n || seen[p.pivot] || !iso_bit(p.r, p.pivot, n)) return false;
+    seen[p.pivot] = 1;
+    for (size_t j = 0; j < g.pk.size(); ++j)
+      if (j != i && iso_bit(g.pk[j].r, p.pivot, n)) return false;
+  }
+  return delta == g.delta;
+}
+
 static inline uint64_t sat_add(uint64_t a, uint64_t b) { return (a + b > kSat) ? kSat : a + b; }
 static inline uint64_t sat_mul(uint64_t a, int c) { return a > kSat / 3 ? kSat : std::min<uint64_t>(a * c, kSat); }
 
@@ -280,62 +369,82 @@ uint64_t esym(const std::vector<int> &sizes, int t) {
   return e[t];
 }
 
-static double esym_d(const std::vector<int> &sizes, int t) {
-  std::vector<double> e(t + 1, 0.0);
-  e[0] = 1.0;
-  for (int c : sizes)
-    for (int r = t; r > 0; --r) e[r] += e[r - 1] * c;
-  return e[t];
-}
-
-int lower_bound(const std::vector<int> &tdone, const std::vector<int> &delta) {
+int lower_bound(const std::vector<int> &tdone, const std::vector<int> &delta, bool halve) {
   int L = 0;
   for (size_t j = 0; j < tdone.size(); ++j) L += std::max(0, tdone[j] + 1 - delta[j]);
-  return L;
+  return halve ? (L + 1) / 2 : L;
 }
 
 int estimate_distance(int n, int k, int upper) {
   // log2 of the expected number of nonzero codewords of weight <= w in a
-  // random code of 2^k words inside the 4^n symplectic space.
-  double lk = k >= 60 ? double(k) : std::log2(std::ldexp(1.0, k) - 1.0);
-  double acc = 0.0;
+  // random code of 2^k words inside the 4^n symplectic space; lc(w) =
+  // log2(C(n, w) 3^w), updated from w - 1.
+  const double lk = k >= 60 ? double(k) : std::log2(std::ldexp(1.0, k) - 1.0);
+  const double l3 = std::log2(3.0);
+  double acc = 0.0, lc = 0.0;
   for (int w = 1; w <= n; ++w) {
-    double lc = (std::lgamma(n + 1.0) - std::lgamma(w + 1.0) - std::lgamma(n - w + 1.0)) / std::log(2.0) +
-                w * std::log2(3.0);
+    lc += std::log2(double(n - w + 1) / double(w)) + l3;
     acc += std::exp2(lc - 2.0 * n + lk);
     if (acc >= 1.0) return std::max(1, std::min(upper, w));
   }
   return std::max(1, std::min(upper, n));
 }
 
-static std::vector<int> sizes_of(const Gamma &g) {
-  std::vector<int> s;
-  for (const Package &p : g.pk) s.push_back(p.dim == 2 ? 3 : 1);
-  return s;
+// e_t(sizes) as doubles for t = 0..P, one table per matrix.
+static std::vector<double> esym_all(const Gamma &g) {
+  std::vector<double> e(g.P() + 1, 0.0);
+  e[0] = 1.0;
+  for (const Package &p : g.pk) {
+    const double c = p.dim == 2 ? 3.0 : 1.0;
+    for (int r = g.P(); r > 0; --r) e[r] += e[r - 1] * c;
+  }
+  return e;
 }
 
-double predict_work(const std::vector<Gamma> &gs, int h, int d_est) {
+static double predict_with(const std::vector<Gamma> &gs, const std::vector<std::vector<double>> &E, int h,
+                           int d_est, bool halve) {
   std::vector<int> tdone(h, 0), delta(h);
-  std::vector<std::vector<int>> sz(h);
-  for (int j = 0; j < h; ++j) {
-    delta[j] = gs[j].delta;
-    sz[j] = sizes_of(gs[j]);
-  }
-  if (lower_bound(tdone, delta) >= d_est) return 0.0;
+  for (int j = 0; j < h; ++j) delta[j] = gs[j].delta;
+  if (lower_bound(tdone, delta, halve) >= d_est) return 0.0;
   double w = 0.0;
   for (int t = 1; t <= kMaxN * 2; ++t) {
     for (int j = 0; j < h; ++j) {
       if (t > gs[j].P()) continue;
-      w += esym_d(sz[j], t);
+      w += E[j][t];
       tdone[j] = t;
-      if (lower_bound(tdone, delta) >= d_est || t == gs[j].P()) return w;
+      if (lower_bound(tdone, delta, halve) >= d_est || t == gs[j].P()) return w;
     }
   }
   return w;
 }
 
-PlanChoice choose_plan(const std::vector<Gamma> &f4, const Gamma &f2, int n, int rank, int diag_req,
-                       int max_gamma_req) {
+double predict_work(const std::vector<Gamma> &gs, int h, int d_est, bool halve) {
+  std::vector<std::vector<double>> E;
+  for (int j = 0; j < h; ++j) E.push_back(esym_all(gs[j]));
+  return predict_with(gs, E, h, d_est, halve);
+}
+
+double iso_work_floor(int n, int rank, int d_est) {
+  // Information sets are disjoint subsets of the 3n image columns with at
+  // most `rank` columns each, so after round t the Hamming bound is at most
+  // full * (t + 1) + max(0, t + 1 - (rank - rest)); it must reach
+  // 2 d_est - 1 (the bound is halved, rounding up).
+  if (rank <= 0) return 0.0;
+  const int full = 3 * n / rank, rest = 3 * n % rank, need = 2 * d_est - 1;
+  for (int t = 0; t <= rank; ++t) {
+    const int L = full * (t + 1) + std::max(0, t + 1 - (rank - rest));
+    if (L >= need) {
+      if (t == 0) return 0.0;
+      double c = 1.0;  // C(rank, t): the least work of a round t on one matrix
+      for (int i = 1; i <= t; ++i) c = c * double(rank - t + i) / double(i);
+      return c;
+    }
+  }
+  return 0.0;
+}
+
+PlanChoice choose_plan(const std::vector<Gamma> &f4, const Gamma &f2, const std::vector<Gamma> &iso, int n,
+                       int rank, int diag_req, int max_gamma_req) {
   int upper = n;
   auto probe = [&](const Gamma &g) {
     for (const Package &p : g.pk) {
@@ -349,27 +458,42 @@ PlanChoice choose_plan(const std::vector<Gamma> &f4, const Gamma &f2, int n, int
   };
   for (const Gamma &g : f4) probe(g);
   probe(f2);
+  for (const Gamma &g : iso) probe(g);
   PlanChoice pc;
   pc.d_est = estimate_distance(n, rank, upper);
-  const int hmax = max_gamma_req > 0 ? std::min<int>(max_gamma_req, int(f4.size())) : int(f4.size());
   double best = -1.0;
-  pc.predicted_f4 = -1.0;
-  if (diag_req != QD_DIAG_F2) {
+  // Matrices 1..h of one construction, for the h with the least work.
+  auto consider = [&](const std::vector<Gamma> &gs, int diag, bool halve, double *pred) {
+    const int hmax = max_gamma_req > 0 ? std::min<int>(max_gamma_req, int(gs.size())) : int(gs.size());
+    std::vector<std::vector<double>> E;
+    for (int j = 0; j < hmax; ++j) E.push_back(esym_all(gs[j]));
+    *pred = -1.0;
     for (int h = 1; h <= hmax; ++h) {
-      double w = predict_work(f4, h, pc.d_est);
-      if (pc.predicted_f4 < 0 || w < pc.predicted_f4) pc.predicted_f4 = w;
+      const double w = predict_with(gs, E, h, pc.d_est, halve);
+      if (*pred < 0 || w < *pred) *pred = w;
+      if (diag_req != QD_DIAG_AUTO && diag_req != diag) continue;
       if (best < 0 || w < best) {
         best = w;
-        pc.diag = QD_DIAG_F4;
+        pc.diag = diag;
         pc.h_used = h;
       }
     }
-  }
-  pc.predicted_f2 = predict_work(std::vector<Gamma>{f2}, 1, pc.d_est);
-  if (diag_req != QD_DIAG_F4 && (best < 0 || pc.predicted_f2 < best)) {
-    best = pc.predicted_f2;
-    pc.diag = QD_DIAG_F2;
-    pc.h_used = 1;
+  };
+  consider(f4, QD_DIAG_F4, false, &pc.predicted_f4);
+  consider(std::vector<Gamma>{f2}, QD_DIAG_F2, false, &pc.predicted_f2);
+  if (!iso.empty()) {
+    // The isometry brings more matrices (tables, uploads, rounds), so the
+    // automatic choice takes it only for a clear saving of real work.
+    const PlanChoice other = pc;
+    const double other_best = best;
+    consider(iso, QD_DIAG_ISO, true, &pc.predicted_iso);
+    if (diag_req == QD_DIAG_AUTO && pc.diag == QD_DIAG_ISO &&
+        !(other_best >= kIsoMinWork && best < kIsoMargin * other_best)) {
+      const double p_iso = pc.predicted_iso;
+      pc = other;
+      pc.predicted_iso = p_iso;
+      best = other_best;
+    }
   }
   pc.predicted = best;
   return pc;

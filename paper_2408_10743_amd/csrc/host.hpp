@@ -57,6 +57,23 @@ Gamma build_f2(const std::vector<BRow> &basis, int n);
 // Checks the package invariants behind the lower bound; true when they hold.
 bool check_gamma(const Gamma &g, int n);
 
+// Saved_isometry (Sec. 2.4).  The image (x, z, x^z) of the code is a binary
+// code of length 3n with Hamming weight = 2 x symplectic weight.  Matrix j
+// is the reduced row echelon form of the basis on the image columns (q,
+// n+q, 2n+q for x, z, x^z of qubit q) outside the information sets of the
+// earlier matrices, scanned in that order; every package is one row,
+// pivoted on its image column or -1 (delta).  At most max_gamma matrices,
+// each with >= 1 pivot.  Its bounds count Hamming weight (lower_bound with
+// halve = true).
+std::vector<Gamma> build_iso(const std::vector<BRow> &basis, int n, int max_gamma);
+
+// Reduced form of an isometry matrix: each pivot row has a 1 on its image
+// column, every other row a 0; pivot columns distinct.
+bool check_gamma_iso(const Gamma &g, int n);
+
+// Bit of image column c (0 <= c < 3n) of a row.
+int iso_bit(const BRow &r, int c, int n);
+
 // Elementary symmetric polynomials e_r of package sizes (1 or 3) as
 // saturating 64-bit integers.  prefix[h][r] = e_r(c_0..c_{h-1}),
 // suffix[h][r] = e_r(c_h..c_{P-1}); rmax columns + 1.
@@ -65,15 +82,18 @@ void esym_tables(const std::vector<int> &sizes, int rmax, std::vector<uint64_t> 
                  std::vector<uint64_t> &suffix);
 uint64_t esym(const std::vector<int> &sizes, int t);
 
-// Lower bound after matrix j has finished round t_j (t_j = 0: nothing yet).
-int lower_bound(const std::vector<int> &tdone, const std::vector<int> &delta);
+// Lower bound after matrix j has finished round t_j (t_j = 0: nothing yet):
+// sum_j max(0, t_j + 1 - delta_j).  With halve (isometry matrices, whose
+// bound counts Hamming weight, twice the symplectic weight) it is rounded
+// up to half of that.
+int lower_bound(const std::vector<int> &tdone, const std::vector<int> &delta, bool halve = false);
 
 struct PlanChoice {
   int diag = 4;
   int h_used = 1;
   int d_est = 0;
   double predicted = 0;
-  double predicted_f2 = 0, predicted_f4 = 0;
+  double predicted_f2 = 0, predicted_f4 = 0, predicted_iso = -1;
 };
 
 // Distance estimate for a code of rank k on n qubits with a known upper
@@ -82,10 +102,22 @@ struct PlanChoice {
 int estimate_distance(int n, int k, int upper);
 
 // Predicted combinations to certify distance d_est with the given matrices.
-double predict_work(const std::vector<Gamma> &gs, int h, int d_est);
+double predict_work(const std::vector<Gamma> &gs, int h, int d_est, bool halve = false);
 
-// Picks the construction and number of matrices with the least predicted work.
-PlanChoice choose_plan(const std::vector<Gamma> &f4, const Gamma &f2, int n, int rank,
-                       int diag_req, int max_gamma_req);
+// The automatic choice takes the isometry matrices only when the other
+// constructions need at least kIsoMinWork combinations and the isometry
+// less than kIsoMargin of that.
+constexpr double kIsoMinWork = 1e8;
+constexpr double kIsoMargin = 0.8;
+
+// A lower bound on predict_work for any isometry matrices of a rank-`rank`
+// code on n qubits (0 when none can be given): callers may skip building
+// them when it exceeds a cheaper construction's prediction.
+double iso_work_floor(int n, int rank, int d_est);
+
+// Picks the construction (F2, F4 or isometry, or the one diag_req names)
+// and the number of matrices with the least predicted work.
+PlanChoice choose_plan(const std::vector<Gamma> &f4, const Gamma &f2, const std::vector<Gamma> &iso, int n,
+                       int rank, int diag_req, int max_gamma_req);
 
 }  // namespace qd

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqdist.so")
 
 QD_FIELD_F2, QD_FIELD_F4 = 2, 4
-QD_DIAG_AUTO, QD_DIAG_F2, QD_DIAG_F4 = 0, 2, 4
+QD_DIAG_AUTO, QD_DIAG_F2, QD_DIAG_F4, QD_DIAG_ISO = 0, 2, 4, 3
 QD_OK, QD_INCOMPLETE = 0, 1
 QD_ERR_INVALID, QD_ERR_ZERO_CODE, QD_ERR_TOO_LARGE = -1, -2, -3
 QD_ERR_NOMEM, QD_ERR_DEVICE, QD_ERR_INTERNAL = -4, -5, -6
@@ -85,7 +85,7 @@ class qd_plan_info(ctypes.Structure):
                 ("dims", (ctypes.c_int * (2 * QD_MAX_N)) * QD_MAX_GAMMA),
                 ("pivot", (ctypes.c_int * (2 * QD_MAX_N)) * QD_MAX_GAMMA),
                 ("d_estimate", ctypes.c_int), ("predicted_f2", ctypes.c_double),
-                ("predicted_f4", ctypes.c_double)]
+                ("predicted_f4", ctypes.c_double), ("predicted_iso", ctypes.c_double)]
 
 
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -204,7 +204,7 @@ def qd_plan(G, field=QD_FIELD_F2, diag=QD_DIAG_AUTO, max_gamma=0):
                    "pivots": list(info.pivot[j])[:P]})
     return {"n": info.n, "rank": info.rank, "diag": info.diag, "h": info.h, "h_used": info.h_used,
             "gammas": gs, "d_estimate": info.d_estimate, "predicted_f2": info.predicted_f2,
-            "predicted_f4": info.predicted_f4}
+            "predicted_f4": info.predicted_f4, "predicted_iso": info.predicted_iso}
 
 
 def qd_round_min(rows, dims, t):

@@ -124,7 +124,11 @@ def test_structure_matches_oracle(Q):
         B = O.expand(G, f)
         st, d, wit, s = Q.qd_distance_ex(G, f)
         assert st == 0
-        gs = O.gamma(B, s.diag, 8)
+        if s.diag == Q.QD_DIAG_ISO:  # the planner may pick the isometry for small codes
+            r, gi = O.gamma_iso(B, 8)
+            gs = [{"P": r, "delta": r - k} for k, _, _ in gi]
+        else:
+            gs = O.gamma(B, s.diag, 8)
         for j in range(s.h):
             assert (s.P[j], s.delta[j]) == (gs[j]["P"], gs[j]["delta"])
 
@@ -221,3 +225,44 @@ def test_valu_probes_run(Q):
     for name, mix in Q.QD_MIXES.items():
         st, v = Q.qd_valu_mix(mix)
         assert st == 0 and v > 1e12, name
+
+
+def test_isometry_path_against_oracle(Q):
+    """Saved_isometry on the GPU: the same distances as brute force and the
+    oracle's Hamming BZ; every completed round visits C(r, t) rows subsets;
+    the bound after each round is the oracle's Hamming bound, halved."""
+    import math
+    for i in range(30):
+        G, f = W.config1(i)
+        B = O.expand(G, f)
+        d_ref, _ = O.brute(B)
+        print(f"iso config1 seed {i} d={d_ref}", flush=True)
+        s = check_distance(Q, G, f, d_ref, diag=Q.QD_DIAG_ISO)
+        assert s.diag == Q.QD_DIAG_ISO
+        d_o, _, olog = O.bz_iso(B, s.h)  # the matrices the planner kept
+        assert d_o == d_ref
+        rounds = s.rounds()
+        for r, o in zip(rounds, olog):
+            assert (r["t"], r["j"]) == (o[0], o[1])
+            assert r["L"] == (o[2] + 1) // 2
+            assert r["planned"] == math.comb(s.rank, r["t"])
+        for r in rounds[:-1]:
+            assert r["combinations"] == r["planned"]
+    gold = json.load(open(os.path.join(GOLD_DIR, "oracle_distances.json")))
+    for i in range(3):
+        G, f = W.config2(i)
+        print(f"iso config2 seed {i}", flush=True)
+        check_distance(Q, G, f, gold["config2"][i], diag=Q.QD_DIAG_ISO)
+    for n in (7, 33, 64, 65, 100, 128):
+        G = W.additive(n, 14, W.config_seed(42, n))
+        d_ref, _ = O.brute(O.expand(G, 2))
+        print(f"iso additive n={n} d={d_ref}", flush=True)
+        check_distance(Q, G, 2, d_ref, diag=Q.QD_DIAG_ISO)
+
+
+def test_isometry_batch_and_mix(Q):
+    codes = [W.config1(400 + i) for i in range(6)] + [W.config2(0)]
+    st, ds, wits, sts, stats = Q.qd_distance_batch(codes, diag=Q.QD_DIAG_ISO)
+    assert st == 0 and all(x == 0 for x in sts)
+    for (G, f), d in zip(codes, ds):
+        assert d == Q.qd_distance_ex(G, f, diag=Q.QD_DIAG_F4)[1]

@@ -121,3 +121,35 @@ def test_valu_mix_validation(Q):
     # an unknown mix is rejected before any device work
     assert Q.qd_valu_mix(-1)[0] == Q.QD_ERR_INVALID
     assert Q.qd_valu_mix(len(Q.QD_MIXES))[0] == Q.QD_ERR_INVALID
+
+
+def _iso_sets(gs):
+    return [(g["P"], g["delta"], tuple(sorted(p for p in g["pivots"] if p >= 0))) for g in gs]
+
+
+def _oracle_iso_sets(B):
+    r, gs = O.gamma_iso(B, 8)
+    return [(r, r - k, tuple(sorted(int(c) for c in piv if c >= 0))) for k, piv, _ in gs]
+
+
+def test_iso_structure_matches_oracle(Q):
+    # Saved_isometry: the information sets (pivot image columns) and delta of
+    # every matrix are determined by the column order, whatever the basis
+    for s in range(800):
+        B = W.tiny_code(72000 + s, n_max=10, m_max=20)
+        if not B.any():
+            continue
+        assert _iso_sets(Q.qd_plan(B, 2, Q.QD_DIAG_ISO, 8)["gammas"]) == _oracle_iso_sets(B), s
+    for G, f in [W.config1(0), W.config2(0), W.config3(0), W.config1(5)]:
+        p = Q.qd_plan(G, f, Q.QD_DIAG_ISO, 8)
+        assert p["diag"] == Q.QD_DIAG_ISO
+        assert _iso_sets(p["gammas"]) == _oracle_iso_sets(O.expand(G, f))
+        assert p["predicted_iso"] > 0 and all(d == 1 for g in p["gammas"] for d in g["dims"])
+
+
+def test_iso_planner_prefers_cheaper_construction(Q):
+    # the isometry costs more than the F4 matrices on the config shapes, so
+    # the automatic choice stays with F4 there
+    for G, f in [W.config1(0), W.config2(0), W.config3(0)]:
+        p = Q.qd_plan(G, f)
+        assert p["diag"] == Q.QD_DIAG_F4 and p["predicted_f4"] <= p["predicted_iso"]
