@@ -231,3 +231,30 @@ def bz_iso(B, max_gamma=8, nthreads=0, log_cap=4096):
                             log.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), log_cap,
                             ctypes.byref(nl)), "bz_iso")
     return d.value, wit, _log_records(log, nl.value)
+
+
+def brute_stab(B, nthreads=0):
+    """Exhaustive Modified-BZ minimum: least weight over span(B) minus its
+    symplectic radical (the stabilizer when B generates a normalizer)."""
+    B, p = _u8(B)
+    n = B.shape[1] // 2
+    d = ctypes.c_int(-1)
+    wit = np.zeros(2 * n, dtype=np.uint8)
+    _check(lib().qdo_brute_stab(p, B.shape[0], n, nthreads, ctypes.byref(d), wit.ctypes.data_as(_u8p)),
+           "brute_stab")
+    return d.value, wit
+
+
+def bz_stab(B, diag=DIAG_F4, max_gamma=8, nthreads=0, log_cap=4096):
+    """Modified BZ (Sec. 2.1) over the diag construction: (d, witness, log)."""
+    B, p = _u8(B)
+    n = B.shape[1] // 2
+    d = ctypes.c_int(-1)
+    wit = np.zeros(2 * n, dtype=np.uint8)
+    log = np.zeros((log_cap, 5), dtype=np.int64)
+    nl = ctypes.c_int(0)
+    _check(lib().qdo_bz_stab(p, B.shape[0], n, diag, max_gamma, nthreads, ctypes.byref(d),
+                             wit.ctypes.data_as(_u8p),
+                             log.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), log_cap,
+                             ctypes.byref(nl)), "bz_stab")
+    return d.value, wit, _log_records(log, nl.value)

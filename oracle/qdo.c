@@ -128,6 +128,34 @@ static void unpack_row(const uint64_t *c, int n, uint8_t *v) {
   }
 }
 
+/* Symplectic product <a, b>_s = a_x . b_z + a_z . b_x (mod 2). */
+static int sym_product(const uint64_t *a, const uint64_t *b, int W) {
+  int p = 0;
+  for (int i = 0; i < W; ++i) p ^= __builtin_parityll((a[i] & b[W + i]) ^ (a[W + i] & b[i]));
+  return p;
+}
+
+/* Modified BZ (Sec. 2.1): a codeword c of the span N of the rows updates U
+ * only when it lies in C^{perp_s} \ C.  With N = C^{perp_s} the stabilizer
+ * is C = N^{perp_s}, so c is admitted when its symplectic product with some
+ * row of N is 1.  chk holds the m rows (2W words each); m = 0 admits every
+ * codeword. */
+static int admitted(const uint64_t *c, const uint64_t *chk, int m, int W) {
+  if (m == 0) return 1;
+  for (int r = 0; r < m; ++r)
+    if (sym_product(c, chk + (size_t)r * 2 * W, W)) return 1;
+  return 0;
+}
+
+/* The filter applies unless the span is self-orthogonal (the k = 0 case of
+ * Sec. 2.1, where every codeword updates U): returns m or 0. */
+static int filter_rows(const uint64_t *R, int m, int W) {
+  for (int i = 0; i < m; ++i)
+    for (int j = i + 1; j < m; ++j)
+      if (sym_product(R + (size_t)i * 2 * W, R + (size_t)j * 2 * W, W)) return m;
+  return 0;
+}
+
 static int packed_swt(const uint64_t *c, int W) {
   int w = 0;
   for (int i = 0; i < W; ++i) w += __builtin_popcountll(c[i] | c[W + i]);
@@ -137,14 +165,15 @@ static int packed_swt(const uint64_t *c, int W) {
 /* ------------------------------------------------------------------------ */
 /* Exhaustive minimum (the definition of the distance, Sec. 2).             */
 
-int qdo_brute(const uint8_t *B, int m, int n, int nthreads, int *d,
-              uint8_t *witness) {
+static int brute_impl(const uint8_t *B, int m, int n, int nthreads, int filter, int *d,
+                      uint8_t *witness) {
   if (!B || !d || m <= 0 || n <= 0) return m == 0 ? QDO_ERR_ZERO_CODE : QDO_ERR_INVALID;
   if (m > 40) return QDO_ERR_TOO_LARGE;
   int W = words_of(n);
   uint64_t *R = (uint64_t *)calloc((size_t)m * 2 * W, sizeof(uint64_t));
   if (!R) return QDO_ERR_NOMEM;
   for (int i = 0; i < m; ++i) pack_row(B + (size_t)i * 2 * n, n, R + (size_t)i * 2 * W);
+  const int nchk = filter ? filter_rows(R, m, W) : 0;
   unsigned long long total = 1ull << m;
   int nchunks = m > 16 ? 256 : 1;
   unsigned long long chunk = total / (unsigned long long)nchunks;
@@ -174,7 +203,7 @@ int qdo_brute(const uint8_t *B, int m, int n, int nthreads, int *d,
         for (int k = 0; k < 2 * W; ++k) c[k] ^= R[(size_t)r * 2 * W + k];
       }
       int w = packed_swt(c, W);
-      if (w > 0 && w < lbest) { lbest = w; lidx = i; }
+      if (w > 0 && w < lbest && admitted(c, R, nchk, W)) { lbest = w; lidx = i; }
     }
 #pragma omp critical
     {
@@ -201,6 +230,16 @@ int qdo_brute(const uint8_t *B, int m, int n, int nthreads, int *d,
   }
   free(R);
   return rc;
+}
+
+int qdo_brute(const uint8_t *B, int m, int n, int nthreads, int *d,
+              uint8_t *witness) {
+  return brute_impl(B, m, n, nthreads, 0, d, witness);
+}
+
+int qdo_brute_stab(const uint8_t *B, int m, int n, int nthreads, int *d,
+                   uint8_t *witness) {
+  return brute_impl(B, m, n, nthreads, 1, d, witness);
 }
 
 /* Hamming weight of (a, b, a+b) for every nonzero combination (Sec. 2.4). */
@@ -504,6 +543,8 @@ typedef struct {
   int P, t, W, n;
   const int *ne;        /* elements per package: 1 or 3 */
   const uint64_t *el;   /* package i element e at (i*3+e)*2W */
+  const uint64_t *chk;  /* rows for the Modified-BZ admission test (nchk 0: none) */
+  int nchk;
   int best;
   unsigned long long count;
   uint64_t bestc[8];
@@ -514,7 +555,7 @@ static void round_rec(round_ctx *c, int start, int depth, const uint64_t *cur) {
   if (depth == c->t) {
     int w = packed_swt(cur, c->W);
     ++c->count;
-    if (w < c->best) {
+    if (w < c->best && admitted(cur, c->chk, c->nchk, c->W)) {
       c->best = w;
       memcpy(c->bestc, cur, sizeof(uint64_t) * W2);
     }
@@ -549,9 +590,9 @@ static uint64_t *package_elements(const uint8_t *rows, const int *dims, int P, i
   return el;
 }
 
-int qdo_round(const uint8_t *rows, const int *dims, int P, int n, int t,
-              int nthreads, int *wmin, uint8_t *witness,
-              unsigned long long *count) {
+static int round_impl(const uint8_t *rows, const int *dims, int P, int n, int t,
+                      int nthreads, const uint64_t *chk, int nchk, int *wmin,
+                      uint8_t *witness, unsigned long long *count) {
   if (!rows || !dims || P < 0 || n <= 0 || n > 256 || t < 1 || !wmin || !count)
     return QDO_ERR_INVALID;
   int W = words_of(n);
@@ -573,6 +614,7 @@ int qdo_round(const uint8_t *rows, const int *dims, int P, int n, int t,
     if (i0 > P - t) continue;
     round_ctx c;
     c.P = P; c.t = t; c.W = W; c.n = n; c.ne = ne; c.el = el;
+    c.chk = chk; c.nchk = nchk;
     c.best = n + 1; c.count = 0;
     memset(c.bestc, 0, sizeof(c.bestc));
     uint64_t cur[8];
@@ -599,6 +641,12 @@ int qdo_round(const uint8_t *rows, const int *dims, int P, int n, int t,
   return QDO_OK;
 }
 
+int qdo_round(const uint8_t *rows, const int *dims, int P, int n, int t,
+              int nthreads, int *wmin, uint8_t *witness,
+              unsigned long long *count) {
+  return round_impl(rows, dims, P, n, t, nthreads, NULL, 0, wmin, witness, count);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Brouwer-Zimmermann (Sec. 2.1).                                           */
 /* U: smallest weight seen (starts at the sentinel n+1).                   */
@@ -608,10 +656,10 @@ int qdo_round(const uint8_t *rows, const int *dims, int P, int n, int t,
 /* set; the sets are disjoint, so L = sum_j max(0, t_j + 1 - delta_j).      */
 /* With two matrices this is the bound of Sec. 2.3 (delta_2 = n_p - n_pp). */
 
-int qdo_bz_gamma(int h, const int *P, const int *off, const int *delta,
-                 const uint8_t *rows, const int *dims, int n, int nthreads,
-                 int *d, uint8_t *witness, long long *log, int log_cap,
-                 int *nlog) {
+static int bz_gamma_impl(int h, const int *P, const int *off, const int *delta,
+                         const uint8_t *rows, const int *dims, int n, int nthreads,
+                         const uint64_t *chk, int nchk, int *d, uint8_t *witness,
+                         long long *log, int log_cap, int *nlog) {
   if (h <= 0 || !P || !off || !delta || !rows || !dims || n <= 0 || !d)
     return QDO_ERR_INVALID;
   int len = 2 * n;
@@ -628,8 +676,8 @@ int qdo_bz_gamma(int h, const int *P, const int *off, const int *delta,
       any = 1;
       int w;
       unsigned long long cnt;
-      int rc = qdo_round(rows + (size_t)off[j] * 2 * len, dims + off[j], P[j], n, t,
-                         nthreads, &w, cand, &cnt);
+      int rc = round_impl(rows + (size_t)off[j] * 2 * len, dims + off[j], P[j], n, t,
+                          nthreads, chk, nchk, &w, cand, &cnt);
       if (rc) { free(wit); free(cand); free(tdone); return rc; }
       if (w < U) {
         U = w;
@@ -657,9 +705,17 @@ int qdo_bz_gamma(int h, const int *P, const int *off, const int *delta,
   return U <= n ? QDO_OK : QDO_ERR_ZERO_CODE;
 }
 
-int qdo_bz(const uint8_t *B, int m, int n, int diag, int max_gamma,
-           int nthreads, int *d, uint8_t *witness, long long *log,
-           int log_cap, int *nlog) {
+int qdo_bz_gamma(int h, const int *P, const int *off, const int *delta,
+                 const uint8_t *rows, const int *dims, int n, int nthreads,
+                 int *d, uint8_t *witness, long long *log, int log_cap,
+                 int *nlog) {
+  return bz_gamma_impl(h, P, off, delta, rows, dims, n, nthreads, NULL, 0, d, witness,
+                       log, log_cap, nlog);
+}
+
+static int bz_impl(const uint8_t *B, int m, int n, int diag, int max_gamma,
+                   int nthreads, int filter, int *d, uint8_t *witness, long long *log,
+                   int log_cap, int *nlog) {
   if (!B || m <= 0 || n <= 0 || !d) return m == 0 ? QDO_ERR_ZERO_CODE : QDO_ERR_INVALID;
   int cap = 2 * n;
   int G = max_gamma > 0 ? max_gamma : 1;
@@ -670,16 +726,35 @@ int qdo_bz(const uint8_t *B, int m, int n, int diag, int max_gamma,
   int *piv = (int *)calloc((size_t)G * cap, sizeof(int));
   uint8_t *rows = (uint8_t *)calloc((size_t)G * cap * 2 * 2 * n, 1);
   int h = 0;
-  int rc = qdo_gamma(B, m, n, diag, G, cap, &h, P, delta, dims, piv, rows);
+  int W = words_of(n);
+  uint64_t *chk = (uint64_t *)calloc((size_t)m * 2 * W + 1, sizeof(uint64_t));
+  int nchk = 0;
+  if (chk && filter) {
+    for (int i = 0; i < m; ++i) pack_row(B + (size_t)i * 2 * n, n, chk + (size_t)i * 2 * W);
+    nchk = filter_rows(chk, m, W);
+  }
+  int rc = chk ? qdo_gamma(B, m, n, diag, G, cap, &h, P, delta, dims, piv, rows) : QDO_ERR_NOMEM;
   if (rc >= 0) {
     for (int j = 0; j < h; ++j) off[j] = j * cap;
-    rc = qdo_bz_gamma(h, P, off, delta, rows, dims, n, nthreads, d, witness, log,
-                      log_cap, nlog);
+    rc = bz_gamma_impl(h, P, off, delta, rows, dims, n, nthreads, chk, nchk, d, witness,
+                       log, log_cap, nlog);
   } else {
     *d = -1;
   }
-  free(P); free(off); free(delta); free(dims); free(piv); free(rows);
+  free(P); free(off); free(delta); free(dims); free(piv); free(rows); free(chk);
   return rc;
+}
+
+int qdo_bz(const uint8_t *B, int m, int n, int diag, int max_gamma,
+           int nthreads, int *d, uint8_t *witness, long long *log,
+           int log_cap, int *nlog) {
+  return bz_impl(B, m, n, diag, max_gamma, nthreads, 0, d, witness, log, log_cap, nlog);
+}
+
+int qdo_bz_stab(const uint8_t *B, int m, int n, int diag, int max_gamma,
+                int nthreads, int *d, uint8_t *witness, long long *log,
+                int log_cap, int *nlog) {
+  return bz_impl(B, m, n, diag, max_gamma, nthreads, 1, d, witness, log, log_cap, nlog);
 }
 
 /* ------------------------------------------------------------------------ */

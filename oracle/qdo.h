@@ -98,6 +98,19 @@ int qdo_bz(const uint8_t *B, int m, int n, int diag, int max_gamma,
            int nthreads, int *d, uint8_t *witness, long long *log,
            int log_cap, int *nlog);
 
+/* Modified Brouwer-Zimmermann for a quantum stabilizer code (Sec. 2.1):
+ * the rows of B generate the normalizer N = C^{perp_s}; the distance is the
+ * least symplectic weight over N \ C, where the stabilizer C = N^{perp_s}
+ * holds the codewords whose symplectic product with every row is 0.  When
+ * N is self-orthogonal (k = 0) every nonzero codeword counts, as the paper
+ * prescribes.  Same outputs as qdo_brute / qdo_bz; QDO_ERR_ZERO_CODE when no
+ * codeword is admitted. */
+int qdo_brute_stab(const uint8_t *B, int m, int n, int nthreads, int *d,
+                   uint8_t *witness);
+int qdo_bz_stab(const uint8_t *B, int m, int n, int diag, int max_gamma,
+                int nthreads, int *d, uint8_t *witness, long long *log,
+                int log_cap, int *nlog);
+
 /* Saved_isometry (Sec. 2.4).  The image of each basis row (a|b) is
  * (a, b, a+b): a binary linear code of length 3n whose Hamming weights are
  * twice the symplectic weights.  Gamma_j is the reduced row echelon form of

@@ -147,3 +147,69 @@ def tiny_code(seed, n_max=7, m_max=None):
     m_hi = m_max if m_max is not None else 2 * n + 1
     m = rng.uniform_int(1, m_hi)
     return additive(n, m, rng.next())
+
+
+def random_stabilizer(n, k, seed):
+    """Normalizer matrix (n + k) x 2n of a random [[n, k]] stabilizer code.
+
+    The canonical code with stabilizer Z_1..Z_{n-k} has the normalizer rows
+    Z_1..Z_n and X_{n-k+1}..X_n; every row is mapped by the same product of
+    4n symplectic transvections x -> x + <x, v>_s v with random nonzero v,
+    which preserves symplectic products, so the image is the normalizer of
+    a random stabilizer code.  Rows: n - k stabilizer generators first, then
+    the 2k logical operators."""
+    if not 0 <= k <= n:
+        raise ValueError("need 0 <= k <= n")
+    rng = SplitMix64(seed)
+    A = np.zeros((n + k, 2 * n), dtype=np.uint8)
+    for i in range(n):
+        A[i, n + i] = 1  # Z_{i+1}
+    for j in range(k):
+        A[n + j, n - k + j] = 1  # X_{n-k+1+j}
+    order = list(range(n - k)) + list(range(n - k, n)) + list(range(n, n + k))
+    A = A[order]
+    for _ in range(4 * n):
+        v = rng.bits(2 * n)
+        if not v.any():
+            continue
+        # <a, v>_s = a_x . v_z + a_z . v_x (mod 2), for every row at once
+        prod = ((A[:, :n].astype(np.int64) @ v[n:].astype(np.int64)) +
+                (A[:, n:].astype(np.int64) @ v[:n].astype(np.int64))) & 1
+        A ^= (prod[:, None].astype(np.uint8) & v[None, :])
+    return A
+
+
+def textbook_code(name):
+    """Normalizer matrices of textbook stabilizer codes, from their Pauli
+    strings (stabilizer generators, then logical operators)."""
+    paulis = {
+        # five-qubit code: cyclic shifts of XZZXI; logicals X^5, Z^5
+        "[[5,1,3]]": ["XZZXI", "IXZZX", "XIXZZ", "ZXIXZ", "XXXXX", "ZZZZZ"],
+        # Shor's nine-qubit code (degenerate: weight-2 stabilizers)
+        "[[9,1,3]]": ["ZZIIIIIII", "IZZIIIIII", "IIIZZIIII", "IIIIZZIII", "IIIIIIZZI", "IIIIIIIZZ",
+                      "XXXXXXIII", "IIIXXXXXX", "ZZZZZZZZZ", "XXXXXXXXX"],
+        # Steane's seven-qubit code; logicals X^7, Z^7
+        "[[7,1,3]]": ["IIIXXXX", "IXXIIXX", "XIXIXIX", "IIIZZZZ", "IZZIIZZ", "ZIZIZIZ", "XXXXXXX", "ZZZZZZZ"],
+        # four-qubit error-detecting code; logicals XXII, XIXI, ZZII... one choice
+        "[[4,2,2]]": ["XXXX", "ZZZZ", "XXII", "ZIZI", "XIXI", "ZZII"],
+        # a k = 0 code (self-dual): the three-qubit GHZ state
+        "[[3,0,2]]": ["XXX", "ZZI", "IZZ"],
+    }[name]
+    n = len(paulis[0])
+    A = np.zeros((len(paulis), 2 * n), dtype=np.uint8)
+    for i, p in enumerate(paulis):
+        for q, ch in enumerate(p):
+            A[i, q] = ch in "XY"
+            A[i, n + q] = ch in "ZY"
+    return A
+
+
+def config_stab(index=0):
+    """Random stabilizer codes shaped like the paper's larger data sets:
+    n ~ U{32..64}, K/N = (n + k) / 2n ~ U[0.586, 0.758] (so K x N <= 12,416
+    elements), normalizer matrix as input, field 2."""
+    rng = SplitMix64(config_seed(6, index))
+    n = rng.uniform_int(32, 64)
+    ratio = 0.586 + (0.758 - 0.586) * rng.uniform01()
+    k = max(1, min(n - 1, int(round((2 * ratio - 1) * n))))
+    return random_stabilizer(n, k, rng.next()), 2

@@ -41,6 +41,13 @@ MUTANTS = {
     "iso_echelon_not_reduced": ("        if (i != p && R[(size_t)i * len + c]) row_add(R + (size_t)i * len, R + (size_t)p * len, len);",
                                 "        if (i > p && R[(size_t)i * len + c]) row_add(R + (size_t)i * len, R + (size_t)p * len, len);"),
     "iso_sets_not_disjoint": ("      if (piv[i] >= 0) used[piv[i]] = 1;", "      (void)used;"),
+    "stab_test_inverted": ("    if (sym_product(c, chk + (size_t)r * 2 * W, W)) return 1;",
+                           "    if (!sym_product(c, chk + (size_t)r * 2 * W, W)) return 1;"),
+    "stab_product_missing_term": ("p ^= __builtin_parityll((a[i] & b[W + i]) ^ (a[W + i] & b[i]));",
+                                  "p ^= __builtin_parityll(a[i] & b[W + i]);"),
+    "stab_no_k0_rule": ("      if (sym_product(R + (size_t)i * 2 * W, R + (size_t)j * 2 * W, W)) return m;\n  return 0;",
+                        "      if (sym_product(R + (size_t)i * 2 * W, R + (size_t)j * 2 * W, W)) return m;\n  return m;"),
+    "stab_round_unfiltered": ("    if (w < c->best && admitted(cur, c->chk, c->nchk, c->W)) {", "    if (w < c->best) {"),
     "iso_round_skips_last_row": ("  for (int i = start; i <= c->m - (c->t - depth); ++i) {",
                                  "  for (int i = start; i < c->m - (c->t - depth); ++i) {"),
 }
@@ -92,6 +99,17 @@ def quick_pins():
             B = O.expand(*W.config1(s))
             _, _, log = O.bz_iso(B, 8)
             if max(t for t, *_ in log) < 2 or any(cnt != math.comb(20, t) for t, j, L, U, cnt in log):
+                return False
+        for name, dref in (("[[9,1,3]]", 3), ("[[5,1,3]]", 3), ("[[3,0,2]]", 2), ("[[4,2,2]]", 2)):
+            A = W.textbook_code(name)
+            if O.brute_stab(A)[0] != dref or O.bz_stab(A, O.DIAG_F4)[0] != dref:
+                return False
+        for s in range(40):
+            rng = W.SplitMix64(W.config_seed(19, s))
+            n = rng.uniform_int(2, 8)
+            k = rng.uniform_int(0, n)
+            A = W.random_stabilizer(n, k, rng.next())
+            if O.bz_stab(A, O.DIAG_F4, 8)[0] != O.brute_stab(A)[0]:
                 return False
         rows, dims = W.random_packages(6, 20, W.config_seed(15, 0), 0.5)
         sizes = [3 if d == 2 else 1 for d in dims]
