@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--batch-codes", type=int, default=512)
     ap.add_argument("--batch-max-work", type=float, default=1e11)
     ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--stab-codes", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=0.0, help="requests/s (0: 60%% of measured capacity)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 3 device copies of 1 GiB (reference for HBM byte counters)")
@@ -181,6 +182,49 @@ def leg_constructions(Q, W):
             res[label] = {"mean_ms": sum(ms) / len(ms), "codewords": comb, "d": ds}
         out[name] = res
     return out
+
+
+def leg_stabilizer(Q, W, a):
+    """Quantum stabilizer codes shaped like the paper's larger data set
+    (normalizer matrices, n 32..64, K/N 0.586..0.758), distance with the
+    Modified-BZ filter: a batch of the first draws whose predicted work is
+    at most --batch-max-work, and each construction timed alone on the
+    first four of them."""
+    codes, drawn, i = [], 0, 0
+    while len(codes) < a.stab_codes and drawn < 20 * a.stab_codes:
+        A, f = W.config_stab(i)
+        i += 1
+        drawn += 1
+        if Q.qd_plan(A, f)["predicted_" + {2: "f2", 3: "iso", 4: "f4"}[Q.qd_plan(A, f)["diag"]]] <= a.batch_max_work:
+            codes.append((A, f))
+    flt = Q.QD_FILTER_STABILIZER
+    t0 = time.perf_counter()
+    st, ds, _, sts, stats = Q.qd_distance_batch(codes, filter=flt, budget=int(a.batch_max_work * 4))
+    t_batch = time.perf_counter() - t0
+    comb = sum(s.combinations for s in stats)
+    diags = {}
+    for s in stats:
+        diags[{2: "F2", 3: "isometry", 4: "F4"}[s.diag]] = diags.get({2: "F2", 3: "isometry", 4: "F4"}[s.diag], 0) + 1
+    per = {}
+    for label, diag in (("F2", Q.QD_DIAG_F2), ("F4", Q.QD_DIAG_F4), ("isometry", Q.QD_DIAG_ISO)):
+        ms, skip = [], False
+        for A, f in codes[:4]:
+            p = Q.qd_plan(A, f, diag)
+            if p["predicted_" + {2: "f2", 3: "iso", 4: "f4"}[diag]] > 1e12:
+                skip = True
+                break
+            Q.qd_distance_ex(A, f, diag=diag, filter=flt)
+            t1 = time.perf_counter()
+            Q.qd_distance_ex(A, f, diag=diag, filter=flt)
+            ms.append((time.perf_counter() - t1) * 1e3)
+        per[label] = "skipped (planned work > 1e12)" if skip else {"mean_ms": sum(ms) / len(ms)}
+    ns = [A.shape[1] // 2 for A, _ in codes]
+    ks = [A.shape[0] - A.shape[1] // 2 for A, _ in codes]
+    return {"workload": f"{len(codes)} of {drawn} random [[n,k]] stabilizer codes, n {min(ns)}..{max(ns)}, "
+                        f"k {min(ks)}..{max(ks)}, predicted work <= {a.batch_max_work:.0e}",
+            "exact": sum(1 for x in sts if x == 0), "d_range": [min(ds), max(ds)],
+            "batched_s": t_batch, "codewords_per_s": comb / t_batch, "constructions_chosen": diags,
+            "first4_time_to_exact_d": per}
 
 
 def leg_latency(Q, W):
@@ -337,6 +381,7 @@ def main():
         out["serving"] = leg_serving(Q, W, a)
         out["latency"] = leg_latency(Q, W)
         out["constructions"] = leg_constructions(Q, W)
+        out["stabilizer"] = leg_stabilizer(Q, W, a)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(G, field, a.cpu_seconds)
     print(json.dumps(out), flush=True)

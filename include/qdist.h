@@ -52,6 +52,13 @@ extern "C" {
 #define QD_DIAG_ISO 3 /* Saved_isometry (Sec. 2.4): binary information sets of the
                          image (x, z, x^z), bound on Hamming weight, d = d_H / 2 */
 
+#define QD_FILTER_NONE 0       /* minimum over the whole span */
+#define QD_FILTER_STABILIZER 1 /* Modified BZ (Sec. 2.1): the rows generate a normalizer
+                                  N = C^{perp_s}; U takes only codewords of N outside the
+                                  stabilizer C = N^{perp_s} (the radical of the span), so d is
+                                  the quantum code's distance.  A self-orthogonal span (k = 0)
+                                  counts every codeword, as the paper prescribes. */
+
 #define QD_OK 0
 #define QD_INCOMPLETE 1 /* budget or cancel: *d = U, stats hold L <= d <= U */
 #define QD_ERR_INVALID (-1)
@@ -80,6 +87,7 @@ typedef struct qd_options {
   int timing;                 /* 1: time every enumeration launch with HIP events */
   int tops_mode;              /* tuning override: 0 auto, 1 tops from a table,
                                  2 tops unranked by each lane */
+  int filter;                 /* QD_FILTER_NONE or QD_FILTER_STABILIZER */
 } qd_options;
 
 /* One (t, Gamma_j) round of the enumeration. */
@@ -109,6 +117,8 @@ typedef struct qd_stats {
   double wall_ms;             /* whole call */
   int launches;               /* enumeration-kernel launches that carried its rounds
                                  (one launch may carry several consecutive rounds) */
+  int logical_pairs;          /* QD_FILTER_STABILIZER: k, the logical operator pairs
+                                 the admission test uses (0: no filter applied) */
   int nlog;                   /* rounds run (entries in log, capped at QD_MAX_LOG) */
   qd_round_log log[QD_MAX_LOG];
 } qd_stats;

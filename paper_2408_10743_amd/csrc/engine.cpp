@@ -280,7 +280,7 @@ void Executor::prepare(Job &job) {
     return;
   }
   if (o.seg_len < 0 || o.seg_len % kBlock || o.saved_depth < -1 || o.max_gamma < 0 || o.tops_mode < 0 ||
-      o.tops_mode > 2) {
+      o.tops_mode > 2 || (o.filter != QD_FILTER_NONE && o.filter != QD_FILTER_STABILIZER)) {
     job.status = QD_ERR_INVALID;
     return;
   }
@@ -289,6 +289,9 @@ void Executor::prepare(Job &job) {
   const int n = job.n;
   job.rank = make_basis(job.basis, n);
   if (job.rank == 0) { job.status = QD_ERR_ZERO_CODE; return; }
+  // Modified BZ: with no logical pair the span is self-orthogonal (k = 0)
+  // and every codeword counts.
+  if (o.filter == QD_FILTER_STABILIZER) logical_pairs(job.basis, job.logicals);
   if (job.use.empty()) {
     std::vector<Gamma> f4 = build_f4(job.basis, n, kMaxGamma);
     Gamma f2 = build_f2(job.basis, n);
@@ -321,6 +324,7 @@ void Executor::prepare_gammas(Job &job) {
   job.D = (n + 31) / 32;
   job.S.n = n; job.S.rank = job.rank; job.S.D = job.D; job.S.diag = job.pc.diag; job.S.h = h;
   job.S.d_estimate = job.pc.d_est; job.S.predicted = job.pc.predicted;
+  job.S.logical_pairs = int(job.logicals.size() / 2);
   job.tdone.assign(h, 0);
   job.delta.resize(h);
   for (int j = 0; j < h; ++j) {
@@ -390,7 +394,8 @@ int Executor::admit(Job &job, hipStream_t s) {
   // aligned as Staging::put places them | per Gamma_j prefix and suffix
   // tables, which the device computes from the sizes.
   const size_t cb = size_t(kCountersPerCode) * kCounterStride * 8;
-  size_t a_bytes = 0, total = cb;
+  const size_t lbytes = job.logicals.size() * kElemWords * 4;
+  size_t a_bytes = lbytes, total = cb + lbytes;
   for (const GammaDev &g : job.gd) {
     if (g.R > kWave || g.P > kMaxEsymPackages) return QD_ERR_INTERNAL;
     a_bytes += align16(g.h_elems.size() * 4) + align16(g.h_csize.size());
@@ -401,6 +406,13 @@ int Executor::admit(Job &job, hipStream_t s) {
   recs_.push_back({dev, kZeroFill, cb, 0, 0, 0});
   const size_t o0 = align16(staging_.size());
   unsigned char *a0 = dev + cb, *b = dev + cb + a_bytes;
+  if (lbytes) {
+    std::vector<uint32_t> lw(job.logicals.size() * kElemWords);
+    for (size_t i = 0; i < job.logicals.size(); ++i) to_words(job.logicals[i], &lw[i * kElemWords]);
+    const size_t ol = staging_.put(lw.data(), lbytes);
+    if (ol == SIZE_MAX) return QD_ERR_NOMEM;
+    job.dlogicals = reinterpret_cast<const uint32_t *>(a0 + (ol - o0));
+  }
   for (GammaDev &g : job.gd) {
     const size_t oe = staging_.put(g.h_elems.data(), g.h_elems.size() * 4);
     const size_t oc = staging_.put(g.h_csize.data(), g.h_csize.size());
@@ -658,6 +670,8 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         d.csize = g.csize;
         d.state = states_ + job.state_slot;
         d.counters = static_cast<unsigned long long *>(job.data.p);
+        d.logicals = job.dlogicals;
+        d.nlogicals = int(job.logicals.size());
         d.tile_begin = L.tiles;
         d.ntiles = take;
         d.tile_lo = f.sent;
@@ -773,7 +787,12 @@ void Executor::retire(Job &job) {
     S.U = job.U;
     S.combinations = job.visited;
     // The witness must have weight U and lie in the row space.
-    const bool wit_ok = job.U <= job.n && rweight(job.wit) == job.U && in_span(job.basis, job.n, job.wit);
+    bool wit_ok = job.U <= job.n && rweight(job.wit) == job.U && in_span(job.basis, job.n, job.wit);
+    if (!job.logicals.empty()) {  // Modified BZ: the witness is no stabilizer
+      bool outside = false;
+      for (const BRow &l : job.logicals) outside = outside || sym_product(job.wit, l);
+      wit_ok = wit_ok && outside;
+    }
     if (job.single_round) {
       // U is the round minimum (n + 1 if the round is empty), not a distance
     } else if (job.incomplete) {
@@ -785,6 +804,7 @@ void Executor::retire(Job &job) {
   }
   for (GammaDev &g : job.gd) {
     g.elems = nullptr; g.csize = nullptr; g.dprefix = g.dsuffix = nullptr;
+    job.dlogicals = nullptr;
     for (int u = 0; u <= kTMax; ++u) { release(g.table[u]); release(g.tops[u]); }
   }
   release(job.data);

@@ -105,6 +105,8 @@ struct Job {
   std::vector<Gamma> use;
   PlanChoice pc;
   bool halve = false;  // isometry matrices: bounds count Hamming weight
+  std::vector<BRow> logicals;  // Modified BZ: the admission test's operators
+  const uint32_t *dlogicals = nullptr;
   std::vector<GammaDev> gd;
   int state_slot = -1;
   PoolBuf data;  // visited counters, then every Gamma_j's elements and tables

@@ -257,6 +257,35 @@ bool check_gamma(const Gamma &g, int n) {
   return true;
 }
 
+int sym_product(const BRow &a, const BRow &b) {
+  uint64_t v = 0;
+  for (int i = 0; i < 2; ++i) v ^= (a.x[i] & b.z[i]) ^ (a.z[i] & b.x[i]);
+  return __builtin_parityll(v);
+}
+
+int logical_pairs(const std::vector<BRow> &basis, std::vector<BRow> &out) {
+  out.clear();
+  std::vector<BRow> rem = basis;
+  size_t head = 0;
+  while (head < rem.size()) {
+    const BRow a = rem[head++];
+    size_t j = head;
+    while (j < rem.size() && !sym_product(a, rem[j])) ++j;
+    if (j == rem.size()) continue;  // a commutes with the whole span: radical
+    const BRow b = rem[j];
+    rem.erase(rem.begin() + long(j));
+    // r + <r, b> a + <r, a> b commutes with both a and b.
+    for (size_t i = head; i < rem.size(); ++i) {
+      const int pa = sym_product(rem[i], a), pb = sym_product(rem[i], b);
+      if (pb) radd(rem[i], a);
+      if (pa) radd(rem[i], b);
+    }
+    out.push_back(a);
+    out.push_back(b);
+  }
+  return int(out.size() / 2);
+}
+
 int iso_bit(const BRow &r, int c, int n) {
   if (c < 2 * n) return rbit(r, c, n);
   return rbit(r, c - 2 * n, n) ^ rbit(r, c - n, n);

@@ -74,6 +74,16 @@ bool check_gamma_iso(const Gamma &g, int n);
 // Bit of image column c (0 <= c < 3n) of a row.
 int iso_bit(const BRow &r, int c, int n);
 
+// Symplectic product <a, b>_s = a_x . b_z + a_z . b_x (mod 2).
+int sym_product(const BRow &a, const BRow &b);
+
+// Logical operator pairs of the span of `basis`: rows a_1, b_1, ..., a_k,
+// b_k with <a_i, b_i>_s = 1 and every other product 0, spanning a
+// complement of the span's radical (the stabilizer, for a normalizer).  A
+// codeword of the span lies in the radical exactly when its product with
+// every one of them is 0.  Returns k.
+int logical_pairs(const std::vector<BRow> &basis, std::vector<BRow> &out);
+
 // Elementary symmetric polynomials e_r of package sizes (1 or 3) as
 // saturating 64-bit integers.  prefix[h][r] = e_r(c_0..c_{h-1}),
 // suffix[h][r] = e_r(c_h..c_{P-1}); rmax columns + 1.

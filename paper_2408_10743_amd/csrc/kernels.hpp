@@ -68,6 +68,8 @@ struct RoundDesc {
   const unsigned char *csize;          // elements per package (1 or 3)
   DevState *state;
   unsigned long long *counters;        // kCountersPerCode x kCounterStride
+  const uint32_t *logicals;            // Modified BZ: logical operators, kElemWords each
+  int nlogicals;                       // 0: every codeword may update U
   unsigned long long tile_begin;       // first launch tile of the piece
   unsigned long long ntiles;           // tiles of the piece
   unsigned long long tile_lo;          // round tile of the piece's first tile

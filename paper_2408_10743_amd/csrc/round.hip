@@ -118,6 +118,20 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
+// Modified BZ: a codeword of the span is outside its radical (the
+// stabilizer) when its symplectic product with some logical operator is 1.
+template <int D>
+__device__ bool admitted(const uint32_t (&cx)[D], const uint32_t (&cz)[D], const uint32_t *L, int nL) {
+  for (int i = 0; i < nL; ++i) {
+    const uint32_t *l = L + static_cast<size_t>(i) * kElemWords;
+    uint32_t v = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) v ^= (cx[d] & l[4 + d]) ^ (cz[d] & l[d]);
+    if (__builtin_popcount(v) & 1) return true;
+  }
+  return false;
+}
+
 // One tile = one table segment [k0, k0 + seg) x 64 tops.  The tops of a
 // tile come from every group whose table prefix reaches the segment, so
 // lanes stay full; a lane stops at its own group's prefix length.  A launch
@@ -242,6 +256,48 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
               static_cast<unsigned long long>(visited));
 
   key = uniform64(*reinterpret_cast<volatile unsigned long long *>(&st->key));
+  if (p.nlogicals > 0) {
+    // Modified BZ: the tile's minimum may be a stabilizer element, which
+    // must not update U.  Rare path: look for the least admitted weight
+    // below U in this tile, then publish it as below.
+    const uint32_t thr = static_cast<uint32_t>(key >> 32);
+    if (wmin >= thr) return;
+    uint32_t be = 0xFFFFFFFFu, kf = 0xFFFFFFFFu;
+    for (uint32_t i = 0; i < send; ++i) {
+      const uint32_t w = weight_at<D>(p.table, k0 + i, ax, az);
+      if (active && i < span && w < thr && w < be) {
+        const unsigned long long kk = k0 + i;
+        const uint32_t *e = p.table + (kk / kBlock) * (2 * D * kBlock) + (kk % kBlock);
+        uint32_t cx[D], cz[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          cx[d] = ax[d] ^ e[d * kBlock];
+          cz[d] = az[d] ^ e[(D + d) * kBlock];
+        }
+        if (admitted<D>(cx, cz, p.logicals, p.nlogicals)) {
+          be = w;
+          kf = i;
+        }
+      }
+    }
+    const uint32_t wadm = wave_min(be);
+    if (wadm >= thr) return;
+    const unsigned long long mask = __ballot(be == wadm);
+    const int winner = __ffsll(static_cast<long long>(mask)) - 1;
+    if (static_cast<int>(lane) == winner) {
+      const uint32_t slot = static_cast<uint32_t>(p.slot0 + local);
+      uint32_t *out = lp.slots + static_cast<size_t>(slot) * kElemWords;
+      const unsigned long long kk = k0 + kf;
+      const uint32_t *e = p.table + (kk / kBlock) * (2 * D * kBlock) + (kk % kBlock);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        out[d] = d < D ? (ax[d] ^ e[d * kBlock]) : 0u;
+        out[4 + d] = d < D ? (az[d] ^ e[(D + d) * kBlock]) : 0u;
+      }
+      atomicMin(&st->key, (static_cast<unsigned long long>(wadm) << 32) | slot);
+    }
+    return;
+  }
   if (wmin < static_cast<uint32_t>(key >> 32)) {
     // Rare: this tile improves U.  Find where, write the codeword to this
     // tile's own slot, then publish (U, slot) with one 64-bit atomicMin.

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libqdist.so")
 
 QD_FIELD_F2, QD_FIELD_F4 = 2, 4
 QD_DIAG_AUTO, QD_DIAG_F2, QD_DIAG_F4, QD_DIAG_ISO = 0, 2, 4, 3
+QD_FILTER_NONE, QD_FILTER_STABILIZER = 0, 1
 QD_OK, QD_INCOMPLETE = 0, 1
 QD_ERR_INVALID, QD_ERR_ZERO_CODE, QD_ERR_TOO_LARGE = -1, -2, -3
 QD_ERR_NOMEM, QD_ERR_DEVICE, QD_ERR_INTERNAL = -4, -5, -6
@@ -37,7 +38,8 @@ class qd_options(ctypes.Structure):
     _fields_ = [("diag", ctypes.c_int), ("max_gamma", ctypes.c_int),
                 ("budget", ctypes.c_ulonglong), ("cancel", ctypes.POINTER(ctypes.c_int)),
                 ("stream", ctypes.c_void_p), ("seg_len", ctypes.c_int),
-                ("saved_depth", ctypes.c_int), ("timing", ctypes.c_int), ("tops_mode", ctypes.c_int)]
+                ("saved_depth", ctypes.c_int), ("timing", ctypes.c_int), ("tops_mode", ctypes.c_int),
+                ("filter", ctypes.c_int)]
 
 
 class qd_round_log(ctypes.Structure):
@@ -54,7 +56,7 @@ class qd_stats(ctypes.Structure):
                 ("d_estimate", ctypes.c_int), ("predicted", ctypes.c_double),
                 ("combinations", ctypes.c_ulonglong), ("host_ms", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
-                ("launches", ctypes.c_int), ("nlog", ctypes.c_int),
+                ("launches", ctypes.c_int), ("logical_pairs", ctypes.c_int), ("nlog", ctypes.c_int),
                 ("log", qd_round_log * QD_MAX_LOG)]
 
     def rounds(self):

@@ -266,3 +266,76 @@ def test_isometry_batch_and_mix(Q):
     assert st == 0 and all(x == 0 for x in sts)
     for (G, f), d in zip(codes, ds):
         assert d == Q.qd_distance_ex(G, f, diag=Q.QD_DIAG_F4)[1]
+
+
+def _stab_check(Q, A, d_ref, **opts):
+    st, d, wit, s = Q.qd_distance_ex(A, 2, filter=Q.QD_FILTER_STABILIZER, **opts)
+    assert st == 0, Q.qd_strerror(st)
+    assert d == d_ref
+    assert swt(wit) == d and O.in_rowspace(A, wit)
+    n = A.shape[1] // 2
+    if s.logical_pairs:
+        prods = (A[:, :n].astype(int) @ wit[n:].astype(int) + A[:, n:].astype(int) @ wit[:n].astype(int)) % 2
+        assert prods.any()  # the witness is no stabilizer
+    return s
+
+
+def test_stabilizer_filter_textbook(Q):
+    ref = {"[[5,1,3]]": 3, "[[9,1,3]]": 3, "[[7,1,3]]": 3, "[[4,2,2]]": 2, "[[3,0,2]]": 2}
+    for name, d in ref.items():
+        A = W.textbook_code(name)
+        for diag in (Q.QD_DIAG_F2, Q.QD_DIAG_F4):
+            s = _stab_check(Q, A, d, diag=diag)
+            assert s.logical_pairs == (A.shape[0] - A.shape[1] // 2 if name != "[[3,0,2]]" else 0)
+    # the filter matters: without it Shor's code gives its weight-2 stabilizers
+    assert Q.qd_distance(W.textbook_code("[[9,1,3]]"), 2)[1] == 2
+
+
+def test_stabilizer_filter_random_codes(Q):
+    for s in range(60):
+        rng = W.SplitMix64(W.config_seed(21, s))
+        n = rng.uniform_int(3, 14)
+        k = rng.uniform_int(0, n)
+        A = W.random_stabilizer(n, k, rng.next())
+        d_ref = O.brute_stab(A)[0]
+        print(f"stab n={n} k={k} d={d_ref}", flush=True)
+        _stab_check(Q, A, d_ref)
+    for s in range(12):
+        rng = W.SplitMix64(W.config_seed(22, s))
+        n = rng.uniform_int(16, 40)
+        k = rng.uniform_int(1, n // 2)
+        A = W.random_stabilizer(n, k, rng.next())
+        d_ref = O.bz_stab(A, O.DIAG_F4, 8)[0]
+        print(f"stab n={n} k={k} d={d_ref}", flush=True)
+        _stab_check(Q, A, d_ref)
+    # a generic span: the filter removes its radical
+    for s in range(20):
+        G = W.additive(12, 14, W.config_seed(23, s))
+        _stab_check(Q, G, O.brute_stab(G)[0])
+
+
+def test_stabilizer_filter_wide_code(Q):
+    """D = 4: Shor's code on 9 of 100 qubits, single-qubit Z stabilizers on
+    the others, qubits permuted.  d = 3; without the filter d = 1."""
+    n = 100
+    S = W.textbook_code("[[9,1,3]]")
+    A = np.zeros((10 + 91, 2 * n), np.uint8)
+    A[:10, :9] = S[:, :9]
+    A[:10, n:n + 9] = S[:, 9:]
+    for q in range(9, n):
+        A[10 + q - 9, n + q] = 1
+    rng = W.SplitMix64(W.config_seed(24, 0))
+    perm = np.array(sorted(range(n), key=lambda q: rng.next()))
+    A = np.concatenate([A[:, perm], A[:, n + perm]], axis=1)
+    s = _stab_check(Q, A, 3)
+    assert s.D == 4 and s.logical_pairs == 1
+    assert Q.qd_distance(A, 2)[1] == 1
+
+
+def test_stabilizer_filter_batch(Q):
+    codes = [(W.random_stabilizer(10, 2, W.config_seed(25, i)), 2) for i in range(8)]
+    codes.append((W.textbook_code("[[9,1,3]]"), 2))
+    st, ds, wits, sts, stats = Q.qd_distance_batch(codes, filter=Q.QD_FILTER_STABILIZER)
+    assert st == 0 and all(x == 0 for x in sts)
+    for (A, f), d in zip(codes, ds):
+        assert d == O.brute_stab(A)[0]

@@ -153,3 +153,12 @@ def test_iso_planner_prefers_cheaper_construction(Q):
     for G, f in [W.config1(0), W.config2(0), W.config3(0)]:
         p = Q.qd_plan(G, f)
         assert p["diag"] == Q.QD_DIAG_F4 and p["predicted_f4"] <= p["predicted_iso"]
+
+
+def test_filter_option_validation(Q):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    # an unknown filter is rejected before any device work
+    st, d, _, _ = Q.qd_distance_ex(W.textbook_code("[[5,1,3]]"), 2, filter=7)
+    assert st == Q.QD_ERR_INVALID and d == -1
