@@ -88,6 +88,9 @@ typedef struct qd_options {
   int tops_mode;              /* tuning override: 0 auto, 1 tops from a table,
                                  2 tops unranked by each lane */
   int filter;                 /* QD_FILTER_NONE or QD_FILTER_STABILIZER */
+  int scalar_classes;         /* F4-linear input (QD_FIELD_F4) with the F4 construction:
+                                 0 enumerate one codeword of each class {c, alpha c,
+                                 alpha^2 c} (equal weights, a third of the work); -1 all */
 } qd_options;
 
 /* One (t, Gamma_j) round of the enumeration. */
@@ -119,6 +122,7 @@ typedef struct qd_stats {
                                  (one launch may carry several consecutive rounds) */
   int logical_pairs;          /* QD_FILTER_STABILIZER: k, the logical operator pairs
                                  the admission test uses (0: no filter applied) */
+  int scalar_classes;         /* 1: one codeword per F4 scalar class was enumerated */
   int nlog;                   /* rounds run (entries in log, capped at QD_MAX_LOG) */
   qd_round_log log[QD_MAX_LOG];
 } qd_stats;

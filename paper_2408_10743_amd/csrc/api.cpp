@@ -184,7 +184,7 @@ int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma, 
   std::vector<Gamma> iso = build_iso(rows, n, hmax);
   for (const Gamma &g : iso)
     if (!check_gamma_iso(g, n)) return QD_ERR_INTERNAL;
-  PlanChoice pc = choose_plan(f4, f2, iso, n, k, diag, max_gamma);
+  PlanChoice pc = choose_plan(f4, f2, iso, n, k, diag, max_gamma, field == QD_FIELD_F4);
   out->n = n;
   out->rank = k;
   out->d_estimate = pc.d_est;

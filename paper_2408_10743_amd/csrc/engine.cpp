@@ -92,13 +92,16 @@ unsigned choose_seg(unsigned long long planned, int sharing) {
 // (c_h * e_{t-u-1}(c_{h+1}..)) with the first e_u(c_0..c_{h-1}) table
 // entries.  Segment s of the table is shared by every group reaching it,
 // so its tiles take 64 tops at a time from those groups together.
-unsigned long long plan_round(const GammaDev &g, int t, int u, unsigned seg, std::vector<DevGroup> &groups,
-                              std::vector<DevRun> &runs) {
+// With `scalar` (packages are F4 scalar orbits) group h keeps only the tops
+// whose element of package h is element 0 (r): h is the smallest package of
+// the top, so this picks one codeword of each class {c, alpha c, alpha^2 c}.
+unsigned long long plan_round(const GammaDev &g, int t, int u, unsigned seg, bool scalar,
+                              std::vector<DevGroup> &groups, std::vector<DevRun> &runs) {
   groups.clear();
   runs.clear();
   const int R = g.R, r = t - u - 1;
   for (int h = 0; h < g.P; ++h) {
-    const unsigned long long items = g.suffix[size_t(h + 1) * R + r] * g.sizes[h];
+    const unsigned long long items = g.suffix[size_t(h + 1) * R + r] * (scalar ? 1 : g.sizes[h]);
     const unsigned long long len = g.prefix[size_t(h) * R + u];
     if (!items || !len) continue;
     DevGroup grp{};
@@ -280,7 +283,8 @@ void Executor::prepare(Job &job) {
     return;
   }
   if (o.seg_len < 0 || o.seg_len % kBlock || o.saved_depth < -1 || o.max_gamma < 0 || o.tops_mode < 0 ||
-      o.tops_mode > 2 || (o.filter != QD_FILTER_NONE && o.filter != QD_FILTER_STABILIZER)) {
+      o.tops_mode > 2 || (o.filter != QD_FILTER_NONE && o.filter != QD_FILTER_STABILIZER) ||
+      (o.scalar_classes != 0 && o.scalar_classes != -1)) {
     job.status = QD_ERR_INVALID;
     return;
   }
@@ -299,7 +303,9 @@ void Executor::prepare(Job &job) {
       if (!check_gamma(g, n)) { job.status = QD_ERR_INTERNAL; return; }
     if (!check_gamma(f2, n)) { job.status = QD_ERR_INTERNAL; return; }
     std::vector<Gamma> iso;
-    job.pc = choose_plan(f4, f2, iso, n, job.rank, o.diag == QD_DIAG_ISO ? QD_DIAG_AUTO : o.diag, o.max_gamma);
+    const bool f4_scalar = job.field == QD_FIELD_F4 && o.scalar_classes == 0;
+    job.pc = choose_plan(f4, f2, iso, n, job.rank, o.diag == QD_DIAG_ISO ? QD_DIAG_AUTO : o.diag, o.max_gamma,
+                         f4_scalar);
     // The isometry matrices are built only when asked for, or when they
     // might beat the other constructions' predicted work.
     if (o.diag == QD_DIAG_ISO ||
@@ -308,12 +314,13 @@ void Executor::prepare(Job &job) {
       iso = build_iso(job.basis, n, kMaxGamma);
       for (const Gamma &g : iso)
         if (!check_gamma_iso(g, n)) { job.status = QD_ERR_INTERNAL; return; }
-      job.pc = choose_plan(f4, f2, iso, n, job.rank, o.diag, o.max_gamma);
+      job.pc = choose_plan(f4, f2, iso, n, job.rank, o.diag, o.max_gamma, f4_scalar);
     }
     if (job.pc.diag == QD_DIAG_F2) job.use.push_back(f2);
     else if (job.pc.diag == QD_DIAG_ISO) job.use.assign(iso.begin(), iso.begin() + job.pc.h_used);
     else job.use.assign(f4.begin(), f4.begin() + job.pc.h_used);
     job.halve = job.pc.diag == QD_DIAG_ISO;
+    if (f4_scalar && job.pc.diag == QD_DIAG_F4) job.scalar = make_scalar_orbits(job.use);
   }
   prepare_gammas(job);
 }
@@ -325,6 +332,7 @@ void Executor::prepare_gammas(Job &job) {
   job.S.n = n; job.S.rank = job.rank; job.S.D = job.D; job.S.diag = job.pc.diag; job.S.h = h;
   job.S.d_estimate = job.pc.d_est; job.S.predicted = job.pc.predicted;
   job.S.logical_pairs = int(job.logicals.size() / 2);
+  job.S.scalar_classes = job.scalar ? 1 : 0;
   job.tdone.assign(h, 0);
   job.delta.resize(h);
   for (int j = 0; j < h; ++j) {
@@ -555,7 +563,8 @@ int Executor::schedule(Job &job, int sharing) {
     }
     GammaDev &g = job.gd[job.j];
     const int t = job.t;
-    const uint64_t planned = g.prefix[size_t(g.P) * g.R + t];
+    const uint64_t full = g.prefix[size_t(g.P) * g.R + t];
+    const uint64_t planned = job.scalar && full < kSat ? full / 3 : full;  // e_t(3,..,3) = 3^t C(P, t)
     if (t > kTMax || (job.opt.cancel && *job.opt.cancel) || planned >= kSat ||
         (job.opt.budget && job.planned_total + cum + planned > job.opt.budget)) {
       if (job.fl.empty()) job.incomplete = job.done = true;
@@ -573,7 +582,7 @@ int Executor::schedule(Job &job, int sharing) {
     int rc = ensure_table(job, g, f.u, false);
     if (!rc && f.use_tops) rc = ensure_table(job, g, t - f.u, true);
     if (rc) return rc;
-    f.tiles = plan_round(g, t, f.u, f.seg, f.hg, f.hr);
+    f.tiles = plan_round(g, t, f.u, f.seg, job.scalar, f.hg, f.hr);
     f.planned = planned;
     const int fj = f.j;
     job.fl.push_back(std::move(f));

@@ -105,6 +105,7 @@ struct Job {
   std::vector<Gamma> use;
   PlanChoice pc;
   bool halve = false;  // isometry matrices: bounds count Hamming weight
+  bool scalar = false; // one codeword per F4 scalar class
   std::vector<BRow> logicals;  // Modified BZ: the admission test's operators
   const uint32_t *dlogicals = nullptr;
   std::vector<GammaDev> gd;

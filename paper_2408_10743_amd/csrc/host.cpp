@@ -472,8 +472,17 @@ double iso_work_floor(int n, int rank, int d_est) {
   return 0.0;
 }
 
+bool make_scalar_orbits(std::vector<Gamma> &gs) {
+  for (const Gamma &g : gs)
+    for (const Package &p : g.pk)
+      if (p.dim != 2) return false;
+  for (Gamma &g : gs)
+    for (Package &p : g.pk) p.s = alpha_row(p.r);
+  return true;
+}
+
 PlanChoice choose_plan(const std::vector<Gamma> &f4, const Gamma &f2, const std::vector<Gamma> &iso, int n,
-                       int rank, int diag_req, int max_gamma_req) {
+                       int rank, int diag_req, int max_gamma_req, bool f4_scalar) {
   int upper = n;
   auto probe = [&](const Gamma &g) {
     for (const Package &p : g.pk) {
@@ -495,7 +504,11 @@ PlanChoice choose_plan(const std::vector<Gamma> &f4, const Gamma &f2, const std:
   auto consider = [&](const std::vector<Gamma> &gs, int diag, bool halve, double *pred) {
     const int hmax = max_gamma_req > 0 ? std::min<int>(max_gamma_req, int(gs.size())) : int(gs.size());
     std::vector<std::vector<double>> E;
-    for (int j = 0; j < hmax; ++j) E.push_back(esym_all(gs[j]));
+    for (int j = 0; j < hmax; ++j) {
+      E.push_back(esym_all(gs[j]));
+      if (diag == QD_DIAG_F4 && f4_scalar)
+        for (double &e : E.back()) e /= 3.0;
+    }
     *pred = -1.0;
     for (int h = 1; h <= hmax; ++h) {
       const double w = predict_with(gs, E, h, pc.d_est, halve);

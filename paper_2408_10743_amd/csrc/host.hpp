@@ -22,6 +22,16 @@ inline int qsym(const BRow &r, int q) {  // F4 symbol x + 2z at qubit q
 inline void radd(BRow &a, const BRow &b) {
   a.x[0] ^= b.x[0]; a.x[1] ^= b.x[1]; a.z[0] ^= b.z[0]; a.z[1] ^= b.z[1];
 }
+// alpha * (x | z) = (z | x ^ z): the F4 scalar alpha on a row (Sec. 2.3
+// convention a + alpha b <-> (a | b)).
+inline BRow alpha_row(const BRow &r) {
+  BRow o;
+  for (int i = 0; i < 2; ++i) {
+    o.x[i] = r.z[i];
+    o.z[i] = r.x[i] ^ r.z[i];
+  }
+  return o;
+}
 inline bool rzero(const BRow &a) { return !(a.x[0] | a.x[1] | a.z[0] | a.z[1]); }
 int rweight(const BRow &a);  // symplectic weight
 
@@ -84,6 +94,14 @@ int sym_product(const BRow &a, const BRow &b);
 // every one of them is 0.  Returns k.
 int logical_pairs(const std::vector<BRow> &basis, std::vector<BRow> &out);
 
+// F4 scalar classes.  For an F4-linear code every package of the F4
+// matrices has two rows; with s replaced by alpha r each package is the
+// orbit {r, alpha r, alpha^2 r} (still a basis with the same invariants), so
+// fixing the element of one designated package of a combination picks one
+// codeword of each class {c, alpha c, alpha^2 c}.  Returns false, leaving
+// the matrices unchanged, if some package has one row.
+bool make_scalar_orbits(std::vector<Gamma> &gs);
+
 // Elementary symmetric polynomials e_r of package sizes (1 or 3) as
 // saturating 64-bit integers.  prefix[h][r] = e_r(c_0..c_{h-1}),
 // suffix[h][r] = e_r(c_h..c_{P-1}); rmax columns + 1.
@@ -127,7 +145,9 @@ double iso_work_floor(int n, int rank, int d_est);
 
 // Picks the construction (F2, F4 or isometry, or the one diag_req names)
 // and the number of matrices with the least predicted work.
+// f4_scalar: the F4 matrices will enumerate scalar classes (a third of
+// their combinations).
 PlanChoice choose_plan(const std::vector<Gamma> &f4, const Gamma &f2, const std::vector<Gamma> &iso, int n,
-                       int rank, int diag_req, int max_gamma_req);
+                       int rank, int diag_req, int max_gamma_req, bool f4_scalar = false);
 
 }  // namespace qd

@@ -39,7 +39,7 @@ class qd_options(ctypes.Structure):
                 ("budget", ctypes.c_ulonglong), ("cancel", ctypes.POINTER(ctypes.c_int)),
                 ("stream", ctypes.c_void_p), ("seg_len", ctypes.c_int),
                 ("saved_depth", ctypes.c_int), ("timing", ctypes.c_int), ("tops_mode", ctypes.c_int),
-                ("filter", ctypes.c_int)]
+                ("filter", ctypes.c_int), ("scalar_classes", ctypes.c_int)]
 
 
 class qd_round_log(ctypes.Structure):
@@ -56,7 +56,8 @@ class qd_stats(ctypes.Structure):
                 ("d_estimate", ctypes.c_int), ("predicted", ctypes.c_double),
                 ("combinations", ctypes.c_ulonglong), ("host_ms", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
-                ("launches", ctypes.c_int), ("logical_pairs", ctypes.c_int), ("nlog", ctypes.c_int),
+                ("launches", ctypes.c_int), ("logical_pairs", ctypes.c_int),
+                ("scalar_classes", ctypes.c_int), ("nlog", ctypes.c_int),
                 ("log", qd_round_log * QD_MAX_LOG)]
 
     def rounds(self):

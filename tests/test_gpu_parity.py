@@ -339,3 +339,34 @@ def test_stabilizer_filter_batch(Q):
     assert st == 0 and all(x == 0 for x in sts)
     for (A, f), d in zip(codes, ds):
         assert d == O.brute_stab(A)[0]
+
+
+def test_f4_scalar_classes(Q):
+    """F4-linear input: one codeword per class {c, alpha c, alpha^2 c} gives
+    the same distance with a third of each round's combinations."""
+    gold = json.load(open(os.path.join(GOLD_DIR, "oracle_distances.json")))
+    for i in range(6):
+        G, f = W.config2(i)
+        print(f"scalar config2 seed {i}", flush=True)
+        s1 = check_distance(Q, G, f, gold["config2"][i], diag=Q.QD_DIAG_F4)
+        s0 = check_distance(Q, G, f, gold["config2"][i], diag=Q.QD_DIAG_F4, scalar_classes=-1)
+        assert s1.scalar_classes == 1 and s0.scalar_classes == 0
+        r1, r0 = s1.rounds(), s0.rounds()
+        for a, b in zip(r1, r0):
+            assert (a["t"], a["j"]) == (b["t"], b["j"])
+            assert 3 * a["planned"] == b["planned"]
+            assert a["L"] == b["L"]
+        for a in r1[:-1]:
+            assert a["combinations"] == a["planned"]
+    for s in range(40):
+        rng = W.SplitMix64(W.config_seed(26, s))
+        n = rng.uniform_int(4, 40)
+        k = rng.uniform_int(1, min(10, n))
+        G = W.f4_linear(n, k, rng.next())
+        d_ref = O.brute(O.expand(G, 4))[0]
+        st, d, wit, s1 = Q.qd_distance_ex(G, 4)
+        assert st == 0 and d == d_ref and swt(wit) == d, (s, n, k)
+        assert O.in_rowspace(O.expand(G, 4), wit)
+    # binary input never uses classes
+    G, f = W.config1(0)
+    assert Q.qd_distance_ex(G, f)[3].scalar_classes == 0
