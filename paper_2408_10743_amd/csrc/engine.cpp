@@ -25,6 +25,9 @@ constexpr unsigned long long kTargetTiles = 1ull << 18;    // ~32 tiles per wave
 constexpr unsigned kMinSeg = 256, kMaxSeg = 4096;
 constexpr unsigned kStageMaxBytes = 32768;
 constexpr unsigned long long kSpecCombos = 1ull << 24;  // rounds grouped per step below this
+// Rounds up to this size skip the saved and tops tables: every lane unranks
+// its whole combination (no table-build launch for small codes).
+constexpr unsigned long long kTinyRound = 1ull << 19;
 constexpr size_t kBigClass = size_t(64) << 20;
 constexpr size_t kSlabMax = size_t(16) << 20;   // largest class carved from slabs
 constexpr size_t kSlabBytes = size_t(64) << 20;
@@ -223,10 +226,15 @@ Executor::Executor(hipStream_t stream) {
     if (hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking) != hipSuccess) return;
     own_stream_ = true;
   }
+  // Depth 0 needs no build: one block of kBlock zero entries of up to 4 words per half.
+  const size_t zb = size_t(2) * 4 * kBlock * sizeof(uint32_t);
+  if (hipMalloc(reinterpret_cast<void **>(&zero_table_), zb) != hipSuccess) return;
+  if (hipMemset(zero_table_, 0, zb) != hipSuccess) return;
   ok_ = grow_states(64) == QD_OK;
 }
 
 Executor::~Executor() {
+  if (zero_table_) (void)hipFree(zero_table_);
   if (states_) (void)hipFree(states_);
   if (hstates_) (void)hipHostFree(hstates_);
   for (hipEvent_t e : events_) (void)hipEventDestroy(e);
@@ -579,7 +587,11 @@ int Executor::schedule(Job &job, int sharing) {
     f.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : choose_seg(planned, sharing);
     const int tm = job.opt.tops_mode;
     f.use_tops = tm == 1 || (tm == 0 && g.suffix[t - f.u] <= kMaxTopEntries);
-    int rc = ensure_table(job, g, f.u, false);
+    if (planned <= kTinyRound && job.opt.saved_depth == 0 && tm == 0) {
+      f.u = 0;
+      f.use_tops = false;
+    }
+    int rc = f.u > 0 ? ensure_table(job, g, f.u, false) : QD_OK;
     if (!rc && f.use_tops) rc = ensure_table(job, g, t - f.u, true);
     if (rc) return rc;
     f.tiles = plan_round(g, t, f.u, f.seg, job.scalar, f.hg, f.hr);
@@ -667,7 +679,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         GammaDev &g = job.gd[f.j];
         RoundDesc d{};
         d.elems = g.elems;
-        d.table = static_cast<const uint32_t *>(g.table[f.u].p);
+        d.table = f.u == 0 ? zero_table_ : static_cast<const uint32_t *>(g.table[f.u].p);
         d.tops = f.use_tops ? static_cast<const uint32_t *>(g.tops[f.t - f.u].p) : nullptr;
         // groups and runs travel with this step's upload (set by flush)
         const size_t go = staging_.put(f.hg.data(), f.hg.size() * sizeof(DevGroup));

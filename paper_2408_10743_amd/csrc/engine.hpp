@@ -178,6 +178,7 @@ class Executor {
   hipStream_t inflight_stream_ = nullptr;
   // launch resources
   PoolBuf slots_;
+  uint32_t *zero_table_ = nullptr;  // the saved table of depth 0: one zero entry
   std::vector<SavedParams> builds_[5];  // queued table builds per word count
   std::vector<RoundDesc> descs_;
   std::vector<size_t> desc_groups_;  // staged offsets of each piece's groups and runs
