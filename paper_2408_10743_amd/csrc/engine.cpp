@@ -24,7 +24,9 @@ constexpr unsigned long long kTilesPerLaunch = 1ull << 21;
 constexpr unsigned long long kTargetTiles = 1ull << 18;    // ~32 tiles per wave slot
 constexpr unsigned kMinSeg = 256, kMaxSeg = 4096;
 constexpr unsigned kStageMaxBytes = 32768;
-constexpr unsigned long long kSpecCombos = 1ull << 24;  // rounds grouped per step below this
+// Rounds of a code are grouped into one step while the step's total stays
+// below the executor's limit (kSpecCombos unless set_spec_combos changed it).
+constexpr unsigned long long kSpecCombos = 1ull << 36;
 // Rounds up to this size skip the saved and tops tables: every lane unranks
 // its whole combination (no table-build launch for small codes).
 constexpr unsigned long long kTinyRound = 1ull << 19;
@@ -214,7 +216,7 @@ size_t Staging::put(const void *src, size_t bytes) {
 
 // -- Executor ------------------------------------------------------------------
 
-Executor::Executor(hipStream_t stream) {
+Executor::Executor(hipStream_t stream) : spec_combos_(kSpecCombos) {
   int dev = 0, cnt = 0;
   hipDeviceProp_t prop;
   if (hipGetDeviceCount(&cnt) != hipSuccess || cnt <= 0 || hipGetDevice(&dev) != hipSuccess ||
@@ -581,7 +583,10 @@ int Executor::schedule(Job &job, int sharing) {
     Flight f;
     f.t = t;
     f.j = job.j;
-    f.L_before = job.single_round ? -1 : job.L;
+    // The bound certified once the rounds before this one have finished; they
+    // are in this step or earlier, so the round's waves may stop as soon as U
+    // reaches it.
+    f.L_before = job.single_round ? -1 : lower_bound(tsim, job.delta, job.halve);
     const int cap = job.opt.saved_depth < 0 ? 0 : job.opt.saved_depth ? job.opt.saved_depth : kDefaultSavedDepth;
     f.u = saved_depth(g, job.D, t, cap);
     f.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : choose_seg(planned, sharing);
@@ -601,7 +606,8 @@ int Executor::schedule(Job &job, int sharing) {
     cum += planned;
     ++job.j;
     tsim[fj] = t;
-    if (job.single_round || cum >= kSpecCombos || t == job.use[fj].P() || lower_bound(tsim, job.delta, job.halve) >= stop_at)
+    if (job.single_round || cum >= spec_combos_ || t == job.use[fj].P() ||
+        lower_bound(tsim, job.delta, job.halve) >= stop_at)
       return QD_OK;
   }
 }

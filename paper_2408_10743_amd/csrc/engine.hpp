@@ -131,6 +131,9 @@ class Executor {
   bool ok() const { return ok_; }
   hipStream_t stream() const { return stream_; }
   size_t device_bytes() const { return pool_.held(); }
+  // Combinations of one code's consecutive rounds that one step may carry
+  // (more: fewer steps; less: shorter steps, e.g. for serving).
+  void set_spec_combos(unsigned long long c) { spec_combos_ = c; }
 
   // Host-side preparation of a job (input check, basis, diagonalizations,
   // plan).  Thread-safe; touches no device state.
@@ -158,6 +161,7 @@ class Executor {
   int grow_states(int need);
 
   bool ok_ = false;
+  unsigned long long spec_combos_;
   bool own_stream_ = false;
   hipStream_t stream_ = nullptr;
   DevPool pool_;

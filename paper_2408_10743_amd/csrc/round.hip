@@ -132,6 +132,9 @@ __device__ bool admitted(const uint32_t (&cx)[D], const uint32_t (&cz)[D], const
   return false;
 }
 
+// Workgroups per chunk dealt to one XCD (see qd_round_kernel).
+constexpr uint32_t kXcdChunk = 16;
+
 // One tile = one table segment [k0, k0 + seg) x 64 tops.  The tops of a
 // tile come from every group whose table prefix reaches the segment, so
 // lanes stay full; a lane stops at its own group's prefix length.  A launch
@@ -139,10 +142,13 @@ __device__ bool admitted(const uint32_t (&cx)[D], const uint32_t (&cz)[D], const
 template <int D>
 __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   extern __shared__ unsigned long long smem[];
-  // Consecutive workgroups land on different XCDs; give each XCD a
-  // contiguous range of tiles so its L2 sees a contiguous table range.
-  const uint32_t per = gridDim.x / 8;
-  const uint32_t wg = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  // Consecutive workgroups land on different XCDs (round robin).  Deal them
+  // to the XCDs in chunks of kXcdChunk consecutive workgroups instead: a
+  // chunk's tiles share table segments (one L2), and every XCD gets chunks
+  // from the whole launch, so pieces whose tiles cost different amounts
+  // (rounds of other sizes, other codes) stay balanced across XCDs.
+  const uint32_t xcd = blockIdx.x % 8, r = blockIdx.x / 8;
+  const uint32_t wg = ((r / kXcdChunk) * 8 + xcd) * kXcdChunk + r % kXcdChunk;
   const unsigned long long wtile = static_cast<unsigned long long>(wg) * kWavesPerGroup;
   if (wtile >= lp.tiles) return;  // whole workgroup: launch padding
   int lo = 0, hi = lp.ndesc;
@@ -327,7 +333,7 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
 
 hipError_t launch_round(int D, const LaunchParams &lp, hipStream_t s) {
   unsigned long long wgs = lp.tiles / kWavesPerGroup;
-  wgs = (wgs + 7) / 8 * 8;
+  wgs = (wgs + 8 * kXcdChunk - 1) / (8 * kXcdChunk) * (8 * kXcdChunk);  // the XCD dealing is a bijection
   dim3 grid(static_cast<uint32_t>(wgs)), block(kWave * kWavesPerGroup);
   switch (D) {
     case 1: hipLaunchKernelGGL(qd_round_kernel<1>, grid, block, lp.lds, s, lp); break;

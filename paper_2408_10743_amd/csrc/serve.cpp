@@ -111,6 +111,8 @@ qd_engine *qd_engine_create(size_t mem_budget, int max_active, void *stream) {
   if (hipGetDevice(&e->device) != hipSuccess) return nullptr;
   e->ex = std::make_unique<Executor>(static_cast<hipStream_t>(stream));
   if (!e->ex->ok()) return nullptr;
+  // Short steps, so that new requests join the device work every few ms.
+  e->ex->set_spec_combos(1ull << 24);
   e->budget = mem_budget ? mem_budget : (size_t(8) << 30);
   e->max_active = max_active > 0 ? max_active : 512;
   qd_engine *raw = e.release();
