@@ -33,7 +33,7 @@ PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # 1 GiB device copy in the same runs), valid only for the kernel source
 # with this fingerprint (sha256 prefixes of round.hip and kernels.hpp, the
 # enumeration kernel and its data layouts).
-TRAFFIC = {"fingerprint": "b95b3d8853f979ed03a148c7ba2736e7", "bytes_per_launch": 130878725}
+TRAFFIC = {"fingerprint": "37fc9468e51fb44503a148c7ba2736e7", "bytes_per_launch": 1200509987}
 
 
 def kernel_fingerprint():
@@ -98,8 +98,13 @@ def cpu_baseline(G, field, budget_s):
 
 
 def predicted_work(Q, G, f):
+    """Planner-predicted combinations of the cheaper of the F2 and F4
+    constructions, enumerating every codeword.  This defines which draws
+    the workloads keep, so it counts all three codewords of each F4 scalar
+    class even though the library enumerates one of them."""
     p = Q.qd_plan(G, f)
-    cands = [x for x in (p["predicted_f2"], p["predicted_f4"]) if x >= 0]
+    f4 = p["predicted_f4"] * (3 if f == 4 else 1)
+    cands = [x for x in (p["predicted_f2"], f4) if x >= 0]
     return min(cands)
 
 
@@ -195,7 +200,7 @@ def leg_stabilizer(Q, W, a):
         A, f = W.config_stab(i)
         i += 1
         drawn += 1
-        if Q.qd_plan(A, f)["predicted_" + {2: "f2", 3: "iso", 4: "f4"}[Q.qd_plan(A, f)["diag"]]] <= a.batch_max_work:
+        if predicted_work(Q, A, f) <= a.batch_max_work:
             codes.append((A, f))
     flt = Q.QD_FILTER_STABILIZER
     t0 = time.perf_counter()
@@ -255,6 +260,8 @@ def leg_serving(Q, W, a):
             if len(reqs) == a.serve_requests:
                 break
     # service capacity: the same requests run back to back as one batch
+    # (timed on a second call, after device memory and tables are warm)
+    Q.qd_distance_batch(reqs)
     t0 = time.perf_counter()
     Q.qd_distance_batch(reqs)
     t_all = time.perf_counter() - t0
