@@ -25,6 +25,15 @@ QD_MAX_N, QD_MAX_GAMMA, QD_MAX_LOG = 128, 8, 96
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libqdist.so not found at {LIB_PATH}; build it with __graft_entry__.build()")
+# PyTorch ships its own HIP runtime under the same soname as the system one
+# the library links to, and whichever loads first serves the whole process.
+# Load PyTorch's first when it is installed, so that both share one runtime:
+# streams passed from PyTorch are then valid here, and PyTorch still finds
+# the GPU after this library has used it.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = ctypes.CDLL(LIB_PATH)
 
 

@@ -1,0 +1,119 @@
+"""GPU checks at the benchmark's full sizes, in the call patterns bench.py
+times: every output is checked by its properties (witness weight equals d,
+witness in the row space, the same d alone and in a batch), and samples
+that the oracle finishes quickly are compared with it exactly."""
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import bench
+from oracle import oracle as O
+from paper_2408_10743_amd import workloads as W
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_distances.json")))
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2408_10743_amd import qdist
+    st, name = qdist.qd_device_check()
+    assert st == 0, name
+    return qdist
+
+
+def swt(v):
+    n = v.shape[-1] // 2
+    return int(np.count_nonzero(v[:n] | v[n:]))
+
+
+def test_config1_every_seed(Q):
+    """Config 1 at its stated size: all 1,000 seeds in one batch against the
+    oracle's exhaustive search."""
+    codes = [W.config1(i) for i in range(1000)]
+    st, ds, wits, sts, _ = Q.qd_distance_batch(codes)
+    assert st == 0 and all(x == 0 for x in sts)
+    for i, ((G, f), d, w) in enumerate(zip(codes, ds, wits)):
+        if i % 100 == 0:
+            print(f"config1 seed {i}", flush=True)
+        B = O.expand(G, f)
+        assert d == O.brute(B)[0], i
+        assert swt(w) == d and O.in_rowspace(B, w)
+
+
+def test_config4_full_batch(Q):
+    """The bench's config-4 batch (512 codes): each code's d equals its
+    per-code result, witnesses check out, and the codes the oracle settles
+    in well under a second agree with it."""
+    codes, drawn = bench.config4_codes(Q, W, 512, 1e11)
+    budget = int(4e11)
+    print(f"config4 batch of {len(codes)} (of {drawn} drawn)", flush=True)
+    st, ds, wits, sts, stats = Q.qd_distance_batch(codes, budget=budget)
+    assert all(x in (0, Q.QD_INCOMPLETE) for x in sts)
+    for (G, f), d, w, s, x in zip(codes, ds, wits, stats, sts):
+        B = O.expand(G, f)
+        assert swt(w) == d and O.in_rowspace(B, w)
+        st1, d1, _, s1 = Q.qd_distance_ex(G, f, budget=budget)
+        assert st1 == x and d1 == d
+    # exact oracle comparison on the cheapest codes of each field
+    order = sorted(range(len(codes)), key=lambda i: stats[i].combinations)
+    checked = {2: 0, 4: 0}
+    for i in order:
+        G, f = codes[i]
+        if checked[f] >= 6 or sts[i] != 0:
+            continue
+        B = O.expand(G, f)
+        t0 = time.perf_counter()
+        d_ref = O.brute(B)[0] if O.rank(B) <= 22 else O.bz(B, O.DIAG_F4, 8)[0]
+        print(f"config4 code {i} field {f} n {B.shape[1] // 2} d {d_ref} ({time.perf_counter() - t0:.2f} s)",
+              flush=True)
+        assert ds[i] == d_ref
+        checked[f] += 1
+    assert checked[2] == 6 and checked[4] == 6
+
+
+def test_config5_engine_mix(Q):
+    """The bench's config-5 request mix through the serving engine: every
+    result equals the same code alone (tolerance 0)."""
+    raw = W.config5(300 * 4, 1.0)
+    reqs = []
+    for _, G, f in raw:
+        if bench.predicted_work(Q, G, f) <= 1e10:
+            reqs.append((G, f))
+            if len(reqs) == 300:
+                break
+    e = Q.qd_engine_create()
+    got = {}
+    try:
+        for tag, (G, f) in enumerate(reqs):
+            assert Q.qd_engine_submit(e, G, f, tag) == 0
+        t_end = time.time() + 90
+        while len(got) < len(reqs) and time.time() < t_end:
+            for r, w in Q.qd_engine_poll(e, 64, 200):
+                got[r.tag] = (r.status, r.d, w)
+    finally:
+        Q.qd_engine_destroy(e)
+    assert len(got) == len(reqs)
+    for tag, (G, f) in enumerate(reqs):
+        status, d, w = got[tag]
+        st1, d1, _ = Q.qd_distance(G, f)
+        assert status == 0 and d == d1, tag
+        assert swt(w) == d and O.in_rowspace(O.expand(G, f), w)
+
+
+def test_config3_full_size_bench_call(Q):
+    """Config 3 exactly as bench.py times it (stream, timing on): the oracle's
+    golden distance, and every completed round visited its planned count."""
+    import torch
+    stream = torch.cuda.current_stream()
+    G, f = W.config3(0)
+    for _ in range(2):
+        st, d, w, s = Q.qd_distance_ex(G, f, stream=stream.cuda_stream, timing=1)
+        assert st == 0 and d == GOLD["config3"][0]
+        assert swt(w) == d and O.in_rowspace(O.expand(G, f), w)
+        assert s.combinations == sum(r["combinations"] for r in s.rounds())
+        assert s.launches >= 1 and s.kernel_ms > 0
