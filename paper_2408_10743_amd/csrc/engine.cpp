@@ -27,6 +27,11 @@ constexpr unsigned kStageMaxBytes = 32768;
 // Rounds of a code are grouped into one step while the step's total stays
 // below the executor's limit (kSpecCombos unless set_spec_combos changed it).
 constexpr unsigned long long kSpecCombos = 1ull << 36;
+// Combinations a step may add past the planner's distance estimate, so that
+// a low estimate costs small codes no extra step: at most kSpecExtraRatio
+// times the work the estimate needed, and at most kSpecExtra.
+constexpr unsigned long long kSpecExtra = 1ull << 24;
+constexpr unsigned long long kSpecExtraRatio = 16;
 // Rounds up to this size skip the saved and tops tables: every lane unranks
 // its whole combination (no table-build launch for small codes).
 constexpr unsigned long long kTinyRound = 1ull << 19;
@@ -550,10 +555,18 @@ int Executor::flush(hipStream_t s, const unsigned char **base, size_t *desc_off)
 int Executor::schedule(Job &job, int sharing) {
   const int h = int(job.use.size());
   unsigned long long cum = 0;
-  // Speculation stops once the scheduled rounds would certify a bound that
-  // meets the current upper bound or the planner's distance estimate.
+  // Speculation: rounds are added while the scheduled ones would not yet
+  // certify the planner's distance estimate, then (the estimate may be
+  // low) only while the extra rounds stay cheap, and never past a bound
+  // that meets the current upper bound.
   std::vector<int> tsim = job.tdone;
   const int stop_at = std::min(job.U, std::max(job.pc.d_est, 1));
+  bool beyond = lower_bound(tsim, job.delta, job.halve) >= stop_at;
+  unsigned long long extra = 0, extra_cap = 0;
+  auto cap_extra = [&](unsigned long long needed) {
+    extra_cap = std::min<unsigned long long>(kSpecExtra, kSpecExtraRatio * std::max<unsigned long long>(needed, 1));
+  };
+  if (beyond) cap_extra(job.planned_total);
   for (;;) {
     if (!job.single_round) {
       bool found = false;
@@ -579,6 +592,10 @@ int Executor::schedule(Job &job, int sharing) {
         (job.opt.budget && job.planned_total + cum + planned > job.opt.budget)) {
       if (job.fl.empty()) job.incomplete = job.done = true;
       return QD_OK;
+    }
+    if (beyond && !job.fl.empty()) {
+      if (extra + planned > extra_cap) return QD_OK;
+      extra += planned;
     }
     Flight f;
     f.t = t;
@@ -606,9 +623,12 @@ int Executor::schedule(Job &job, int sharing) {
     cum += planned;
     ++job.j;
     tsim[fj] = t;
-    if (job.single_round || cum >= spec_combos_ || t == job.use[fj].P() ||
-        lower_bound(tsim, job.delta, job.halve) >= stop_at)
-      return QD_OK;
+    const int Lsim = lower_bound(tsim, job.delta, job.halve);
+    if (job.single_round || cum >= spec_combos_ || t == job.use[fj].P() || Lsim >= job.U) return QD_OK;
+    if (!beyond && Lsim >= stop_at) {
+      beyond = true;
+      cap_extra(job.planned_total + cum);
+    }
   }
 }
 
