@@ -370,3 +370,27 @@ def test_f4_scalar_classes(Q):
     # binary input never uses classes
     G, f = W.config1(0)
     assert Q.qd_distance_ex(G, f)[3].scalar_classes == 0
+
+
+def test_stabilizer_filter_with_scalar_classes(Q):
+    """F4-linear input with the filter: the radical of an F4-linear span is
+    F4-linear, so one codeword per scalar class still finds the least
+    admitted weight.  The five-qubit code in F4 form (two cyclic shifts of
+    1 a a 1 0 and the logical 1 1 1 1 1), then random F4-linear spans."""
+    base = [1, 2, 2, 1, 0]
+    G4 = np.array([base[-i:] + base[:-i] for i in range(2)] + [[1, 1, 1, 1, 1]], dtype=np.uint8)
+    for sc in (0, -1):
+        st, d, wit, s = Q.qd_distance_ex(G4, 4, filter=Q.QD_FILTER_STABILIZER, scalar_classes=sc)
+        assert st == 0 and d == 3 and s.logical_pairs == 1
+        assert s.scalar_classes == (1 if sc == 0 and s.diag == Q.QD_DIAG_F4 else 0)
+    for s_ in range(30):
+        rng = W.SplitMix64(W.config_seed(27, s_))
+        n = rng.uniform_int(3, 12)
+        k = rng.uniform_int(1, min(6, n))
+        G = W.f4_linear(n, k, rng.next())
+        B = O.expand(G, 4)
+        d_ref = O.brute_stab(B)[0]
+        for sc in (0, -1):
+            st, d, wit, s = Q.qd_distance_ex(G, 4, filter=Q.QD_FILTER_STABILIZER, scalar_classes=sc, diag=Q.QD_DIAG_F4)
+            assert st == 0 and d == d_ref, (s_, n, k, sc)
+            assert swt(wit) == d and O.in_rowspace(B, wit)
