@@ -103,7 +103,7 @@ def predicted_work(Q, G, f):
     the workloads keep, so it counts all three codewords of each F4 scalar
     class even though the library enumerates one of them."""
     p = Q.qd_plan(G, f)
-    f4 = p["predicted_f4"] * (3 if f == 4 else 1)
+    f4 = p["predicted_f4"] * (3 if p["f4_scalar_classes"] else 1)
     cands = [x for x in (p["predicted_f2"], f4) if x >= 0]
     return min(cands)
 

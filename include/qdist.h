@@ -88,9 +88,10 @@ typedef struct qd_options {
   int tops_mode;              /* tuning override: 0 auto, 1 tops from a table,
                                  2 tops unranked by each lane */
   int filter;                 /* QD_FILTER_NONE or QD_FILTER_STABILIZER */
-  int scalar_classes;         /* F4-linear input (QD_FIELD_F4) with the F4 construction:
-                                 0 enumerate one codeword of each class {c, alpha c,
-                                 alpha^2 c} (equal weights, a third of the work); -1 all */
+  int scalar_classes;         /* F4-linear code (QD_FIELD_F4 input, or a binary span closed
+                                 under alpha) with the F4 construction: 0 enumerate one
+                                 codeword of each class {c, alpha c, alpha^2 c} (equal
+                                 weights, a third of the work); -1 all */
 } qd_options;
 
 /* One (t, Gamma_j) round of the enumeration. */
@@ -142,6 +143,8 @@ typedef struct qd_plan_info {
   int d_estimate;
   double predicted_f2, predicted_f4;      /* predicted combinations per construction */
   double predicted_iso;
+  int f4_scalar_classes;                  /* 1: the code is F4-linear, so the F4 prediction
+                                             counts one codeword per scalar class */
 } qd_plan_info;
 
 /* Symplectic minimum distance of the code spanned by G (Sec. 2 definition,

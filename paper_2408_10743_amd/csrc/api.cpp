@@ -184,7 +184,9 @@ int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma, 
   std::vector<Gamma> iso = build_iso(rows, n, hmax);
   for (const Gamma &g : iso)
     if (!check_gamma_iso(g, n)) return QD_ERR_INTERNAL;
-  PlanChoice pc = choose_plan(f4, f2, iso, n, k, diag, max_gamma, field == QD_FIELD_F4);
+  const bool f4_scalar = field == QD_FIELD_F4 || alpha_closed(rows, n);
+  PlanChoice pc = choose_plan(f4, f2, iso, n, k, diag, max_gamma, f4_scalar);
+  out->f4_scalar_classes = f4_scalar ? 1 : 0;
   out->n = n;
   out->rank = k;
   out->d_estimate = pc.d_est;

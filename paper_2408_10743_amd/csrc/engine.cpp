@@ -318,7 +318,8 @@ void Executor::prepare(Job &job) {
       if (!check_gamma(g, n)) { job.status = QD_ERR_INTERNAL; return; }
     if (!check_gamma(f2, n)) { job.status = QD_ERR_INTERNAL; return; }
     std::vector<Gamma> iso;
-    const bool f4_scalar = job.field == QD_FIELD_F4 && o.scalar_classes == 0;
+    const bool f4_scalar =
+        o.scalar_classes == 0 && (job.field == QD_FIELD_F4 || alpha_closed(job.basis, n));
     job.pc = choose_plan(f4, f2, iso, n, job.rank, o.diag == QD_DIAG_ISO ? QD_DIAG_AUTO : o.diag, o.max_gamma,
                          f4_scalar);
     // The isometry matrices are built only when asked for, or when they

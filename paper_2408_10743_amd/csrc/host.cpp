@@ -472,6 +472,12 @@ double iso_work_floor(int n, int rank, int d_est) {
   return 0.0;
 }
 
+bool alpha_closed(const std::vector<BRow> &basis, int n) {
+  std::vector<BRow> rows = basis;
+  for (const BRow &r : basis) rows.push_back(alpha_row(r));
+  return make_basis(rows, n) == int(basis.size());
+}
+
 bool make_scalar_orbits(std::vector<Gamma> &gs) {
   for (const Gamma &g : gs)
     for (const Package &p : g.pk)

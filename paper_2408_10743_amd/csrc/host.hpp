@@ -102,6 +102,10 @@ int logical_pairs(const std::vector<BRow> &basis, std::vector<BRow> &out);
 // the matrices unchanged, if some package has one row.
 bool make_scalar_orbits(std::vector<Gamma> &gs);
 
+// True when the span of `basis` is closed under alpha (an F4-linear code,
+// whatever the input field): alpha times every basis row lies in the span.
+bool alpha_closed(const std::vector<BRow> &basis, int n);
+
 // Elementary symmetric polynomials e_r of package sizes (1 or 3) as
 // saturating 64-bit integers.  prefix[h][r] = e_r(c_0..c_{h-1}),
 // suffix[h][r] = e_r(c_h..c_{P-1}); rmax columns + 1.

@@ -97,7 +97,8 @@ class qd_plan_info(ctypes.Structure):
                 ("dims", (ctypes.c_int * (2 * QD_MAX_N)) * QD_MAX_GAMMA),
                 ("pivot", (ctypes.c_int * (2 * QD_MAX_N)) * QD_MAX_GAMMA),
                 ("d_estimate", ctypes.c_int), ("predicted_f2", ctypes.c_double),
-                ("predicted_f4", ctypes.c_double), ("predicted_iso", ctypes.c_double)]
+                ("predicted_f4", ctypes.c_double), ("predicted_iso", ctypes.c_double),
+                ("f4_scalar_classes", ctypes.c_int)]
 
 
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -216,7 +217,8 @@ def qd_plan(G, field=QD_FIELD_F2, diag=QD_DIAG_AUTO, max_gamma=0):
                    "pivots": list(info.pivot[j])[:P]})
     return {"n": info.n, "rank": info.rank, "diag": info.diag, "h": info.h, "h_used": info.h_used,
             "gammas": gs, "d_estimate": info.d_estimate, "predicted_f2": info.predicted_f2,
-            "predicted_f4": info.predicted_f4, "predicted_iso": info.predicted_iso}
+            "predicted_f4": info.predicted_f4, "predicted_iso": info.predicted_iso,
+            "f4_scalar_classes": info.f4_scalar_classes}
 
 
 def qd_round_min(rows, dims, t):

@@ -394,3 +394,15 @@ def test_stabilizer_filter_with_scalar_classes(Q):
             st, d, wit, s = Q.qd_distance_ex(G, 4, filter=Q.QD_FILTER_STABILIZER, scalar_classes=sc, diag=Q.QD_DIAG_F4)
             assert st == 0 and d == d_ref, (s_, n, k, sc)
             assert swt(wit) == d and O.in_rowspace(B, wit)
+
+
+def test_scalar_classes_for_alpha_closed_binary_input(Q):
+    gold = json.load(open(os.path.join(GOLD_DIR, "oracle_distances.json")))
+    for i in range(3):
+        G, f = W.config2(i)
+        B = O.expand(G, f)
+        st, d, wit, s = Q.qd_distance_ex(B, 2, diag=Q.QD_DIAG_F4)
+        assert st == 0 and d == gold["config2"][i] and s.scalar_classes == 1
+    A = W.textbook_code("[[5,1,3]]")
+    st, d, wit, s = Q.qd_distance_ex(A, 2, filter=Q.QD_FILTER_STABILIZER, diag=Q.QD_DIAG_F4)
+    assert st == 0 and d == 3 and s.scalar_classes == 1

@@ -162,3 +162,15 @@ def test_filter_option_validation(Q):
     # an unknown filter is rejected before any device work
     st, d, _, _ = Q.qd_distance_ex(W.textbook_code("[[5,1,3]]"), 2, filter=7)
     assert st == Q.QD_ERR_INVALID and d == -1
+
+
+def test_alpha_closed_binary_input_uses_scalar_classes(Q):
+    # a binary input whose span is closed under alpha is F4-linear: the F4
+    # prediction counts one codeword per scalar class, as for F4 input
+    G, f = W.config2(0)
+    B = O.expand(G, f)
+    p2, p4 = Q.qd_plan(B, 2), Q.qd_plan(G, 4)
+    assert p2["f4_scalar_classes"] == p4["f4_scalar_classes"] == 1
+    assert p2["predicted_f4"] == p4["predicted_f4"]
+    assert Q.qd_plan(*W.config1(0))["f4_scalar_classes"] == 0
+    assert Q.qd_plan(W.textbook_code("[[5,1,3]]"), 2)["f4_scalar_classes"] == 1
