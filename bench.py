@@ -69,6 +69,9 @@ def parse():
                     help="also run 3 device copies of 1 GiB (reference for HBM byte counters)")
     ap.add_argument("--valu-probe", action="store_true",
                     help="only time the VALU instruction mixes of qd_valu_mix and print their rates")
+    ap.add_argument("--round-sweep", action="store_true",
+                    help="only run one large round (48 two-row packages, t = 6) at D = 1..4 words per "
+                         "half, for per-D kernel durations from a profiler")
     return ap.parse_args()
 
 
@@ -305,6 +308,21 @@ def main():
     if st != 0:
         print(f"device check failed: {Q.qd_strerror(st)} ({name})", file=sys.stderr)
         sys.exit(1)
+    if a.round_sweep:
+        out = {}
+        for D in (1, 2, 3, 4):
+            n = 32 * D
+            rows, dims = W.random_packages(48, n, W.config_seed(50, D), 1.0)
+            for rep in range(2):  # the second call's kernel is the one to read
+                t0 = time.perf_counter()
+                st, wmin, _, count = Q.qd_round_min(rows, dims, 6)
+                ms = (time.perf_counter() - t0) * 1e3
+                if st != 0:
+                    raise RuntimeError(Q.qd_strerror(st))
+            out[f"D{D}"] = {"n": n, "combinations": count, "ops_per_codeword": ops_per_codeword(D),
+                            "wall_ms": ms, "wmin": wmin}
+        print(json.dumps({"round_sweep": out}))
+        return
     if a.valu_probe:
         rates = {}
         for name_, mix in Q.QD_MIXES.items():
