@@ -78,7 +78,8 @@ typedef struct qd_options {
   int max_gamma;              /* 0: planner decides; else at most this many matrices */
   unsigned long long budget;  /* stop before a round that would exceed this many
                                  combinations in total (0: no limit) -> QD_INCOMPLETE */
-  const volatile int *cancel; /* host flag polled between rounds (NULL: none) */
+  const volatile int *cancel; /* host flag polled before each device step, which carries
+                                 one or more consecutive rounds (NULL: none) */
   void *stream;               /* hipStream_t for all work (NULL: the library's own) */
   int seg_len;                /* tuning override: table entries per tile, multiple of 8 (0: auto) */
   int saved_depth;            /* tuning override: max packages in the saved-sum table (0: auto;
