@@ -8,12 +8,13 @@
  * Quantum Codes":
  *   d = min { wt_s(c) : c in C, c != 0 },  wt_s(a,b) = #{i : a_i or b_i != 0}
  * (Sec. 2, the first two displays), for the code C spanned by the rows of
- * a normalizer-type matrix (Sec. 2, the matrix A; for k = 0 the paper's
- * modified algorithm updates U with every codeword, Sec. 2.1, which is the
- * rule used here for any input).  The generator matrices are built by the
- * diagonalizations of Sec. 2.2 (over F2) and Sec. 2.3 (over F4, with the
- * second matrix on the principal columns); the lower bound is the one of
- * Sec. 2.1 and Sec. 2.3.
+ * a normalizer-type matrix (Sec. 2, the matrix A).  By default every
+ * codeword updates U (the paper's modified algorithm does so for k = 0,
+ * Sec. 2.1); QD_FILTER_STABILIZER applies its C^{perp_s} \ C test for k > 0.
+ * The generator matrices are built by the diagonalizations of Sec. 2.2
+ * (over F2) and Sec. 2.3 (over F4, with further matrices on the principal
+ * columns), or as the information sets of the isometric image (Sec. 2.4);
+ * the lower bound is the one of Sec. 2.1 and Sec. 2.3.
  *
  * Conventions for every entry point:
  *  - Buffers are host memory owned by the caller, read or written only
@@ -158,9 +159,10 @@ int qd_distance_ex(const uint8_t *G, int m, int n, int field, const qd_options *
                    int *d, uint8_t *witness, qd_stats *st);
 
 /* Distances of `count` independent codes.  Every code's rounds advance on
- * their own; each step of the batch launches the next round piece of every
- * unfinished code together (one enumeration launch per word count D), so
- * small codes fill the device jointly.  Arrays are indexed by code; witness
+ * their own; each step of the batch launches the next rounds (or the next
+ * piece of a large round) of every unfinished code together (one
+ * enumeration launch per word count D), so small codes fill the device
+ * jointly.  Arrays are indexed by code; witness
  * may be NULL or hold NULL entries; status[i] receives the per-code status
  * (as qd_distance).  Returns QD_OK when no code failed, else the first
  * negative status.  opt may be NULL; its budget and cancel apply to every
