@@ -46,9 +46,18 @@ def kernel_fingerprint():
 
 
 def ops_per_codeword(D):
-    """32-bit integer ops per codeword: per word one XOR (x), one fused
-    XOR-OR (z, v_bitop3) and one popcount, plus one MIN."""
+    """32-bit integer ops per codeword with every word evaluated: per word
+    one XOR (x), one fused XOR-OR (z, v_bitop3) and one popcount, plus one
+    MIN."""
     return 3 * D + 1
+
+
+def algorithmic_ops(words, combos):
+    """Integer ops the enumeration needs: three per evaluated word and one
+    MIN per codeword.  With partial weights a codeword whose first words
+    already decide it costs fewer words; without, words = D x combos and
+    this is combos x ops_per_codeword(D)."""
+    return 3 * words + combos
 
 
 def parse():
@@ -163,6 +172,26 @@ def leg_plain(Q, G, field, engine_step_ms, engine_combos):
     return {"ms_per_step": s.wall_ms, "codewords_per_s": s.combinations / (s.wall_ms * 1e-3),
             "kernel_codewords_per_s": s.combinations / (s.kernel_ms * 1e-3), "d": d,
             "engine_speedup": s.wall_ms / engine_step_ms}
+
+
+def leg_full_weight(Q, G, field, stream, steps):
+    """The same code with every word of every codeword evaluated
+    (partial_weight = -1): the enumeration rate without partial weights."""
+    runs = []
+    for i in range(steps + 1):
+        st, d, wit, s = Q.qd_distance_ex(G, field, stream=stream, timing=1, partial_weight=-1)
+        assert st == 0
+        if i:
+            runs.append(s)
+    combos = sum(s.combinations for s in runs)
+    enum = sum(s.enumerated for s in runs)
+    words = sum(s.words for s in runs)
+    kernel_ms = sum(s.kernel_ms for s in runs)
+    enum_ms = sum(s.enumerated_kernel_ms for s in runs)
+    wall_ms = sum(s.wall_ms for s in runs)
+    return {"d": d, "ms_per_step": wall_ms / steps, "codewords_per_s": combos / (wall_ms * 1e-3),
+            "kernel_codewords_per_s": combos / (kernel_ms * 1e-3),
+            "roofline_frac": algorithmic_ops(words, enum) / (enum_ms * 1e-3) / PEAK_LANE_OPS}
 
 
 def leg_constructions(Q, W):
@@ -355,8 +384,13 @@ def main():
     kernel_ms = sum(s.kernel_ms for _, s in stats)
     launches = sum(s.launches for _, s in stats)
     D = stats[0][1].D
-    achieved = combos * ops_per_codeword(D) / (kernel_ms * 1e-3)
-    achieved_survey = combos * (4 * D + 1) / (kernel_ms * 1e-3)
+    # The roofline counts what the device enumerated (rounds run ahead
+    # speculatively included) over the launch time spent on it.
+    words = sum(s.words for _, s in stats)
+    enum = sum(s.enumerated for _, s in stats)
+    enum_ms = sum(s.enumerated_kernel_ms for _, s in stats)
+    achieved = algorithmic_ops(words, enum) / (enum_ms * 1e-3)
+    achieved_survey = (4 * words + enum) / (enum_ms * 1e-3)
     s0 = stats[0][1]
     out = {
         "metric": "codewords/s (XOR+symplectic wt) & time-to-exact-d",
@@ -386,10 +420,11 @@ def main():
             "frac": achieved / PEAK_LANE_OPS,
             "traffic": TRAFFIC["bytes_per_launch"] if kernel_fingerprint() == TRAFFIC["fingerprint"] else None,
             "kernel": f"qd_round_kernel<{D}>",
-            "ops_per_codeword": ops_per_codeword(D),
+            "ops_per_codeword": algorithmic_ops(words, enum) / enum,
+            "words_per_codeword": words / enum,
             "frac_4D1_ops": achieved_survey / PEAK_LANE_OPS,
             "launches": launches,
-            "avg_launch_ms": kernel_ms / max(launches, 1),
+            "avg_launch_ms": enum_ms / max(launches, 1),
         },
         "device": name,
     }
@@ -401,6 +436,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = src.numel() * 4
     if not a.no_extra:
+        out["full_weight"] = leg_full_weight(Q, G, field, stream.cuda_stream, 5)
         out["plain_per_code"] = leg_plain(Q, G, field, wall * 1e3 / a.steps, combos / a.steps)
         out["batched"] = leg_batched(Q, W, a)
         out["serving"] = leg_serving(Q, W, a)

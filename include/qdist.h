@@ -94,6 +94,11 @@ typedef struct qd_options {
                                  under alpha) with the F4 construction: 0 enumerate one
                                  codeword of each class {c, alpha c, alpha^2 c} (equal
                                  weights, a third of the work); -1 all */
+  int partial_weight;         /* 0: once U is small enough, decide a codeword from the
+                                 weight of its first words plus the pivots its packages
+                                 must hit beyond them, and evaluate the rest only where
+                                 that bound is below U (same d and witness rules);
+                                 -1: evaluate every word of every codeword */
 } qd_options;
 
 /* One (t, Gamma_j) round of the enumeration. */
@@ -118,8 +123,16 @@ typedef struct qd_stats {
   int d_estimate;             /* planner's distance estimate */
   double predicted;           /* planner's predicted combinations */
   unsigned long long combinations; /* combinations visited in total */
+  unsigned long long enumerated; /* combinations the device enumerated: the visited ones
+                                 plus those of rounds run ahead speculatively that the stop
+                                 made unnecessary */
+  unsigned long long words;   /* 32-bit words (of D per half) whose weight was evaluated,
+                                 summed over the enumerated combinations: D x enumerated
+                                 without partial weights, less with them */
   double host_ms;             /* input check, basis, diagonalization, planning */
-  double kernel_ms;           /* summed enumeration-kernel time (timing = 1) */
+  double kernel_ms;           /* summed enumeration-kernel time of the visited rounds
+                                 (timing = 1) */
+  double enumerated_kernel_ms; /* the same over every enumerated combination */
   double wall_ms;             /* whole call */
   int launches;               /* enumeration-kernel launches that carried its rounds
                                  (one launch may carry several consecutive rounds) */
@@ -184,7 +197,8 @@ int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma,
  * (Sec. 2.3, packages).  rows: 2P rows of 2n bytes; rows 2i and 2i+1 span
  * package i when dims[i] == 2, row 2i alone when dims[i] == 1.  Writes the
  * minimum symplectic weight (n + 1 when t > P), one codeword reaching it
- * (witness: 2n bytes or NULL) and the number of combinations visited. */
+ * (witness: 2n bytes or NULL) and the number of combinations visited.
+ * Every word of every codeword is evaluated (no partial weights). */
 int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int *wmin,
                  uint8_t *witness, unsigned long long *count);
 

@@ -220,6 +220,7 @@ int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int 
   job.n = n;
   job.single_round = true;
   job.t = t;
+  job.opt.partial_weight = -1;
   Gamma g;
   for (int i = 0; i < P; ++i) {
     if (dims[i] != 1 && dims[i] != 2) return QD_ERR_INVALID;

@@ -299,7 +299,7 @@ void Executor::prepare(Job &job) {
   }
   if (o.seg_len < 0 || o.seg_len % kBlock || o.saved_depth < -1 || o.max_gamma < 0 || o.tops_mode < 0 ||
       o.tops_mode > 2 || (o.filter != QD_FILTER_NONE && o.filter != QD_FILTER_STABILIZER) ||
-      (o.scalar_classes != 0 && o.scalar_classes != -1)) {
+      (o.scalar_classes != 0 && o.scalar_classes != -1) || (o.partial_weight != 0 && o.partial_weight != -1)) {
     job.status = QD_ERR_INVALID;
     return;
   }
@@ -358,21 +358,26 @@ void Executor::prepare_gammas(Job &job) {
   job.L = lower_bound(job.tdone, job.delta, job.halve);
   job.U = n + 1;
   job.gd.assign(h, GammaDev{});
+  // Partial weights need a second word; with them off the qubit order stays.
+  const bool partial = job.opt.partial_weight == 0 && job.D >= 2;
   for (int j = 0; j < h; ++j) {
     GammaDev &g = job.gd[j];
     const Gamma &gm = job.use[j];
     g.P = gm.P();
     g.R = std::min(g.P, kTMax) + 1;
+    g.delta = gm.delta;
+    if (partial) g.order = qubit_order(gm, n, job.halve);
+    const std::vector<unsigned char> &pos = g.order.pos;
     g.h_elems.assign(size_t(g.P) * 3 * kElemWords, 0);
     g.h_csize.assign(g.P, 0);
     for (int i = 0; i < g.P; ++i) {
       const Package &p = gm.pk[i];
-      to_words(p.r, &g.h_elems[size_t(3 * i) * kElemWords]);
+      to_words(permute_row(p.r, pos, n), &g.h_elems[size_t(3 * i) * kElemWords]);
       if (p.dim == 2) {
         BRow rs = p.r;
         radd(rs, p.s);
-        to_words(p.s, &g.h_elems[size_t(3 * i + 1) * kElemWords]);
-        to_words(rs, &g.h_elems[size_t(3 * i + 2) * kElemWords]);
+        to_words(permute_row(p.s, pos, n), &g.h_elems[size_t(3 * i + 1) * kElemWords]);
+        to_words(permute_row(rs, pos, n), &g.h_elems[size_t(3 * i + 2) * kElemWords]);
       }
       g.h_csize[i] = p.dim == 2 ? 3 : 1;
       g.sizes.push_back(g.h_csize[i]);
@@ -414,35 +419,44 @@ int Executor::admit(Job &job, hipStream_t s) {
   std::memset(&hs, 0, sizeof(hs));
   hs.key = (static_cast<unsigned long long>(job.n + 1) << 32) | kNoSlot;
   dirty_slots_.push_back(job.state_slot);
-  // Block layout: counters | per Gamma_j elements and sizes, each 16-byte
-  // aligned as Staging::put places them | per Gamma_j prefix and suffix
-  // tables, which the device computes from the sizes.
+  // Block layout: counters | per Gamma_j elements, sizes, qubit order and
+  // logical operators (both in its stored order), each 16-byte aligned as
+  // Staging::put places them | per Gamma_j prefix and suffix tables, which
+  // the device computes from the sizes.
   const size_t cb = size_t(kCountersPerCode) * kCounterStride * 8;
   const size_t lbytes = job.logicals.size() * kElemWords * 4;
-  size_t a_bytes = lbytes, total = cb + lbytes;
+  size_t a_bytes = 0, total = cb;
   for (const GammaDev &g : job.gd) {
     if (g.R > kWave || g.P > kMaxEsymPackages) return QD_ERR_INTERNAL;
-    a_bytes += align16(g.h_elems.size() * 4) + align16(g.h_csize.size());
-    total += align16(g.h_elems.size() * 4) + align16(g.h_csize.size()) + 2 * g.prefix.size() * 8;
+    const size_t ga = align16(g.h_elems.size() * 4) + align16(g.h_csize.size()) + align16(g.order.pos.size()) +
+                      align16(lbytes);
+    a_bytes += ga;
+    total += ga + 2 * g.prefix.size() * 8;
   }
   if (!alloc(job.data, total)) return QD_ERR_NOMEM;
   unsigned char *dev = static_cast<unsigned char *>(job.data.p);
   recs_.push_back({dev, kZeroFill, cb, 0, 0, 0});
   const size_t o0 = align16(staging_.size());
   unsigned char *a0 = dev + cb, *b = dev + cb + a_bytes;
-  if (lbytes) {
-    std::vector<uint32_t> lw(job.logicals.size() * kElemWords);
-    for (size_t i = 0; i < job.logicals.size(); ++i) to_words(job.logicals[i], &lw[i * kElemWords]);
-    const size_t ol = staging_.put(lw.data(), lbytes);
-    if (ol == SIZE_MAX) return QD_ERR_NOMEM;
-    job.dlogicals = reinterpret_cast<const uint32_t *>(a0 + (ol - o0));
-  }
+  std::vector<uint32_t> lw(job.logicals.size() * kElemWords);
   for (GammaDev &g : job.gd) {
     const size_t oe = staging_.put(g.h_elems.data(), g.h_elems.size() * 4);
     const size_t oc = staging_.put(g.h_csize.data(), g.h_csize.size());
     if (oe == SIZE_MAX || oc == SIZE_MAX) return QD_ERR_NOMEM;
     g.elems = reinterpret_cast<const uint32_t *>(a0 + (oe - o0));
     g.csize = a0 + (oc - o0);
+    if (!g.order.pos.empty()) {
+      const size_t op = staging_.put(g.order.pos.data(), g.order.pos.size());
+      if (op == SIZE_MAX) return QD_ERR_NOMEM;
+      g.inv = a0 + (op - o0);
+    }
+    if (lbytes) {
+      for (size_t i = 0; i < job.logicals.size(); ++i)
+        to_words(permute_row(job.logicals[i], g.order.pos, job.n), &lw[i * kElemWords]);
+      const size_t ol = staging_.put(lw.data(), lbytes);
+      if (ol == SIZE_MAX) return QD_ERR_NOMEM;
+      g.logicals = reinterpret_cast<const uint32_t *>(a0 + (ol - o0));
+    }
     g.dprefix = reinterpret_cast<const unsigned long long *>(b);
     g.dsuffix = g.dprefix + g.prefix.size();
     recs_.push_back({b, kEsymTables, 0, oc, g.P, g.R});
@@ -647,6 +661,8 @@ void Executor::end_round(Job &job, Flight &f) {
   // its rounds in order, each at most its planned size.
   const unsigned long long this_round = std::min<unsigned long long>(hs.count - job.visited, f.planned);
   job.visited += this_round;
+  job.S.enumerated = hs.count;
+  job.S.words = hs.words;
   job.planned_total += f.planned;
   job.tdone[f.j] = f.t;
   job.L = lower_bound(job.tdone, job.delta, job.halve);
@@ -718,8 +734,17 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         d.csize = g.csize;
         d.state = states_ + job.state_slot;
         d.counters = static_cast<unsigned long long *>(job.data.p);
-        d.logicals = job.dlogicals;
+        d.logicals = g.logicals;
         d.nlogicals = int(job.logicals.size());
+        d.inv = g.inv;
+        d.n = job.n;
+        for (int w = 1; w <= 3; ++w) {
+          // Words 0..w-1 hold min(32 w, nonpivot) qubits without pivots.
+          const int q = std::min(32 * w, g.order.nonpivot);
+          const bool on = job.opt.partial_weight == 0 && w < job.D && partial_limit(q) >= 0;
+          d.credit[w - 1] = on ? partial_credit(f.t, g.delta, g.order.kin[w - 1], job.halve) : 0;
+          d.cap[w - 1] = on ? partial_limit(q) + d.credit[w - 1] : -1;
+        }
         d.tile_begin = L.tiles;
         d.ntiles = take;
         d.tile_lo = f.sent;
@@ -801,8 +826,11 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, events_[2 * i], events_[2 * i + 1]) != hipSuccess) return QD_ERR_DEVICE;
     // A launch's time is shared by its pieces in proportion to their tiles.
-    for (size_t d = L.d0; d < L.d1; ++d)
-      members[d].job->fl[members[d].flight].ms += ms * float(descs_[d].ntiles) / float(L.tiles);
+    for (size_t d = L.d0; d < L.d1; ++d) {
+      const float share = ms * float(descs_[d].ntiles) / float(L.tiles);
+      members[d].job->fl[members[d].flight].ms += share;
+      members[d].job->S.enumerated_kernel_ms += share;
+    }
   }
   for (Job *jp : jobs) {
     Job &job = *jp;
@@ -852,7 +880,7 @@ void Executor::retire(Job &job) {
   }
   for (GammaDev &g : job.gd) {
     g.elems = nullptr; g.csize = nullptr; g.dprefix = g.dsuffix = nullptr;
-    job.dlogicals = nullptr;
+    g.inv = nullptr; g.logicals = nullptr;
     for (int u = 0; u <= kTMax; ++u) { release(g.table[u]); release(g.tops[u]); }
   }
   release(job.data);

@@ -52,10 +52,14 @@ struct GammaDev {
   int P = 0, R = 0;
   std::vector<int> sizes;
   std::vector<uint64_t> prefix, suffix;  // e_r tables (host copies)
-  std::vector<uint32_t> h_elems;
+  std::vector<uint32_t> h_elems;         // in the stored qubit order
   std::vector<unsigned char> h_csize;
+  QubitOrder order;                      // stored qubit order (partial weights)
+  int delta = 0;
   const uint32_t *elems = nullptr;
   const unsigned char *csize = nullptr;
+  const unsigned char *inv = nullptr;    // device copy of order.pos (NULL: unchanged)
+  const uint32_t *logicals = nullptr;    // Modified BZ operators in the stored order
   const unsigned long long *dprefix = nullptr, *dsuffix = nullptr;
   PoolBuf table[kTMax + 1], tops[kTMax + 1];
 };
@@ -107,7 +111,6 @@ struct Job {
   bool halve = false;  // isometry matrices: bounds count Hamming weight
   bool scalar = false; // one codeword per F4 scalar class
   std::vector<BRow> logicals;  // Modified BZ: the admission test's operators
-  const uint32_t *dlogicals = nullptr;
   std::vector<GammaDev> gd;
   int state_slot = -1;
   PoolBuf data;  // visited counters, then every Gamma_j's elements and tables

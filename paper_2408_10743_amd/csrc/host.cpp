@@ -547,4 +547,50 @@ PlanChoice choose_plan(const std::vector<Gamma> &f4, const Gamma &f2, const std:
   return pc;
 }
 
+// -- partial weights -----------------------------------------------------------
+
+QubitOrder qubit_order(const Gamma &g, int n, bool iso) {
+  QubitOrder o;
+  std::vector<char> piv(n, 0);
+  for (const Package &p : g.pk)
+    if (p.pivot >= 0) piv[iso ? p.pivot % n : p.pivot] = 1;
+  std::vector<unsigned char> pos(n);
+  int k = 0;
+  for (int q = 0; q < n; ++q)
+    if (!piv[q]) pos[q] = static_cast<unsigned char>(k++);
+  o.nonpivot = k;
+  for (int q = 0; q < n; ++q)
+    if (piv[q]) pos[q] = static_cast<unsigned char>(k++);
+  bool identity = true;
+  for (int q = 0; q < n; ++q) identity = identity && pos[q] == q;
+  for (const Package &p : g.pk) {
+    if (p.pivot < 0) continue;
+    const int at = pos[iso ? p.pivot % n : p.pivot];
+    for (int w = 0; w < 4; ++w) o.kin[w] += at < 32 * (w + 1);
+  }
+  if (!identity) o.pos = std::move(pos);
+  return o;
+}
+
+BRow permute_row(const BRow &r, const std::vector<unsigned char> &pos, int n) {
+  if (pos.empty()) return r;
+  BRow o;
+  for (int q = 0; q < n; ++q) {
+    const int p = pos[q];
+    o.x[p >> 6] |= ((r.x[q >> 6] >> (q & 63)) & 1) << (p & 63);
+    o.z[p >> 6] |= ((r.z[q >> 6] >> (q & 63)) & 1) << (p & 63);
+  }
+  return o;
+}
+
+int partial_credit(int t, int delta, int kin, bool iso) {
+  const int outside = std::max(0, t - delta - kin);
+  return iso ? (outside + 1) / 2 : outside;
+}
+
+int partial_limit(int q) {
+  if (q < 8) return -1;
+  return int(std::floor(0.75 * q - 4.0 * std::sqrt(0.1875 * q)));
+}
+
 }  // namespace qd

@@ -106,6 +106,34 @@ bool make_scalar_orbits(std::vector<Gamma> &gs);
 // whatever the input field): alpha times every basis row lies in the span.
 bool alpha_closed(const std::vector<BRow> &basis, int n);
 
+// Partial weights.  A matrix is stored with the qubits that carry none of
+// its package pivots first, so the first words of a codeword hold its least
+// constrained qubits.  pos[q] is the stored position of qubit q (empty when
+// the order is unchanged); kin[w] counts the packages pivoted at stored
+// positions below 32 (w + 1).  Isometry pivots are image columns; their
+// qubit is the column modulo n.
+struct QubitOrder {
+  std::vector<unsigned char> pos;
+  int nonpivot = 0;
+  int kin[4] = {0, 0, 0, 0};
+};
+QubitOrder qubit_order(const Gamma &g, int n, bool iso);
+BRow permute_row(const BRow &r, const std::vector<unsigned char> &pos, int n);
+
+// Lower bound on the weight of a t-package combination of a matrix outside
+// its first stored words, of which kin packages are pivoted inside them:
+// every chosen package pivoted outside has a nonzero symbol at its own pivot
+// qubit (at most delta chosen packages have no pivot).  Pivot qubits are
+// distinct, except for the isometry matrices, whose pivot columns are
+// linearly independent and so at most two per qubit.
+int partial_credit(int t, int delta, int kin, bool iso);
+
+// The largest threshold below which the weight of q uniformly random
+// qubits (each nonzero with probability 3/4) falls with probability about
+// 3e-5 or less (mean minus four standard deviations); -1 when q < 8.  It
+// only steers the kernel's choice of words, never the result.
+int partial_limit(int q);
+
 // Elementary symmetric polynomials e_r of package sizes (1 or 3) as
 // saturating 64-bit integers.  prefix[h][r] = e_r(c_0..c_{h-1}),
 // suffix[h][r] = e_r(c_h..c_{P-1}); rmax columns + 1.

@@ -45,14 +45,17 @@ struct DevRun {
 };
 
 // Per-code device state: key = (U << 32) | pending slot; count = visited
-// combinations; wit = codeword of weight U (kElemWords words).
+// combinations; words = 32-bit words whose weight was evaluated, summed over
+// the visited combinations; wit = codeword of weight U (kElemWords words).
 struct DevState {
   unsigned long long key;
   unsigned long long count;
+  unsigned long long words;
   uint32_t wit[kElemWords];
 };
 
-// Visited counters per code (separate 128-byte lines).
+// Visited counters per code (separate 128-byte lines); word 0 of a line
+// counts combinations, word 1 the words evaluated for them.
 constexpr int kCountersPerCode = 256;
 
 // One piece of one (code, t, Gamma_j) round inside a launch.  A launch
@@ -70,6 +73,16 @@ struct RoundDesc {
   unsigned long long *counters;        // kCountersPerCode x kCounterStride
   const uint32_t *logicals;            // Modified BZ: logical operators, kElemWords each
   int nlogicals;                       // 0: every codeword may update U
+  // The matrix's qubits are stored permuted: position inv[q] holds qubit q
+  // (NULL: not permuted).  Witnesses are written back in qubit order.
+  const unsigned char *inv;
+  int n;
+  // Partial weights: the weight of words 0..w-1 plus credit[w-1] bounds a
+  // codeword's weight from below.  A tile that starts with U <= cap[w-1]
+  // (smallest such w) evaluates w words first and the rest only for blocks
+  // where some bound is below U; cap -1 disables w.
+  int cap[3];
+  int credit[3];
   unsigned long long tile_begin;       // first launch tile of the piece
   unsigned long long ntiles;           // tiles of the piece
   unsigned long long tile_lo;          // round tile of the piece's first tile

@@ -9,6 +9,14 @@
 // VGPRs; the wavefront streams a segment of the table through SGPRs (all
 // lanes read the same entry), so each codeword costs one XOR per x word,
 // one fused XOR-OR (v_bitop3) per z word, one v_bcnt per word and one MIN.
+//
+// Partial weights.  The host stores each matrix with the qubits that carry
+// none of its pivots first.  Every package of a combination has a nonzero
+// symbol at its own pivot qubit, so the weight of the first w words plus
+// the chosen packages pivoted beyond them (a per-round credit) bounds the
+// weight from below.  Once U is small enough, a tile evaluates w words per
+// codeword and the remaining words only for the blocks where some bound is
+// below U: the other codewords cannot improve U.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -77,6 +85,95 @@ __device__ __forceinline__ uint32_t block_min(const uint32_t (&ax)[D], const uin
 #pragma unroll
   for (int e = 0; e < kBlock; e += 2) best = min3(best, w[e], w[e + 1]);
   return best;
+}
+
+// One block with partial weights: words 0..W-1 first; if some lane's bound
+// (partial weight + credit) falls below U (thr = U - credit), the block's
+// remaining words are added and its full weights enter `best`.  `rec`
+// counts such blocks.
+template <int D, int W>
+__device__ __forceinline__ uint32_t block_min_partial(const uint32_t (&ax)[D], const uint32_t (&az)[D],
+                                                      const uint32_t *__restrict__ blk, uint32_t best,
+                                                      uint32_t thr, uint32_t &rec) {
+  uint32_t w[kBlock];
+  {
+    uint32_t v[2 * W][kBlock];
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+#pragma unroll
+      for (int e = 0; e < kBlock; ++e) {
+        v[j][e] = blk[j * kBlock + e];
+        v[W + j][e] = blk[(D + j) * kBlock + e];
+      }
+#pragma unroll
+    for (int e = 0; e < kBlock; ++e) {
+      uint32_t acc = 0;
+#pragma unroll
+      for (int d = 0; d < W; ++d) {
+        uint32_t o = (ax[d] ^ v[d][e]) | (az[d] ^ v[W + d][e]);
+        acc = d == 0 ? __builtin_popcount(o) : bcnt_acc(o, acc);
+      }
+      w[e] = acc;
+    }
+  }
+  uint32_t pm = min3(w[0], w[1], w[2]);
+  pm = min3(pm, w[3], w[4]);
+  pm = min3(pm, w[5], w[6]);
+  pm = min(pm, w[7]);
+  if (__ballot(pm < thr)) {  // rare once U is small: the block is evaluated in full
+    uint32_t v[2 * (D - W)][kBlock];
+#pragma unroll
+    for (int j = 0; j < D - W; ++j)
+#pragma unroll
+      for (int e = 0; e < kBlock; ++e) {
+        v[j][e] = blk[(W + j) * kBlock + e];
+        v[D - W + j][e] = blk[(D + W + j) * kBlock + e];
+      }
+#pragma unroll
+    for (int e = 0; e < kBlock; ++e) {
+#pragma unroll
+      for (int d = 0; d < D - W; ++d) {
+        uint32_t o = (ax[W + d] ^ v[d][e]) | (az[W + d] ^ v[D - W + d][e]);
+        w[e] = bcnt_acc(o, w[e]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kBlock; e += 2) best = min3(best, w[e], w[e + 1]);
+    ++rec;
+  }
+  return best;
+}
+
+// Writes a codeword given in a matrix's stored qubit order to `out`
+// (kElemWords words) in qubit order: qubit q is at position inv[q].
+template <int D>
+__device__ void store_codeword(uint32_t *out, const uint32_t (&cx)[D], const uint32_t (&cz)[D],
+                               const unsigned char *inv, int n) {
+#pragma unroll
+  for (int ow = 0; ow < 4; ++ow) {
+    uint32_t ox = 0, oz = 0;
+    if (ow < D) {
+      if (!inv) {
+        ox = cx[ow < D ? ow : 0];
+        oz = cz[ow < D ? ow : 0];
+      } else {
+        for (int b = 0; b < 32 && 32 * ow + b < n; ++b) {
+          const uint32_t src = inv[32 * ow + b];
+          uint32_t wx = cx[0], wz = cz[0];
+#pragma unroll
+          for (int d = 1; d < D; ++d)
+            if ((src >> 5) == static_cast<uint32_t>(d)) {
+              wx = cx[d];
+              wz = cz[d];
+            }
+          ox |= ((wx >> (src & 31)) & 1u) << b;
+          oz |= ((wz >> (src & 31)) & 1u) << b;
+        }
+      }
+    }
+    out[ow] = ox;
+    out[4 + ow] = oz;
+  }
 }
 
 // Top combination number `item` of the group whose smallest package is h:
@@ -249,7 +346,35 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   uint32_t best = 0xFFFFFFFFu;
   const uint32_t nfull = sfull / kBlock;
   const uint32_t *blk = p.table + (k0 / kBlock) * (2 * D * kBlock);
-  for (uint32_t i = 0; i < nfull; ++i, blk += 2 * D * kBlock) best = block_min<D>(ax, az, blk, best);
+  // Words evaluated per codeword in the full blocks: the smallest w whose
+  // cap admits the U this tile started with (D: no partial weights).
+  const int U0 = static_cast<int>(key >> 32);
+  int W = D;
+#pragma unroll
+  for (int w = D - 1; w >= 1; --w)
+    if (U0 <= p.cap[w - 1]) W = w;
+  uint32_t rec = 0;  // full blocks evaluated in full
+  if (W == D) {
+    for (uint32_t i = 0; i < nfull; ++i, blk += 2 * D * kBlock) best = block_min<D>(ax, az, blk, best);
+  } else {
+    const int c = p.credit[W - 1];
+    const uint32_t thr = U0 > c ? static_cast<uint32_t>(U0 - c) : 0u;
+    if constexpr (D >= 2) {
+      if (W == 1)
+        for (uint32_t i = 0; i < nfull; ++i, blk += 2 * D * kBlock)
+          best = block_min_partial<D, 1>(ax, az, blk, best, thr, rec);
+    }
+    if constexpr (D >= 3) {
+      if (W == 2)
+        for (uint32_t i = 0; i < nfull; ++i, blk += 2 * D * kBlock)
+          best = block_min_partial<D, 2>(ax, az, blk, best, thr, rec);
+    }
+    if constexpr (D >= 4) {
+      if (W == 3)
+        for (uint32_t i = 0; i < nfull; ++i, blk += 2 * D * kBlock)
+          best = block_min_partial<D, 3>(ax, az, blk, best, thr, rec);
+    }
+  }
   for (uint32_t i = nfull * kBlock; i < send; ++i) {
     const uint32_t w = weight_at<D>(p.table, k0 + i, ax, az);
     if (i < span) best = min(best, w);
@@ -257,9 +382,15 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   if (!active) best = 0xFFFFFFFFu;
   const uint32_t wmin = wave_min(best);
   const uint32_t visited = wave_sum(active ? span : 0u);
-  if (lane == 0)
-    atomicAdd(p.counters + static_cast<size_t>(wg % kCountersPerCode) * kCounterStride,
-              static_cast<unsigned long long>(visited));
+  const unsigned long long nact = __popcll(__ballot(active));  // outside the lane-0 branch
+  if (lane == 0) {
+    // Words: D per visited codeword, less D - W for those of the full
+    // blocks that the partial weights decided.
+    const unsigned long long skipped = static_cast<unsigned long long>(nfull - rec) * kBlock * (D - W) * nact;
+    unsigned long long *c = p.counters + static_cast<size_t>(wg % kCountersPerCode) * kCounterStride;
+    atomicAdd(c, static_cast<unsigned long long>(visited));
+    atomicAdd(c + 1, static_cast<unsigned long long>(visited) * D - skipped);
+  }
 
   key = uniform64(*reinterpret_cast<volatile unsigned long long *>(&st->key));
   if (p.nlogicals > 0) {
@@ -292,14 +423,15 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
     const int winner = __ffsll(static_cast<long long>(mask)) - 1;
     if (static_cast<int>(lane) == winner) {
       const uint32_t slot = static_cast<uint32_t>(p.slot0 + local);
-      uint32_t *out = lp.slots + static_cast<size_t>(slot) * kElemWords;
       const unsigned long long kk = k0 + kf;
       const uint32_t *e = p.table + (kk / kBlock) * (2 * D * kBlock) + (kk % kBlock);
+      uint32_t cx[D], cz[D];
 #pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        out[d] = d < D ? (ax[d] ^ e[d * kBlock]) : 0u;
-        out[4 + d] = d < D ? (az[d] ^ e[(D + d) * kBlock]) : 0u;
+      for (int d = 0; d < D; ++d) {
+        cx[d] = ax[d] ^ e[d * kBlock];
+        cz[d] = az[d] ^ e[(D + d) * kBlock];
       }
+      store_codeword<D>(lp.slots + static_cast<size_t>(slot) * kElemWords, cx, cz, p.inv, p.n);
       atomicMin(&st->key, (static_cast<unsigned long long>(wadm) << 32) | slot);
     }
     return;
@@ -316,14 +448,15 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
     const int winner = __ffsll(static_cast<long long>(mask)) - 1;
     if (static_cast<int>(lane) == winner) {
       const uint32_t slot = static_cast<uint32_t>(p.slot0 + local);  // launch-wide slot
-      uint32_t *out = lp.slots + static_cast<size_t>(slot) * kElemWords;
       const unsigned long long kk = k0 + kf;
       const uint32_t *e = p.table + (kk / kBlock) * (2 * D * kBlock) + (kk % kBlock);
+      uint32_t cx[D], cz[D];
 #pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        out[d] = d < D ? (ax[d] ^ e[d * kBlock]) : 0u;
-        out[4 + d] = d < D ? (az[d] ^ e[(D + d) * kBlock]) : 0u;
+      for (int d = 0; d < D; ++d) {
+        cx[d] = ax[d] ^ e[d * kBlock];
+        cz[d] = az[d] ^ e[(D + d) * kBlock];
       }
+      store_codeword<D>(lp.slots + static_cast<size_t>(slot) * kElemWords, cx, cz, p.inv, p.n);
       atomicMin(&st->key, (static_cast<unsigned long long>(wmin) << 32) | slot);
     }
   }

@@ -84,25 +84,32 @@ __global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
 
 // After a launch, one workgroup per code (its first piece): moves the
 // codeword of the winning slot into the code's state and folds the code's
-// spread counters into its visited count.
+// spread counters into its visited and evaluated-word counts.
 __global__ __launch_bounds__(256) void qd_commit_kernel(LaunchParams lp) {
-  __shared__ unsigned long long part[256];
+  __shared__ unsigned long long part[2][256];
   const RoundDesc &p = lp.desc[blockIdx.x];
   if (!p.commit) return;  // another piece of the same code commits it
-  unsigned long long sum = 0;
+  unsigned long long sum = 0, words = 0;
   for (int i = threadIdx.x; i < kCountersPerCode; i += blockDim.x) {
-    sum += p.counters[static_cast<size_t>(i) * kCounterStride];
-    p.counters[static_cast<size_t>(i) * kCounterStride] = 0;
+    unsigned long long *c = p.counters + static_cast<size_t>(i) * kCounterStride;
+    sum += c[0];
+    words += c[1];
+    c[0] = c[1] = 0;
   }
-  part[threadIdx.x] = sum;
+  part[0][threadIdx.x] = sum;
+  part[1][threadIdx.x] = words;
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (static_cast<int>(threadIdx.x) < w) part[threadIdx.x] += part[threadIdx.x + w];
+    if (static_cast<int>(threadIdx.x) < w) {
+      part[0][threadIdx.x] += part[0][threadIdx.x + w];
+      part[1][threadIdx.x] += part[1][threadIdx.x + w];
+    }
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
   DevState *st = p.state;
-  st->count += part[0];
+  st->count += part[0][0];
+  st->words += part[1][0];
   const unsigned long long key = st->key;
   const uint32_t slot = static_cast<uint32_t>(key & 0xFFFFFFFFull);
   if (slot == kNoSlot) return;

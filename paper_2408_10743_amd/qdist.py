@@ -48,7 +48,8 @@ class qd_options(ctypes.Structure):
                 ("budget", ctypes.c_ulonglong), ("cancel", ctypes.POINTER(ctypes.c_int)),
                 ("stream", ctypes.c_void_p), ("seg_len", ctypes.c_int),
                 ("saved_depth", ctypes.c_int), ("timing", ctypes.c_int), ("tops_mode", ctypes.c_int),
-                ("filter", ctypes.c_int), ("scalar_classes", ctypes.c_int)]
+                ("filter", ctypes.c_int), ("scalar_classes", ctypes.c_int),
+                ("partial_weight", ctypes.c_int)]
 
 
 class qd_round_log(ctypes.Structure):
@@ -63,8 +64,10 @@ class qd_stats(ctypes.Structure):
                 ("h", ctypes.c_int), ("P", ctypes.c_int * QD_MAX_GAMMA),
                 ("delta", ctypes.c_int * QD_MAX_GAMMA), ("L", ctypes.c_int), ("U", ctypes.c_int),
                 ("d_estimate", ctypes.c_int), ("predicted", ctypes.c_double),
-                ("combinations", ctypes.c_ulonglong), ("host_ms", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
+                ("combinations", ctypes.c_ulonglong), ("enumerated", ctypes.c_ulonglong),
+                ("words", ctypes.c_ulonglong), ("host_ms", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double), ("enumerated_kernel_ms", ctypes.c_double),
+                ("wall_ms", ctypes.c_double),
                 ("launches", ctypes.c_int), ("logical_pairs", ctypes.c_int),
                 ("scalar_classes", ctypes.c_int), ("nlog", ctypes.c_int),
                 ("log", qd_round_log * QD_MAX_LOG)]
@@ -170,7 +173,7 @@ def qd_distance(G, field=QD_FIELD_F2):
 def qd_distance_ex(G, field=QD_FIELD_F2, **opts):
     """Returns (status, d, witness, qd_stats).  Options: diag, max_gamma,
     budget, cancel (ctypes.c_int), stream (hipStream_t as int), seg_len,
-    saved_depth, timing, tops_mode."""
+    saved_depth, timing, tops_mode, filter, scalar_classes, partial_weight."""
     G, m, n = _matrix(G, field)
     o, _keep = _options(opts)
     d = ctypes.c_int(-1)
