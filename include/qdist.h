@@ -94,11 +94,14 @@ typedef struct qd_options {
                                  under alpha) with the F4 construction: 0 enumerate one
                                  codeword of each class {c, alpha c, alpha^2 c} (equal
                                  weights, a third of the work); -1 all */
-  int partial_weight;         /* 0: once U is small enough, decide a codeword from the
-                                 weight of its first words plus the pivots its packages
-                                 must hit beyond them, and evaluate the rest only where
-                                 that bound is below U (same d and witness rules);
-                                 -1: evaluate every word of every codeword */
+  int partial_weight;         /* Partial weights: once U is small enough, decide a codeword
+                                 from the weight of its first words plus the pivots its
+                                 packages must hit beyond them, and evaluate the rest only
+                                 where that bound is below U (same d and witness rules).
+                                 0: for codes of two or more words per half whose planned
+                                 work reaches 1e8 combinations; 1: for every code of two or
+                                 more words per half; -1: never (every word of every
+                                 codeword is evaluated) */
 } qd_options;
 
 /* One (t, Gamma_j) round of the enumeration. */

@@ -23,6 +23,8 @@ constexpr unsigned long long kMaxTopEntries = 1ull << 24;  // 512 MB of tops
 constexpr unsigned long long kTilesPerLaunch = 1ull << 21;
 constexpr unsigned long long kTargetTiles = 1ull << 18;    // ~32 tiles per wave slot
 constexpr unsigned kMinSeg = 256, kMaxSeg = 4096;
+// Partial weights for codes whose planned work reaches this many combinations.
+constexpr double kPartialMinWork = 1e8;
 constexpr unsigned kStageMaxBytes = 32768;
 // Rounds of a code are grouped into one step while the step's total stays
 // below the executor's limit (kSpecCombos unless set_spec_combos changed it).
@@ -299,7 +301,7 @@ void Executor::prepare(Job &job) {
   }
   if (o.seg_len < 0 || o.seg_len % kBlock || o.saved_depth < -1 || o.max_gamma < 0 || o.tops_mode < 0 ||
       o.tops_mode > 2 || (o.filter != QD_FILTER_NONE && o.filter != QD_FILTER_STABILIZER) ||
-      (o.scalar_classes != 0 && o.scalar_classes != -1) || (o.partial_weight != 0 && o.partial_weight != -1)) {
+      (o.scalar_classes != 0 && o.scalar_classes != -1) || (o.partial_weight < -1 || o.partial_weight > 1)) {
     job.status = QD_ERR_INVALID;
     return;
   }
@@ -358,26 +360,28 @@ void Executor::prepare_gammas(Job &job) {
   job.L = lower_bound(job.tdone, job.delta, job.halve);
   job.U = n + 1;
   job.gd.assign(h, GammaDev{});
-  // Partial weights need a second word; with them off the qubit order stays.
-  const bool partial = job.opt.partial_weight == 0 && job.D >= 2;
+  // Partial weights need a second word, and pay only for codes with enough
+  // work to outweigh reordering the matrices; with them off the qubit order
+  // stays.
+  job.partial = job.D >= 2 && (job.opt.partial_weight == 1 ||
+                               (job.opt.partial_weight == 0 && job.pc.predicted >= kPartialMinWork));
   for (int j = 0; j < h; ++j) {
     GammaDev &g = job.gd[j];
     const Gamma &gm = job.use[j];
     g.P = gm.P();
     g.R = std::min(g.P, kTMax) + 1;
     g.delta = gm.delta;
-    if (partial) g.order = qubit_order(gm, n, job.halve);
-    const std::vector<unsigned char> &pos = g.order.pos;
+    if (job.partial) g.order = qubit_order(gm, n, job.halve);
     g.h_elems.assign(size_t(g.P) * 3 * kElemWords, 0);
     g.h_csize.assign(g.P, 0);
     for (int i = 0; i < g.P; ++i) {
       const Package &p = gm.pk[i];
-      to_words(permute_row(p.r, pos, n), &g.h_elems[size_t(3 * i) * kElemWords]);
+      to_words(permute_row(p.r, g.order), &g.h_elems[size_t(3 * i) * kElemWords]);
       if (p.dim == 2) {
         BRow rs = p.r;
         radd(rs, p.s);
-        to_words(permute_row(p.s, pos, n), &g.h_elems[size_t(3 * i + 1) * kElemWords]);
-        to_words(permute_row(rs, pos, n), &g.h_elems[size_t(3 * i + 2) * kElemWords]);
+        to_words(permute_row(p.s, g.order), &g.h_elems[size_t(3 * i + 1) * kElemWords]);
+        to_words(permute_row(rs, g.order), &g.h_elems[size_t(3 * i + 2) * kElemWords]);
       }
       g.h_csize[i] = p.dim == 2 ? 3 : 1;
       g.sizes.push_back(g.h_csize[i]);
@@ -452,7 +456,7 @@ int Executor::admit(Job &job, hipStream_t s) {
     }
     if (lbytes) {
       for (size_t i = 0; i < job.logicals.size(); ++i)
-        to_words(permute_row(job.logicals[i], g.order.pos, job.n), &lw[i * kElemWords]);
+        to_words(permute_row(job.logicals[i], g.order), &lw[i * kElemWords]);
       const size_t ol = staging_.put(lw.data(), lbytes);
       if (ol == SIZE_MAX) return QD_ERR_NOMEM;
       g.logicals = reinterpret_cast<const uint32_t *>(a0 + (ol - o0));
@@ -741,7 +745,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         for (int w = 1; w <= 3; ++w) {
           // Words 0..w-1 hold min(32 w, nonpivot) qubits without pivots.
           const int q = std::min(32 * w, g.order.nonpivot);
-          const bool on = job.opt.partial_weight == 0 && w < job.D && partial_limit(q) >= 0;
+          const bool on = job.partial && w < job.D && partial_limit(q) >= 0;
           d.credit[w - 1] = on ? partial_credit(f.t, g.delta, g.order.kin[w - 1], job.halve) : 0;
           d.cap[w - 1] = on ? partial_limit(q) + d.credit[w - 1] : -1;
         }

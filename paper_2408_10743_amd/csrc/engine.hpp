@@ -110,6 +110,7 @@ struct Job {
   PlanChoice pc;
   bool halve = false;  // isometry matrices: bounds count Hamming weight
   bool scalar = false; // one codeword per F4 scalar class
+  bool partial = false; // partial weights (matrices stored in their qubit order)
   std::vector<BRow> logicals;  // Modified BZ: the admission test's operators
   std::vector<GammaDev> gd;
   int state_slot = -1;

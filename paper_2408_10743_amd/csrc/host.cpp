@@ -568,19 +568,35 @@ QubitOrder qubit_order(const Gamma &g, int n, bool iso) {
     const int at = pos[iso ? p.pivot % n : p.pivot];
     for (int w = 0; w < 4; ++w) o.kin[w] += at < 32 * (w + 1);
   }
-  if (!identity) o.pos = std::move(pos);
+  if (identity) return o;
+  o.pos = std::move(pos);
+  for (int q = 0; q < n; ++q) {
+    if (!o.runs.empty()) {
+      QubitOrder::Run &b = o.runs.back();
+      if (q == b.src + b.len && o.pos[q] == b.dst + b.len) {
+        ++b.len;
+        continue;
+      }
+    }
+    o.runs.push_back({q, 1, int(o.pos[q])});
+  }
   return o;
 }
 
-BRow permute_row(const BRow &r, const std::vector<unsigned char> &pos, int n) {
-  if (pos.empty()) return r;
-  BRow o;
-  for (int q = 0; q < n; ++q) {
-    const int p = pos[q];
-    o.x[p >> 6] |= ((r.x[q >> 6] >> (q & 63)) & 1) << (p & 63);
-    o.z[p >> 6] |= ((r.z[q >> 6] >> (q & 63)) & 1) << (p & 63);
+BRow permute_row(const BRow &r, const QubitOrder &o) {
+  if (o.pos.empty()) return r;
+  using u128 = unsigned __int128;
+  const u128 x = (u128(r.x[1]) << 64) | r.x[0], z = (u128(r.z[1]) << 64) | r.z[0];
+  u128 ox = 0, oz = 0;
+  for (const QubitOrder::Run &run : o.runs) {
+    const u128 m = run.len >= 128 ? ~u128(0) : (u128(1) << run.len) - 1;
+    ox |= ((x >> run.src) & m) << run.dst;
+    oz |= ((z >> run.src) & m) << run.dst;
   }
-  return o;
+  BRow out;
+  out.x[0] = uint64_t(ox); out.x[1] = uint64_t(ox >> 64);
+  out.z[0] = uint64_t(oz); out.z[1] = uint64_t(oz >> 64);
+  return out;
 }
 
 int partial_credit(int t, int delta, int kin, bool iso) {

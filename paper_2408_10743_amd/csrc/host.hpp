@@ -113,12 +113,16 @@ bool alpha_closed(const std::vector<BRow> &basis, int n);
 // positions below 32 (w + 1).  Isometry pivots are image columns; their
 // qubit is the column modulo n.
 struct QubitOrder {
+  struct Run {
+    int src, len, dst;  // qubits src..src+len-1 go to positions dst..dst+len-1
+  };
   std::vector<unsigned char> pos;
+  std::vector<Run> runs;  // the same map as maximal runs of consecutive qubits
   int nonpivot = 0;
   int kin[4] = {0, 0, 0, 0};
 };
 QubitOrder qubit_order(const Gamma &g, int n, bool iso);
-BRow permute_row(const BRow &r, const std::vector<unsigned char> &pos, int n);
+BRow permute_row(const BRow &r, const QubitOrder &o);
 
 // Lower bound on the weight of a t-package combination of a matrix outside
 // its first stored words, of which kin packages are pivoted inside them:

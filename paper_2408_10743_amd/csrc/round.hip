@@ -144,35 +144,14 @@ __device__ __forceinline__ uint32_t block_min_partial(const uint32_t (&ax)[D], c
   return best;
 }
 
-// Writes a codeword given in a matrix's stored qubit order to `out`
-// (kElemWords words) in qubit order: qubit q is at position inv[q].
+// A tile's witness slot: the codeword in the matrix's stored qubit order
+// (the commit kernel maps it back to qubit order).
 template <int D>
-__device__ void store_codeword(uint32_t *out, const uint32_t (&cx)[D], const uint32_t (&cz)[D],
-                               const unsigned char *inv, int n) {
+__device__ __forceinline__ void write_slot(uint32_t *out, const uint32_t (&cx)[D], const uint32_t (&cz)[D]) {
 #pragma unroll
-  for (int ow = 0; ow < 4; ++ow) {
-    uint32_t ox = 0, oz = 0;
-    if (ow < D) {
-      if (!inv) {
-        ox = cx[ow < D ? ow : 0];
-        oz = cz[ow < D ? ow : 0];
-      } else {
-        for (int b = 0; b < 32 && 32 * ow + b < n; ++b) {
-          const uint32_t src = inv[32 * ow + b];
-          uint32_t wx = cx[0], wz = cz[0];
-#pragma unroll
-          for (int d = 1; d < D; ++d)
-            if ((src >> 5) == static_cast<uint32_t>(d)) {
-              wx = cx[d];
-              wz = cz[d];
-            }
-          ox |= ((wx >> (src & 31)) & 1u) << b;
-          oz |= ((wz >> (src & 31)) & 1u) << b;
-        }
-      }
-    }
-    out[ow] = ox;
-    out[4 + ow] = oz;
+  for (int d = 0; d < 4; ++d) {
+    out[d] = d < D ? cx[d < D ? d : 0] : 0u;
+    out[4 + d] = d < D ? cz[d < D ? d : 0] : 0u;
   }
 }
 
@@ -431,7 +410,7 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
         cx[d] = ax[d] ^ e[d * kBlock];
         cz[d] = az[d] ^ e[(D + d) * kBlock];
       }
-      store_codeword<D>(lp.slots + static_cast<size_t>(slot) * kElemWords, cx, cz, p.inv, p.n);
+      write_slot<D>(lp.slots + static_cast<size_t>(slot) * kElemWords, cx, cz);
       atomicMin(&st->key, (static_cast<unsigned long long>(wadm) << 32) | slot);
     }
     return;
@@ -456,7 +435,7 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
         cx[d] = ax[d] ^ e[d * kBlock];
         cz[d] = az[d] ^ e[(D + d) * kBlock];
       }
-      store_codeword<D>(lp.slots + static_cast<size_t>(slot) * kElemWords, cx, cz, p.inv, p.n);
+      write_slot<D>(lp.slots + static_cast<size_t>(slot) * kElemWords, cx, cz);
       atomicMin(&st->key, (static_cast<unsigned long long>(wmin) << 32) | slot);
     }
   }

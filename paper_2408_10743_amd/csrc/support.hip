@@ -83,8 +83,9 @@ __global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
 }
 
 // After a launch, one workgroup per code (its first piece): moves the
-// codeword of the winning slot into the code's state and folds the code's
-// spread counters into its visited and evaluated-word counts.
+// codeword of the winning slot into the code's state, in qubit order, and
+// folds the code's spread counters into its visited and evaluated-word
+// counts.
 __global__ __launch_bounds__(256) void qd_commit_kernel(LaunchParams lp) {
   __shared__ unsigned long long part[2][256];
   const RoundDesc &p = lp.desc[blockIdx.x];
@@ -106,16 +107,44 @@ __global__ __launch_bounds__(256) void qd_commit_kernel(LaunchParams lp) {
     }
     __syncthreads();
   }
-  if (threadIdx.x != 0) return;
   DevState *st = p.state;
-  st->count += part[0][0];
-  st->words += part[1][0];
   const unsigned long long key = st->key;
   const uint32_t slot = static_cast<uint32_t>(key & 0xFFFFFFFFull);
+  if (threadIdx.x == 0) {
+    st->count += part[0][0];
+    st->words += part[1][0];
+  }
   if (slot == kNoSlot) return;
-#pragma unroll
-  for (int w = 0; w < kElemWords; ++w) st->wit[w] = lp.slots[static_cast<size_t>(slot) * kElemWords + w];
-  st->key = (key & ~0xFFFFFFFFull) | kNoSlot;
+  // The slot holds the codeword in the stored qubit order of the matrix of
+  // the piece that wrote it (slots are launch tiles; pieces are sorted by
+  // their first tile).  Thread q < 128 moves qubit q back: it sits at
+  // position inv[q].
+  int lo = 0, hi = lp.ndesc;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (lp.desc[mid].slot0 <= slot) lo = mid;
+    else hi = mid;
+  }
+  const RoundDesc &w = lp.desc[lo];
+  const uint32_t *src = lp.slots + static_cast<size_t>(slot) * kElemWords;
+  const int q = static_cast<int>(threadIdx.x);
+  if (!w.inv) {
+    if (q < kElemWords) st->wit[q] = src[q];
+  } else if (q < 128) {
+    const int from = q < w.n ? w.inv[q] : -1;
+    const bool bx = from >= 0 && ((src[from >> 5] >> (from & 31)) & 1u);
+    const bool bz = from >= 0 && ((src[4 + (from >> 5)] >> (from & 31)) & 1u);
+    const unsigned long long mx = __ballot(bx), mz = __ballot(bz);
+    if ((q & 63) == 0) {  // lane 0 of waves 0 and 1: qubits 64 (q / 64) .. + 63
+      const int wd = 2 * (q >> 6);
+      st->wit[wd] = static_cast<uint32_t>(mx);
+      st->wit[wd + 1] = static_cast<uint32_t>(mx >> 32);
+      st->wit[4 + wd] = static_cast<uint32_t>(mz);
+      st->wit[4 + wd + 1] = static_cast<uint32_t>(mz >> 32);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) st->key = (key & ~0xFFFFFFFFull) | kNoSlot;
 }
 
 // Lane l gets lane l-1's value, lane 0 gets 0 (DPP wave_shr:1).

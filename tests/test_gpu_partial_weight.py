@@ -1,5 +1,6 @@
 """GPU parity of the partial-weight path: every result with partial weights
-(the default) equals the oracle's and the result with every word evaluated
+(forced on for every code of two or more words per half, and automatic)
+equals the oracle's and the result with every word evaluated
 (partial_weight = -1), for each construction, the Modified BZ filter and
 batches; the evaluated-word count shows which path ran."""
 import json
@@ -30,11 +31,12 @@ def swt(v):
 
 
 def both(Q, G, f, d_ref, **opts):
-    """Runs with and without partial weights; both must give d_ref and a
-    valid witness.  Returns the two stats."""
+    """Runs with partial weights forced on (1), automatic (0) and off (-1);
+    all must give d_ref and a valid witness.  Returns the stats of the
+    forced and the off runs."""
     out = []
     B = O.expand(G, f)
-    for pw in (0, -1):
+    for pw in (1, 0, -1):
         st, d, wit, s = Q.qd_distance_ex(G, f, partial_weight=pw, **opts)
         assert st == 0, Q.qd_strerror(st)
         assert d == d_ref, (pw, d, d_ref)
@@ -44,7 +46,8 @@ def both(Q, G, f, d_ref, **opts):
             assert s.words == s.D * s.enumerated
         else:
             assert s.words <= s.D * s.enumerated
-        out.append(s)
+        if pw != 0:
+            out.append(s)
     return out
 
 
@@ -121,7 +124,7 @@ def test_batch_partial_equals_full(Q):
             codes.append((W.additive(n, n + rng.uniform_int(-6, 6), rng.next()), 2))
     budget = int(2e10)
     res = {}
-    for pw in (0, -1):
+    for pw in (1, -1):
         print(f"batch of {len(codes)}, partial_weight {pw}", flush=True)
         st, ds, wits, sts, stats = Q.qd_distance_batch(codes, budget=budget, partial_weight=pw)
         assert st == 0 and all(x in (0, Q.QD_INCOMPLETE) for x in sts)
@@ -129,6 +132,6 @@ def test_batch_partial_equals_full(Q):
             assert swt(w) == d and O.in_rowspace(O.expand(G, f), w)
         res[pw] = (ds, sts)
     for i in range(len(codes)):
-        if res[0][1][i] == 0 and res[-1][1][i] == 0:
-            assert res[0][0][i] == res[-1][0][i], i
-    assert sum(1 for x in res[0][1] if x == 0) >= len(codes) // 2
+        if res[1][1][i] == 0 and res[-1][1][i] == 0:
+            assert res[1][0][i] == res[-1][0][i], i
+    assert sum(1 for x in res[1][1] if x == 0) >= len(codes) // 2
