@@ -102,6 +102,12 @@ typedef struct qd_options {
                                  work reaches 1e8 combinations; 1: for every code of two or
                                  more words per half; -1: never (every word of every
                                  codeword is evaluated) */
+  int mixed_packages;         /* Additive codes with fewer independent rows than qubits, F4
+                                 construction: 0 let the planner cap the two-row packages of
+                                 the first two matrices (one-row packages spend the unused
+                                 qubits) when that lowers the predicted work by 5% or more
+                                 and the work reaches 1e10 combinations; 1 the same at any
+                                 work; -1 never (two-row packages first, Sec. 2.3) */
 } qd_options;
 
 /* One (t, Gamma_j) round of the enumeration. */
@@ -142,6 +148,8 @@ typedef struct qd_stats {
   int logical_pairs;          /* QD_FILTER_STABILIZER: k, the logical operator pairs
                                  the admission test uses (0: no filter applied) */
   int scalar_classes;         /* 1: one codeword per F4 scalar class was enumerated */
+  int two_row_cap[QD_MAX_GAMMA]; /* mixed packages: matrix j has at most this many two-row
+                                 packages pivoted inside its set (-1: no cap) */
   int nlog;                   /* rounds run (entries in log, capped at QD_MAX_LOG) */
   qd_round_log log[QD_MAX_LOG];
 } qd_stats;
@@ -161,6 +169,9 @@ typedef struct qd_plan_info {
   int d_estimate;
   double predicted_f2, predicted_f4;      /* predicted combinations per construction */
   double predicted_iso;
+  int f4_two_row_cap[QD_MAX_GAMMA];       /* F4 matrices: the planner's cap on two-row packages
+                                             (mixed packages, qd_options.mixed_packages = 0;
+                                             -1: no cap) */
   int f4_scalar_classes;                  /* 1: the code is F4-linear, so the F4 prediction
                                              counts one codeword per scalar class */
 } qd_plan_info;

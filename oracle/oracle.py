@@ -107,8 +107,10 @@ def brute_iso_hamming(B):
     return dH.value
 
 
-def gamma(B, diag=DIAG_F4, max_gamma=8, with_rows=False):
-    """Generator matrices: list of dicts {P, delta, dims, pivots[, rows]}."""
+def gamma(B, diag=DIAG_F4, max_gamma=8, with_rows=False, max2=None):
+    """Generator matrices: list of dicts {P, delta, dims, pivots[, rows]}.
+    max2 (F4 only): per-matrix caps on two-row packages (mixed packages;
+    -1 or missing entries: no cap)."""
     B, p = _u8(B)
     m, n = B.shape[0], B.shape[1] // 2
     cap = 2 * n
@@ -118,10 +120,18 @@ def gamma(B, diag=DIAG_F4, max_gamma=8, with_rows=False):
     dims = np.zeros(max_gamma * cap, dtype=np.int32)
     piv = np.zeros(max_gamma * cap, dtype=np.int32)
     rows = np.zeros((max_gamma * cap * 2, 2 * n), dtype=np.uint8) if with_rows else None
-    rc = lib().qdo_gamma(p, m, n, diag, max_gamma, cap, ctypes.byref(h),
-                         P.ctypes.data_as(_ip), delta.ctypes.data_as(_ip),
-                         dims.ctypes.data_as(_ip), piv.ctypes.data_as(_ip),
-                         rows.ctypes.data_as(_u8p) if with_rows else None)
+    if max2 is None:
+        rc = lib().qdo_gamma(p, m, n, diag, max_gamma, cap, ctypes.byref(h),
+                             P.ctypes.data_as(_ip), delta.ctypes.data_as(_ip),
+                             dims.ctypes.data_as(_ip), piv.ctypes.data_as(_ip),
+                             rows.ctypes.data_as(_u8p) if with_rows else None)
+    else:
+        assert diag == DIAG_F4
+        caps = _caps(max2, max_gamma)
+        rc = lib().qdo_gamma_mixed(p, m, n, max_gamma, caps.ctypes.data_as(_ip), cap, ctypes.byref(h),
+                                   P.ctypes.data_as(_ip), delta.ctypes.data_as(_ip),
+                                   dims.ctypes.data_as(_ip), piv.ctypes.data_as(_ip),
+                                   rows.ctypes.data_as(_u8p) if with_rows else None)
     _check(rc, "gamma")
     out = []
     for j in range(h.value):
@@ -174,18 +184,32 @@ def bz_gamma(gammas, n, nthreads=0, log_cap=4096):
     return d.value, wit, _log_records(log, nl.value)
 
 
-def bz(B, diag=DIAG_F4, max_gamma=8, nthreads=0, log_cap=4096):
-    """Full BZ pipeline: (d, witness, log[(t, j, L, U, combinations)])."""
+def _caps(max2, max_gamma):
+    caps = np.full(max_gamma, -1, dtype=np.int32)
+    for j, c in enumerate(list(max2)[:max_gamma]):
+        caps[j] = c
+    return caps
+
+
+def bz(B, diag=DIAG_F4, max_gamma=8, nthreads=0, log_cap=4096, max2=None):
+    """Full BZ pipeline: (d, witness, log[(t, j, L, U, combinations)]).
+    max2: as for gamma (F4 with mixed packages)."""
     B, p = _u8(B)
     n = B.shape[1] // 2
     d = ctypes.c_int(-1)
     wit = np.zeros(2 * n, dtype=np.uint8)
     log = np.zeros((log_cap, 5), dtype=np.int64)
     nl = ctypes.c_int(0)
-    _check(lib().qdo_bz(p, B.shape[0], n, diag, max_gamma, nthreads, ctypes.byref(d),
-                        wit.ctypes.data_as(_u8p),
-                        log.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), log_cap,
-                        ctypes.byref(nl)), "bz")
+    logp = log.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong))
+    if max2 is None:
+        _check(lib().qdo_bz(p, B.shape[0], n, diag, max_gamma, nthreads, ctypes.byref(d),
+                            wit.ctypes.data_as(_u8p), logp, log_cap, ctypes.byref(nl)), "bz")
+    else:
+        assert diag == DIAG_F4
+        caps = _caps(max2, max_gamma)
+        _check(lib().qdo_bz_mixed(p, B.shape[0], n, max_gamma, caps.ctypes.data_as(_ip), nthreads,
+                                  ctypes.byref(d), wit.ctypes.data_as(_u8p), logp, log_cap,
+                                  ctypes.byref(nl)), "bz_mixed")
     return d.value, wit, _log_records(log, nl.value)
 
 

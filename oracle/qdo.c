@@ -290,9 +290,12 @@ typedef struct {
 /* The column chosen next among `colok` columns not yet done: the first one
  * where the rows in `cand` show two different nonzero symbols, else the
  * first one where they show exactly one (Sec. 2.3: such columns are
- * prioritized).  Returns -1 if every candidate row is zero there. */
+ * prioritized).  With allow2 = 0 (mixed packages: the matrix has reached
+ * its cap of two-row packages) it is the first column where some
+ * candidate row is nonzero, for a one-row package.  Returns -1 if every
+ * candidate row is zero there. */
 static int pick_column(const uint8_t *R, int k, int n, const int *cand,
-                       const int *colok, const int *done, int *dim) {
+                       const int *colok, const int *done, int allow2, int *dim) {
   int first1 = -1;
   for (int q = 0; q < n; ++q) {
     if (!colok[q] || done[q]) continue;
@@ -301,7 +304,8 @@ static int pick_column(const uint8_t *R, int k, int n, const int *cand,
       if (cand[v]) mask |= 1 << sym(R + (size_t)v * 2 * n, n, q);
     mask &= 0xE; /* nonzero symbols 1, 2, 3 */
     int cnt = __builtin_popcount(mask);
-    if (cnt >= 2) { *dim = 2; return q; }
+    if (cnt >= 2 && allow2) { *dim = 2; return q; }
+    if (cnt >= 1 && !allow2) { *dim = 1; return q; }
     if (cnt == 1 && first1 < 0) first1 = q;
   }
   *dim = 1;
@@ -310,15 +314,17 @@ static int pick_column(const uint8_t *R, int k, int n, const int *cand,
 
 /* Diagonalization over F4 restricted to rows in `cand` (pivots) and rows in
  * `clearset` (rows whose pivot columns get cleared), columns in `colok`.
- * Appends packages to pk and clears cand[] for the rows it uses. */
+ * Appends packages to pk and clears cand[] for the rows it uses.  max2 >= 0
+ * caps the two-row packages of the pass (mixed packages); -1: no cap. */
 static int diag_f4_pass(uint8_t *R, int k, int n, int *cand, const int *clearset,
-                        const int *colok, int outside, pkg_t *pk, int np) {
+                        const int *colok, int outside, int max2, pkg_t *pk, int np) {
   int len = 2 * n;
+  int n2 = 0;
   int *done = (int *)calloc(n, sizeof(int));
   int *pivrow = (int *)calloc(k, sizeof(int)); /* used as a pivot row in this pass */
   for (;;) {
     int dim;
-    int q = pick_column(R, k, n, cand, colok, done, &dim);
+    int q = pick_column(R, k, n, cand, colok, done, max2 < 0 || n2 < max2, &dim);
     if (q < 0) break;
     done[q] = 1;
     int r = -1, s = -1;
@@ -347,19 +353,18 @@ static int diag_f4_pass(uint8_t *R, int k, int n, int *cand, const int *clearset
       }
       cand[r] = cand[s] = 0;
       pivrow[r] = pivrow[s] = 1;
+      ++n2;
     } else {
-      /* One-row package: remaining rows become 0 at q; rows already used as
-       * pivots become 0 or one fixed beta != sr (Sec. 2.3, "clear"). */
+      /* One-row package: every other row becomes 0 or one fixed beta != sr
+       * at q (Sec. 2.3, "clear"): adding r takes sr to 0 and sr ^ beta to
+       * beta.  Remaining rows show only sr at a one-symbol column; past a
+       * two-row cap they may show all three symbols. */
       int beta = (sr == 1) ? 2 : 1;
       for (int v = 0; v < k; ++v) {
-        if (v == r || !clearset[v]) continue;
+        if (v == r || !clearset[v] || !(cand[v] || pivrow[v])) continue;
         int sv = sym(R + (size_t)v * len, n, q);
-        if (cand[v]) {
-          if (sv == sr) row_add(R + (size_t)v * len, R + (size_t)r * len, len);
-        } else if (pivrow[v]) {
-          if (sv == sr || sv == (sr ^ beta))
-            row_add(R + (size_t)v * len, R + (size_t)r * len, len);
-        }
+        if (sv == sr || sv == (sr ^ beta))
+          row_add(R + (size_t)v * len, R + (size_t)r * len, len);
       }
       cand[r] = 0;
       pivrow[r] = 1;
@@ -375,19 +380,20 @@ static int diag_f4_pass(uint8_t *R, int k, int n, int *cand, const int *clearset
   return np;
 }
 
-/* One generator matrix over the allowed qubits; leftover rows (zero on all
- * allowed qubits) are grouped by the same rule over all qubits and counted
- * as packages outside the set. */
-static int build_f4(uint8_t *R, int k, int n, const int *allowed, pkg_t *pk) {
+/* One generator matrix over the allowed qubits, at most max2 two-row
+ * packages among those pivoted there (-1: no cap); leftover rows (zero on
+ * all allowed qubits) are grouped by the same rule over all qubits and
+ * counted as packages outside the set. */
+static int build_f4(uint8_t *R, int k, int n, const int *allowed, int max2, pkg_t *pk) {
   int *cand = (int *)malloc(sizeof(int) * k);
   int *all = (int *)malloc(sizeof(int) * k);
   int *allcols = (int *)malloc(sizeof(int) * n);
   for (int v = 0; v < k; ++v) cand[v] = all[v] = 1;
   for (int q = 0; q < n; ++q) allcols[q] = 1;
-  int np = diag_f4_pass(R, k, n, cand, all, allowed, 0, pk, 0);
+  int np = diag_f4_pass(R, k, n, cand, all, allowed, 0, max2, pk, 0);
   int *left = (int *)malloc(sizeof(int) * k);
   for (int v = 0; v < k; ++v) left[v] = cand[v];
-  np = diag_f4_pass(R, k, n, cand, left, allcols, 1, pk, np);
+  np = diag_f4_pass(R, k, n, cand, left, allcols, 1, -1, pk, np);
   free(cand); free(all); free(allcols); free(left);
   return np;
 }
@@ -472,9 +478,9 @@ static int check_packages(const uint8_t *R, int k, int n, const pkg_t *pk, int n
   return 1;
 }
 
-int qdo_gamma(const uint8_t *B, int m, int n, int diag, int max_gamma,
-              int cap, int *h_out, int *P, int *delta, int *dims, int *pivot,
-              uint8_t *rows) {
+static int gamma_impl(const uint8_t *B, int m, int n, int diag, int max_gamma,
+                      const int *max2, int cap, int *h_out, int *P, int *delta,
+                      int *dims, int *pivot, uint8_t *rows) {
   if (!B || m <= 0 || n <= 0 || max_gamma <= 0 || cap < 2 * n || !h_out || !P ||
       !delta || !dims || !pivot)
     return m == 0 ? QDO_ERR_ZERO_CODE : QDO_ERR_INVALID;
@@ -503,7 +509,7 @@ int qdo_gamma(const uint8_t *B, int m, int n, int diag, int max_gamma,
       int any = 0;
       for (int q = 0; q < n; ++q) { allowed[q] = !used[q]; any |= allowed[q]; }
       if (!any) break;
-      np = build_f4(R, k, n, allowed, pk);
+      np = build_f4(R, k, n, allowed, max2 ? max2[j] : -1, pk);
     }
     if (!check_packages(R, k, n, pk, np)) { rc = -5; goto done; }
     int inside = 0, dsum = 0;
@@ -534,6 +540,19 @@ int qdo_gamma(const uint8_t *B, int m, int n, int diag, int max_gamma,
 done:
   free(basis); free(R); free(pk); free(used); free(allowed);
   return rc;
+}
+
+int qdo_gamma(const uint8_t *B, int m, int n, int diag, int max_gamma,
+              int cap, int *h_out, int *P, int *delta, int *dims, int *pivot,
+              uint8_t *rows) {
+  return gamma_impl(B, m, n, diag, max_gamma, NULL, cap, h_out, P, delta, dims, pivot, rows);
+}
+
+int qdo_gamma_mixed(const uint8_t *B, int m, int n, int max_gamma, const int *max2,
+                    int cap, int *h_out, int *P, int *delta, int *dims, int *pivot,
+                    uint8_t *rows) {
+  if (!max2) return QDO_ERR_INVALID;
+  return gamma_impl(B, m, n, QDO_DIAG_F4, max_gamma, max2, cap, h_out, P, delta, dims, pivot, rows);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -713,7 +732,7 @@ int qdo_bz_gamma(int h, const int *P, const int *off, const int *delta,
                        log, log_cap, nlog);
 }
 
-static int bz_impl(const uint8_t *B, int m, int n, int diag, int max_gamma,
+static int bz_impl(const uint8_t *B, int m, int n, int diag, int max_gamma, const int *max2,
                    int nthreads, int filter, int *d, uint8_t *witness, long long *log,
                    int log_cap, int *nlog) {
   if (!B || m <= 0 || n <= 0 || !d) return m == 0 ? QDO_ERR_ZERO_CODE : QDO_ERR_INVALID;
@@ -733,7 +752,7 @@ static int bz_impl(const uint8_t *B, int m, int n, int diag, int max_gamma,
     for (int i = 0; i < m; ++i) pack_row(B + (size_t)i * 2 * n, n, chk + (size_t)i * 2 * W);
     nchk = filter_rows(chk, m, W);
   }
-  int rc = chk ? qdo_gamma(B, m, n, diag, G, cap, &h, P, delta, dims, piv, rows) : QDO_ERR_NOMEM;
+  int rc = chk ? gamma_impl(B, m, n, diag, G, max2, cap, &h, P, delta, dims, piv, rows) : QDO_ERR_NOMEM;
   if (rc >= 0) {
     for (int j = 0; j < h; ++j) off[j] = j * cap;
     rc = bz_gamma_impl(h, P, off, delta, rows, dims, n, nthreads, chk, nchk, d, witness,
@@ -748,13 +767,20 @@ static int bz_impl(const uint8_t *B, int m, int n, int diag, int max_gamma,
 int qdo_bz(const uint8_t *B, int m, int n, int diag, int max_gamma,
            int nthreads, int *d, uint8_t *witness, long long *log,
            int log_cap, int *nlog) {
-  return bz_impl(B, m, n, diag, max_gamma, nthreads, 0, d, witness, log, log_cap, nlog);
+  return bz_impl(B, m, n, diag, max_gamma, NULL, nthreads, 0, d, witness, log, log_cap, nlog);
+}
+
+int qdo_bz_mixed(const uint8_t *B, int m, int n, int max_gamma, const int *max2,
+                 int nthreads, int *d, uint8_t *witness, long long *log,
+                 int log_cap, int *nlog) {
+  if (!max2) return QDO_ERR_INVALID;
+  return bz_impl(B, m, n, QDO_DIAG_F4, max_gamma, max2, nthreads, 0, d, witness, log, log_cap, nlog);
 }
 
 int qdo_bz_stab(const uint8_t *B, int m, int n, int diag, int max_gamma,
                 int nthreads, int *d, uint8_t *witness, long long *log,
                 int log_cap, int *nlog) {
-  return bz_impl(B, m, n, diag, max_gamma, nthreads, 1, d, witness, log, log_cap, nlog);
+  return bz_impl(B, m, n, diag, max_gamma, NULL, nthreads, 1, d, witness, log, log_cap, nlog);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -75,6 +75,16 @@ int qdo_gamma(const uint8_t *B, int m, int n, int diag, int max_gamma,
               int cap, int *h_out, int *P, int *delta, int *dims, int *pivot,
               uint8_t *rows);
 
+/* Mixed packages (not in the paper): the F4 construction where matrix j has
+ * at most max2[j] two-row packages pivoted inside its set (max2 holds
+ * max_gamma entries; -1: no cap).  Past the cap each package has one row,
+ * pivoted at the first allowed column where a remaining row is nonzero,
+ * and every other row is cleared to 0 or one symbol beta there.  Same
+ * outputs as qdo_gamma. */
+int qdo_gamma_mixed(const uint8_t *B, int m, int n, int max_gamma, const int *max2,
+                    int cap, int *h_out, int *P, int *delta, int *dims, int *pivot,
+                    uint8_t *rows);
+
 /* One round of the enumeration: every choice of t distinct packages and one
  * nonzero element of each (Sec. 2.3, packages).  rows: P*2 rows of 2n bytes
  * (row 2i and, if dims[i] == 2, row 2i+1 span package i).  Writes the
@@ -97,6 +107,11 @@ int qdo_bz_gamma(int h, const int *P, const int *off, const int *delta,
 int qdo_bz(const uint8_t *B, int m, int n, int diag, int max_gamma,
            int nthreads, int *d, uint8_t *witness, long long *log,
            int log_cap, int *nlog);
+
+/* The same over the mixed-package F4 matrices of qdo_gamma_mixed. */
+int qdo_bz_mixed(const uint8_t *B, int m, int n, int max_gamma, const int *max2,
+                 int nthreads, int *d, uint8_t *witness, long long *log,
+                 int log_cap, int *nlog);
 
 /* Modified Brouwer-Zimmermann for a quantum stabilizer code (Sec. 2.1):
  * the rows of B generate the normalizer N = C^{perp_s}; the distance is the

@@ -186,6 +186,13 @@ int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma, 
     if (!check_gamma_iso(g, n)) return QD_ERR_INTERNAL;
   const bool f4_scalar = field == QD_FIELD_F4 || alpha_closed(rows, n);
   PlanChoice pc = choose_plan(f4, f2, iso, n, k, diag, max_gamma, f4_scalar);
+  // Mixed packages, as the automatic plan of qd_distance_ex takes them.
+  std::vector<int> caps;
+  if (!f4_scalar && k < n && pc.predicted_f4 >= kMixMinWork) {
+    if (!try_mixed_f4(rows, n, k, pc.d_est, max_gamma, f4, caps)) return QD_ERR_INTERNAL;
+    if (!caps.empty()) pc = choose_plan(f4, f2, iso, n, k, diag, max_gamma, f4_scalar);
+  }
+  for (int j = 0; j < QD_MAX_GAMMA; ++j) out->f4_two_row_cap[j] = j < int(caps.size()) ? caps[j] : -1;
   out->f4_scalar_classes = f4_scalar ? 1 : 0;
   out->n = n;
   out->rank = k;

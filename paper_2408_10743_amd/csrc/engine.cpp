@@ -301,7 +301,8 @@ void Executor::prepare(Job &job) {
   }
   if (o.seg_len < 0 || o.seg_len % kBlock || o.saved_depth < -1 || o.max_gamma < 0 || o.tops_mode < 0 ||
       o.tops_mode > 2 || (o.filter != QD_FILTER_NONE && o.filter != QD_FILTER_STABILIZER) ||
-      (o.scalar_classes != 0 && o.scalar_classes != -1) || (o.partial_weight < -1 || o.partial_weight > 1)) {
+      (o.scalar_classes != 0 && o.scalar_classes != -1) || (o.partial_weight < -1 || o.partial_weight > 1) ||
+      (o.mixed_packages < -1 || o.mixed_packages > 1)) {
     job.status = QD_ERR_INVALID;
     return;
   }
@@ -324,6 +325,19 @@ void Executor::prepare(Job &job) {
         o.scalar_classes == 0 && (job.field == QD_FIELD_F4 || alpha_closed(job.basis, n));
     job.pc = choose_plan(f4, f2, iso, n, job.rank, o.diag == QD_DIAG_ISO ? QD_DIAG_AUTO : o.diag, o.max_gamma,
                          f4_scalar);
+    // Mixed packages for additive codes with unused qubits (scalar classes
+    // need every package to have two rows).
+    const bool f4_linear = job.field == QD_FIELD_F4 || alpha_closed(job.basis, n);
+    if (o.mixed_packages >= 0 && !f4_linear && job.rank < n && o.diag != QD_DIAG_F2 && o.diag != QD_DIAG_ISO &&
+        (o.mixed_packages == 1 || job.pc.predicted_f4 >= kMixMinWork)) {
+      if (!try_mixed_f4(job.basis, n, job.rank, job.pc.d_est, o.max_gamma, f4, job.caps)) {
+        job.status = QD_ERR_INTERNAL;
+        return;
+      }
+      if (!job.caps.empty())
+        job.pc = choose_plan(f4, f2, iso, n, job.rank, o.diag == QD_DIAG_ISO ? QD_DIAG_AUTO : o.diag, o.max_gamma,
+                             f4_scalar);
+    }
     // The isometry matrices are built only when asked for, or when they
     // might beat the other constructions' predicted work.
     if (o.diag == QD_DIAG_ISO ||
@@ -351,6 +365,8 @@ void Executor::prepare_gammas(Job &job) {
   job.S.d_estimate = job.pc.d_est; job.S.predicted = job.pc.predicted;
   job.S.logical_pairs = int(job.logicals.size() / 2);
   job.S.scalar_classes = job.scalar ? 1 : 0;
+  for (int j = 0; j < QD_MAX_GAMMA; ++j)
+    job.S.two_row_cap[j] = job.pc.diag == QD_DIAG_F4 && j < int(job.caps.size()) ? job.caps[j] : -1;
   job.tdone.assign(h, 0);
   job.delta.resize(h);
   for (int j = 0; j < h; ++j) {

@@ -111,6 +111,7 @@ struct Job {
   bool halve = false;  // isometry matrices: bounds count Hamming weight
   bool scalar = false; // one codeword per F4 scalar class
   bool partial = false; // partial weights (matrices stored in their qubit order)
+  std::vector<int> caps; // mixed packages: two-row caps of the F4 matrices (empty: none)
   std::vector<BRow> logicals;  // Modified BZ: the admission test's operators
   std::vector<GammaDev> gd;
   int state_slot = -1;

@@ -81,9 +81,12 @@ struct PkIdx {
 // Package selection, Sec. 2.3: columns with two different nonzero symbols
 // first, then one; the chosen rows clear the column in every row of
 // `scope` (to 0 for a two-row package, to {0, beta} for a one-row one).
+// With max2 >= 0, after max2 two-row packages every further package has
+// one row, taken at the first column where some candidate row is nonzero.
 void greedy_pass(std::vector<BRow> &w, std::vector<char> &cand, const std::vector<char> &scope,
-                 const std::vector<char> &cols, int n, bool outside, std::vector<PkIdx> &out) {
+                 const std::vector<char> &cols, int n, bool outside, std::vector<PkIdx> &out, int max2 = -1) {
   std::vector<char> used(w.size(), 0);
+  int n2 = 0;
   uint64_t avail[2] = {0, 0};  // allowed qubits not pivoted yet
   for (int q = 0; q < n; ++q)
     if (cols[q]) avail[q >> 6] |= uint64_t(1) << (q & 63);
@@ -106,7 +109,10 @@ void greedy_pass(std::vector<BRow> &w, std::vector<char> &cand, const std::vecto
       k1[i] = (sx[i] | sz[i] | sy[i]) & ~two & avail[i];
     }
     auto first = [](const uint64_t *a) { return a[0] ? __builtin_ctzll(a[0]) : a[1] ? 64 + __builtin_ctzll(a[1]) : -1; };
-    const int q2 = first(k2), q = q2 >= 0 ? q2 : first(k1);
+    const bool allow2 = max2 < 0 || n2 < max2;
+    if (!allow2)
+      for (int i = 0; i < 2; ++i) k1[i] |= k2[i];
+    const int q2 = allow2 ? first(k2) : -1, q = q2 >= 0 ? q2 : first(k1);
     if (q < 0) break;
     const int dim = q2 >= 0 ? 2 : 1;
     avail[q >> 6] &= ~(uint64_t(1) << (q & 63));
@@ -129,12 +135,16 @@ void greedy_pass(std::vector<BRow> &w, std::vector<char> &cand, const std::vecto
       }
       cand[r] = cand[s] = 0;
       used[r] = used[s] = 1;
+      ++n2;
     } else {
-      const int beta = (sr % 3) + 1;  // any nonzero symbol other than sr
+      // Every other row ends with 0 or beta at q: sr + sr = 0 and
+      // (sr ^ beta) + sr = beta.  Candidates show only sr at a one-symbol
+      // column; past the two-row cap they may show all three symbols.
+      const int beta = sr == 1 ? 2 : 1;  // a nonzero symbol other than sr
       for (size_t v = 0; v < w.size(); ++v) {
         if (int(v) == r || !scope[v]) continue;
         const int sv = qsym(w[v], q);
-        if (cand[v] ? sv == sr : (used[v] && (sv == sr || sv == (sr ^ beta)))) radd(w[v], w[r]);
+        if ((cand[v] || used[v]) && (sv == sr || sv == (sr ^ beta))) radd(w[v], w[r]);
       }
       cand[r] = 0;
       used[r] = 1;
@@ -159,7 +169,7 @@ Gamma to_gamma(const std::vector<BRow> &w, const std::vector<PkIdx> &idx) {
 
 }  // namespace
 
-std::vector<Gamma> build_f4(const std::vector<BRow> &basis, int n, int max_gamma) {
+std::vector<Gamma> build_f4(const std::vector<BRow> &basis, int n, int max_gamma, const std::vector<int> &max2) {
   std::vector<Gamma> out;
   std::vector<char> taken(n, 0);
   const size_t k = basis.size();
@@ -171,7 +181,7 @@ std::vector<Gamma> build_f4(const std::vector<BRow> &basis, int n, int max_gamma
     std::vector<BRow> w = basis;
     std::vector<char> cand(k, 1), scope(k, 1);
     std::vector<PkIdx> idx;
-    greedy_pass(w, cand, scope, cols, n, false, idx);
+    greedy_pass(w, cand, scope, cols, n, false, idx, j < int(max2.size()) ? max2[j] : -1);
     // Rows left over are zero on the allowed qubits: they still have to be
     // enumerated, as packages that add nothing to the bound.
     std::vector<char> left = cand;
@@ -545,6 +555,78 @@ PlanChoice choose_plan(const std::vector<Gamma> &f4, const Gamma &f2, const std:
   }
   pc.predicted = best;
   return pc;
+}
+
+// -- mixed packages --------------------------------------------------------------
+
+std::vector<std::vector<int>> mixed_caps(int n, int rank, int d_est, int count) {
+  std::vector<std::pair<double, std::vector<int>>> found;
+  const int m = rank, slack = 2 * (n - m);
+  if (m < 2 || slack <= 0 || d_est <= 2) return {};
+  auto esym_d = [](int a, int b, int tmax) {
+    std::vector<double> e(tmax + 1, 0.0);
+    e[0] = 1.0;
+    for (int i = 0; i < a + b; ++i) {
+      const double c = i < a ? 3.0 : 1.0;
+      for (int t = tmax; t > 0; --t) e[t] += e[t - 1] * c;
+    }
+    return e;
+  };
+  const int tmax = std::min(m, d_est);
+  std::vector<std::vector<double>> E(m + 1);
+  for (int b = m % 2; b <= std::min(m, slack); b += 2) E[b] = esym_d((m - b) / 2, b, tmax);
+  for (int b1 = m % 2; b1 <= std::min(m, slack); b1 += 2)
+    for (int b2 = m % 2; b2 <= std::min(m, slack); b2 += 2) {
+      const int a1 = (m - b1) / 2, a2 = (m - b2) / 2;
+      if (a1 + b1 + a2 + b2 > n || (b1 == m % 2 && b2 == m % 2)) continue;
+      double w = 0.0;
+      int L = 2;
+      for (int t = 1; t <= tmax && L < d_est; ++t) {
+        w += E[b1][t];
+        if (++L >= d_est) break;
+        w += E[b2][t];
+        ++L;
+      }
+      found.push_back({w, {a1, a2}});
+    }
+  std::sort(found.begin(), found.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+  std::vector<std::vector<int>> out;
+  for (size_t i = 0; i < found.size() && int(out.size()) < count; ++i) out.push_back(found[i].second);
+  return out;
+}
+
+double best_predicted(const std::vector<Gamma> &gs, int d_est, int max_gamma, bool scalar) {
+  const int hmax = max_gamma > 0 ? std::min<int>(max_gamma, int(gs.size())) : int(gs.size());
+  std::vector<std::vector<double>> E;
+  double best = -1.0;
+  for (int j = 0; j < hmax; ++j) {
+    E.push_back(esym_all(gs[j]));
+    if (scalar)
+      for (double &e : E.back()) e /= 3.0;
+  }
+  for (int h = 1; h <= hmax; ++h) {
+    const double w = predict_with(gs, E, h, d_est, false);
+    if (best < 0 || w < best) best = w;
+  }
+  return best;
+}
+
+bool try_mixed_f4(const std::vector<BRow> &basis, int n, int rank, int d_est, int max_gamma,
+                  std::vector<Gamma> &f4, std::vector<int> &caps) {
+  caps.clear();
+  double best = best_predicted(f4, d_est, max_gamma, false);
+  for (const std::vector<int> &c : mixed_caps(n, rank, d_est, 2)) {
+    std::vector<Gamma> gs = build_f4(basis, n, 2, c);
+    for (const Gamma &g : gs)
+      if (!check_gamma(g, n)) return false;
+    const double w = best_predicted(gs, d_est, max_gamma, false);
+    if (w >= 0 && w < 0.95 * best) {
+      best = w;
+      f4 = std::move(gs);
+      caps = c;
+    }
+  }
+  return true;
 }
 
 // -- partial weights -----------------------------------------------------------

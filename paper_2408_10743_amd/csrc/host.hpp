@@ -58,8 +58,11 @@ int make_basis(std::vector<BRow> &rows, int n);
 
 // Diagonalization over F4 (Sec. 2.3), generalized to several matrices on
 // disjoint qubit sets; at most max_gamma matrices, each with >= 1 package
-// pivoted inside its own set.
-std::vector<Gamma> build_f4(const std::vector<BRow> &basis, int n, int max_gamma);
+// pivoted inside its own set.  max2[j] >= 0 caps matrix j's two-row
+// packages pivoted inside its set: after that many its packages have one
+// row each (mixed packages; missing or -1: no cap).
+std::vector<Gamma> build_f4(const std::vector<BRow> &basis, int n, int max_gamma,
+                            const std::vector<int> &max2 = {});
 
 // Diagonalization over F2 (Sec. 2.2) with whole-qubit clearing: one matrix.
 Gamma build_f2(const std::vector<BRow> &basis, int n);
@@ -137,6 +140,30 @@ int partial_credit(int t, int delta, int kin, bool iso);
 // 3e-5 or less (mean minus four standard deviations); -1 when q < 8.  It
 // only steers the kernel's choice of words, never the result.
 int partial_limit(int q);
+
+// Mixed packages (not in the paper).  When an additive code has fewer
+// independent rows than qubits, two F4 matrices leave qubits unused;
+// trading two-row packages for one-row ones spends them and lowers
+// e_t(sizes).  Models two disjoint matrices with b_1, b_2 one-row packages
+// (a_j = (rank - b_j) / 2 two-row ones, a_1 + b_1 + a_2 + b_2 <= n), both
+// certifying a bound each round, and returns the caps {a_1, a_2} of the
+// layouts with the least modelled work to reach d_est (at most `count`,
+// best first, the all-two-row layout excluded).
+std::vector<std::vector<int>> mixed_caps(int n, int rank, int d_est, int count);
+
+// The least predicted work of matrices 1..h of a construction, over h.
+double best_predicted(const std::vector<Gamma> &gs, int d_est, int max_gamma, bool scalar);
+
+// Replaces the F4 matrices by capped ones (build_f4 with mixed_caps, two
+// matrices) when that lowers their predicted work by at least 5%; `caps`
+// receives the caps used (empty: unchanged).  Returns false if a capped
+// matrix fails check_gamma (an internal error).  The automatic plan tries
+// it from kMixMinWork predicted combinations: below that the extra
+// constructions (0.1-0.4 ms on the host at n = 72-96) cost more than the
+// saving.
+constexpr double kMixMinWork = 1e10;
+bool try_mixed_f4(const std::vector<BRow> &basis, int n, int rank, int d_est, int max_gamma,
+                  std::vector<Gamma> &f4, std::vector<int> &caps);
 
 // Elementary symmetric polynomials e_r of package sizes (1 or 3) as
 // saturating 64-bit integers.  prefix[h][r] = e_r(c_0..c_{h-1}),

@@ -49,7 +49,7 @@ class qd_options(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("seg_len", ctypes.c_int),
                 ("saved_depth", ctypes.c_int), ("timing", ctypes.c_int), ("tops_mode", ctypes.c_int),
                 ("filter", ctypes.c_int), ("scalar_classes", ctypes.c_int),
-                ("partial_weight", ctypes.c_int)]
+                ("partial_weight", ctypes.c_int), ("mixed_packages", ctypes.c_int)]
 
 
 class qd_round_log(ctypes.Structure):
@@ -69,7 +69,8 @@ class qd_stats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double), ("enumerated_kernel_ms", ctypes.c_double),
                 ("wall_ms", ctypes.c_double),
                 ("launches", ctypes.c_int), ("logical_pairs", ctypes.c_int),
-                ("scalar_classes", ctypes.c_int), ("nlog", ctypes.c_int),
+                ("scalar_classes", ctypes.c_int), ("two_row_cap", ctypes.c_int * QD_MAX_GAMMA),
+                ("nlog", ctypes.c_int),
                 ("log", qd_round_log * QD_MAX_LOG)]
 
     def rounds(self):
@@ -101,7 +102,7 @@ class qd_plan_info(ctypes.Structure):
                 ("pivot", (ctypes.c_int * (2 * QD_MAX_N)) * QD_MAX_GAMMA),
                 ("d_estimate", ctypes.c_int), ("predicted_f2", ctypes.c_double),
                 ("predicted_f4", ctypes.c_double), ("predicted_iso", ctypes.c_double),
-                ("f4_scalar_classes", ctypes.c_int)]
+                ("f4_two_row_cap", ctypes.c_int * QD_MAX_GAMMA), ("f4_scalar_classes", ctypes.c_int)]
 
 
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -173,7 +174,8 @@ def qd_distance(G, field=QD_FIELD_F2):
 def qd_distance_ex(G, field=QD_FIELD_F2, **opts):
     """Returns (status, d, witness, qd_stats).  Options: diag, max_gamma,
     budget, cancel (ctypes.c_int), stream (hipStream_t as int), seg_len,
-    saved_depth, timing, tops_mode, filter, scalar_classes, partial_weight."""
+    saved_depth, timing, tops_mode, filter, scalar_classes, partial_weight,
+    mixed_packages."""
     G, m, n = _matrix(G, field)
     o, _keep = _options(opts)
     d = ctypes.c_int(-1)
@@ -221,7 +223,7 @@ def qd_plan(G, field=QD_FIELD_F2, diag=QD_DIAG_AUTO, max_gamma=0):
     return {"n": info.n, "rank": info.rank, "diag": info.diag, "h": info.h, "h_used": info.h_used,
             "gammas": gs, "d_estimate": info.d_estimate, "predicted_f2": info.predicted_f2,
             "predicted_f4": info.predicted_f4, "predicted_iso": info.predicted_iso,
-            "f4_scalar_classes": info.f4_scalar_classes}
+            "f4_two_row_cap": list(info.f4_two_row_cap), "f4_scalar_classes": info.f4_scalar_classes}
 
 
 def qd_round_min(rows, dims, t):

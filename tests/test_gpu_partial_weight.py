@@ -72,9 +72,11 @@ def test_config2_each_construction(Q):
 
 def test_direct_sums_low_weight(Q):
     """Direct sums of small random codes spread over 40..100 qubits, qubits
-    shuffled: pivots land everywhere, many codewords are light (the full
-    words are evaluated often) and the witness must be mapped back to qubit
-    order.  d = the least component distance (brute force per component)."""
+    shuffled: pivots land everywhere, so the stored qubit order is far from
+    the identity and every witness must be mapped back to qubit order.  (The
+    rounds are small enough to run without saved tables, so the words
+    evaluated stay D per codeword.)  d = the least component distance
+    (brute force per component)."""
     for s in range(8):
         rng = W.SplitMix64(W.config_seed(60, s))
         parts, d_ref = [], 10 ** 9
@@ -131,6 +133,9 @@ def test_batch_partial_equals_full(Q):
         for (G, f), d, w in zip(codes, ds, wits):
             assert swt(w) == d and O.in_rowspace(O.expand(G, f), w)
         res[pw] = (ds, sts)
+        words = sum(x.words for x in stats)
+        full = sum(x.D * x.enumerated for x in stats)
+        assert (words < full) if pw == 1 else (words == full)
     for i in range(len(codes)):
         if res[1][1][i] == 0 and res[-1][1][i] == 0:
             assert res[1][0][i] == res[-1][0][i], i

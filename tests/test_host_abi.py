@@ -183,3 +183,41 @@ def test_alpha_closed_binary_input_uses_scalar_classes(Q):
     assert p2["predicted_f4"] == p4["predicted_f4"]
     assert Q.qd_plan(*W.config1(0))["f4_scalar_classes"] == 0
     assert Q.qd_plan(W.textbook_code("[[5,1,3]]"), 2)["f4_scalar_classes"] == 1
+
+
+def test_mixed_packages_structure_matches_oracle(Q):
+    """Additive config-4 codes with fewer rows than qubits and enough work:
+    the planner caps two-row packages (mixed packages), and the oracle's
+    construction under the same caps has the same matrices (package
+    dimensions, pivots, delta) on these codes.  (The oracle starts from the
+    rows as given and the library from their echelon form, so in general
+    the two may pick different rows and differ in detail.)"""
+    codes = W.config4(count=200)
+    capped = 0
+    for i in range(0, 200, 2):
+        G, f = codes[i]
+        p = Q.qd_plan(G, f)
+        caps = [c for c in p["f4_two_row_cap"] if c >= 0]
+        if not caps:
+            continue
+        capped += 1
+        assert p["diag"] == Q.QD_DIAG_F4 and p["rank"] < p["n"]
+        og = O.gamma(O.expand(G, f), O.DIAG_F4, len(caps), max2=caps)
+        assert len(og) == len(caps) == p["h"]
+        for j, g in enumerate(og):
+            mine = p["gammas"][j]
+            assert (mine["P"], mine["delta"], mine["dims"], mine["pivots"]) == \
+                (g["P"], g["delta"], g["dims"], g["pivots"]), (i, j)
+            assert sum(1 for d, q in zip(g["dims"], g["pivots"]) if d == 2 and q >= 0) <= caps[j]
+        if capped >= 6:
+            break
+    assert capped >= 6
+
+
+def test_mixed_packages_option_validation(Q):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    for v in (2, -2):
+        st, d, _, _ = Q.qd_distance_ex(*W.config1(0), mixed_packages=v)
+        assert st == Q.QD_ERR_INVALID and d == -1, v

@@ -50,6 +50,10 @@ MUTANTS = {
     "stab_round_unfiltered": ("    if (w < c->best && admitted(cur, c->chk, c->nchk, c->W)) {", "    if (w < c->best) {"),
     "iso_round_skips_last_row": ("  for (int i = start; i <= c->m - (c->t - depth); ++i) {",
                                  "  for (int i = start; i < c->m - (c->t - depth); ++i) {"),
+    "mixed_cap_ignored": ("    if (cnt >= 2 && allow2) { *dim = 2; return q; }", "    if (cnt >= 2) { *dim = 2; return q; }"),
+    "mixed_one_row_clears_only_sr": ("        if (sv == sr || sv == (sr ^ beta))\n          row_add(R + (size_t)v * len, R + (size_t)r * len, len);\n      }\n      cand[r] = 0;",
+                                     "        if (sv == sr)\n          row_add(R + (size_t)v * len, R + (size_t)r * len, len);\n      }\n      cand[r] = 0;"),
+    "mixed_cap_counts_from_one": ("  int n2 = 0;\n  int *done", "  int n2 = 1;\n  int *done"),
 }
 
 
@@ -110,6 +114,24 @@ def quick_pins():
             k = rng.uniform_int(0, n)
             A = W.random_stabilizer(n, k, rng.next())
             if O.bz_stab(A, O.DIAG_F4, 8)[0] != O.brute_stab(A)[0]:
+                return False
+        # mixed packages: brute force under caps, and the caps themselves
+        for s in range(120):
+            B = W.tiny_code(99000 + s, n_max=8)
+            if not B.any():
+                continue
+            caps = [(s % 4) - 1, ((s // 4) % 4) - 1]
+            if O.bz(B, O.DIAG_F4, 8, max2=caps)[0] != O.brute(B)[0]:
+                return False
+            for j, g in enumerate(O.gamma(B, O.DIAG_F4, 8, max2=caps)[:2]):
+                two = sum(1 for d, p in zip(g["dims"], g["pivots"]) if d == 2 and p >= 0)
+                if caps[j] >= 0 and two > caps[j]:
+                    return False
+        for s in range(10):
+            B = W.additive(12, 8, W.config_seed(75, s))
+            g = O.gamma(B, O.DIAG_F4, 1, max2=[2])[0]
+            two = sum(1 for d, p in zip(g["dims"], g["pivots"]) if d == 2 and p >= 0)
+            if two != 2:  # a random code has room for both two-row packages
                 return False
         rows, dims = W.random_packages(6, 20, W.config_seed(15, 0), 0.5)
         sizes = [3 if d == 2 else 1 for d in dims]
