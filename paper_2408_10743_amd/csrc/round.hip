@@ -87,26 +87,29 @@ __device__ __forceinline__ uint32_t block_min(const uint32_t (&ax)[D], const uin
   return best;
 }
 
-// One block with partial weights: words 0..W-1 first; if some lane's bound
-// (partial weight + credit) falls below U (thr = U - credit), the block's
-// remaining words are added and its full weights enter `best`.  `rec`
-// counts such blocks.
-template <int D, int W>
-__device__ __forceinline__ uint32_t block_min_partial(const uint32_t (&ax)[D], const uint32_t (&az)[D],
-                                                      const uint32_t *__restrict__ blk, uint32_t best,
-                                                      uint32_t thr, uint32_t &rec) {
-  uint32_t w[kBlock];
+// NB consecutive blocks with partial weights: words 0..W-1 first; if some
+// lane's bound (partial weight + credit) falls below U (thr = U - credit),
+// the blocks' remaining words are added and their full weights enter
+// `best`.  `rec` counts the blocks evaluated in full.
+template <int D, int W, int NB>
+__device__ __forceinline__ uint32_t blocks_min_partial(const uint32_t (&ax)[D], const uint32_t (&az)[D],
+                                                       const uint32_t *__restrict__ blk, uint32_t best,
+                                                       uint32_t thr, uint32_t &rec) {
+  constexpr int N = NB * kBlock;
+  uint32_t w[N];
   {
-    uint32_t v[2 * W][kBlock];
+    uint32_t v[2 * W][N];
 #pragma unroll
-    for (int j = 0; j < W; ++j)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int e = 0; e < kBlock; ++e) {
-        v[j][e] = blk[j * kBlock + e];
-        v[W + j][e] = blk[(D + j) * kBlock + e];
-      }
+      for (int j = 0; j < W; ++j)
 #pragma unroll
-    for (int e = 0; e < kBlock; ++e) {
+        for (int e = 0; e < kBlock; ++e) {
+          v[j][b * kBlock + e] = blk[b * 2 * D * kBlock + j * kBlock + e];
+          v[W + j][b * kBlock + e] = blk[b * 2 * D * kBlock + (D + j) * kBlock + e];
+        }
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
       uint32_t acc = 0;
 #pragma unroll
       for (int d = 0; d < W; ++d) {
@@ -117,20 +120,22 @@ __device__ __forceinline__ uint32_t block_min_partial(const uint32_t (&ax)[D], c
     }
   }
   uint32_t pm = min3(w[0], w[1], w[2]);
-  pm = min3(pm, w[3], w[4]);
-  pm = min3(pm, w[5], w[6]);
-  pm = min(pm, w[7]);
-  if (__ballot(pm < thr)) {  // rare once U is small: the block is evaluated in full
-    uint32_t v[2 * (D - W)][kBlock];
 #pragma unroll
-    for (int j = 0; j < D - W; ++j)
+  for (int e = 3; e + 1 < N; e += 2) pm = min3(pm, w[e], w[e + 1]);
+  pm = min(pm, w[N - 1]);
+  if (__ballot(pm < thr)) {  // rare once U is small: the blocks are evaluated in full
+    uint32_t v[2 * (D - W)][N];
 #pragma unroll
-      for (int e = 0; e < kBlock; ++e) {
-        v[j][e] = blk[(W + j) * kBlock + e];
-        v[D - W + j][e] = blk[(D + W + j) * kBlock + e];
-      }
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int e = 0; e < kBlock; ++e) {
+      for (int j = 0; j < D - W; ++j)
+#pragma unroll
+        for (int e = 0; e < kBlock; ++e) {
+          v[j][b * kBlock + e] = blk[b * 2 * D * kBlock + (W + j) * kBlock + e];
+          v[D - W + j][b * kBlock + e] = blk[b * 2 * D * kBlock + (D + W + j) * kBlock + e];
+        }
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
 #pragma unroll
       for (int d = 0; d < D - W; ++d) {
         uint32_t o = (ax[W + d] ^ v[d][e]) | (az[W + d] ^ v[D - W + d][e]);
@@ -138,9 +143,23 @@ __device__ __forceinline__ uint32_t block_min_partial(const uint32_t (&ax)[D], c
       }
     }
 #pragma unroll
-    for (int e = 0; e < kBlock; e += 2) best = min3(best, w[e], w[e + 1]);
-    ++rec;
+    for (int e = 0; e < N; e += 2) best = min3(best, w[e], w[e + 1]);
+    rec += NB;
   }
+  return best;
+}
+
+// The full blocks of a tile with partial weights, kPartialBlocks blocks per
+// wait for their scalar loads.
+constexpr int kPartialBlocks = 2;
+template <int D, int W>
+__device__ __forceinline__ uint32_t partial_blocks(const uint32_t (&ax)[D], const uint32_t (&az)[D],
+                                                   const uint32_t *__restrict__ blk, uint32_t nfull,
+                                                   uint32_t best, uint32_t thr, uint32_t &rec) {
+  uint32_t i = 0;
+  for (; i + kPartialBlocks <= nfull; i += kPartialBlocks, blk += kPartialBlocks * 2 * D * kBlock)
+    best = blocks_min_partial<D, W, kPartialBlocks>(ax, az, blk, best, thr, rec);
+  for (; i < nfull; ++i, blk += 2 * D * kBlock) best = blocks_min_partial<D, W, 1>(ax, az, blk, best, thr, rec);
   return best;
 }
 
@@ -339,19 +358,13 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
     const int c = p.credit[W - 1];
     const uint32_t thr = U0 > c ? static_cast<uint32_t>(U0 - c) : 0u;
     if constexpr (D >= 2) {
-      if (W == 1)
-        for (uint32_t i = 0; i < nfull; ++i, blk += 2 * D * kBlock)
-          best = block_min_partial<D, 1>(ax, az, blk, best, thr, rec);
+      if (W == 1) best = partial_blocks<D, 1>(ax, az, blk, nfull, best, thr, rec);
     }
     if constexpr (D >= 3) {
-      if (W == 2)
-        for (uint32_t i = 0; i < nfull; ++i, blk += 2 * D * kBlock)
-          best = block_min_partial<D, 2>(ax, az, blk, best, thr, rec);
+      if (W == 2) best = partial_blocks<D, 2>(ax, az, blk, nfull, best, thr, rec);
     }
     if constexpr (D >= 4) {
-      if (W == 3)
-        for (uint32_t i = 0; i < nfull; ++i, blk += 2 * D * kBlock)
-          best = block_min_partial<D, 3>(ax, az, blk, best, thr, rec);
+      if (W == 3) best = partial_blocks<D, 3>(ax, az, blk, nfull, best, thr, rec);
     }
   }
   for (uint32_t i = nfull * kBlock; i < send; ++i) {
