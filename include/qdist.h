@@ -212,9 +212,14 @@ int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma,
  * package i when dims[i] == 2, row 2i alone when dims[i] == 1.  Writes the
  * minimum symplectic weight (n + 1 when t > P), one codeword reaching it
  * (witness: 2n bytes or NULL) and the number of combinations visited.
- * Every word of every codeword is evaluated (no partial weights). */
+ * partial_words = 0 evaluates every word of every codeword; 1 <= w < D
+ * (D = 32-bit words per half) makes every tile evaluate words 0..w-1 first
+ * and the rest only for blocks where some of those partial weights is
+ * below the U the tile started with (no pivot credit: the packages carry
+ * no pivots), which must give the same minimum and count. */
 int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int *wmin,
-                 uint8_t *witness, unsigned long long *count);
+                 uint8_t *witness, unsigned long long *count,
+                 int partial_words);
 
 /* -- Serving: continuous batching of distance requests ------------------------
  * A qd_engine owns a worker thread and a HIP stream.  Requests are checked

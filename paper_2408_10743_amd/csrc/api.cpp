@@ -220,14 +220,16 @@ int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma, 
 }
 
 int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int *wmin, uint8_t *witness,
-                 unsigned long long *count) {
+                 unsigned long long *count, int partial_words) {
   if (!rows || !dims || !wmin || !count || P <= 0 || P > 2 * kMaxN || t < 1 || n <= 0) return QD_ERR_INVALID;
   if (n > kMaxN) return QD_ERR_TOO_LARGE;
+  if (partial_words < 0 || (partial_words > 0 && partial_words >= (n + 31) / 32)) return QD_ERR_INVALID;
   Job job;
   job.n = n;
   job.single_round = true;
   job.t = t;
   job.opt.partial_weight = -1;
+  job.force_words = partial_words;
   Gamma g;
   for (int i = 0; i < P; ++i) {
     if (dims[i] != 1 && dims[i] != 2) return QD_ERR_INVALID;

@@ -759,6 +759,11 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         d.inv = g.inv;
         d.n = job.n;
         for (int w = 1; w <= 3; ++w) {
+          if (job.force_words) {  // qd_round_min: w words first in every tile
+            d.credit[w - 1] = 0;
+            d.cap[w - 1] = w == job.force_words && w < job.D ? job.n + 1 : -1;
+            continue;
+          }
           // Words 0..w-1 hold min(32 w, nonpivot) qubits without pivots.
           const int q = std::min(32 * w, g.order.nonpivot);
           const bool on = job.partial && w < job.D && partial_limit(q) >= 0;

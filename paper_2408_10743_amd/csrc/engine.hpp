@@ -112,6 +112,7 @@ struct Job {
   bool scalar = false; // one codeword per F4 scalar class
   bool partial = false; // partial weights (matrices stored in their qubit order)
   std::vector<int> caps; // mixed packages: two-row caps of the F4 matrices (empty: none)
+  int force_words = 0;   // > 0: every tile evaluates this many words first (no credit)
   std::vector<BRow> logicals;  // Modified BZ: the admission test's operators
   std::vector<GammaDev> gd;
   int state_slot = -1;

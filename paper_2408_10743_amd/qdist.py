@@ -117,7 +117,7 @@ _lib.qd_distance_batch_ex.argtypes = [ctypes.c_int, ctypes.POINTER(_u8p), _ip, _
 _lib.qd_plan.argtypes = [_u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                          ctypes.POINTER(qd_plan_info)]
 _lib.qd_round_min.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _u8p,
-                              ctypes.POINTER(ctypes.c_ulonglong)]
+                              ctypes.POINTER(ctypes.c_ulonglong), ctypes.c_int]
 _lib.qd_device_check.argtypes = [ctypes.c_char_p, ctypes.c_int]
 _lib.qd_engine_create.restype = ctypes.c_void_p
 _lib.qd_engine_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
@@ -226,8 +226,9 @@ def qd_plan(G, field=QD_FIELD_F2, diag=QD_DIAG_AUTO, max_gamma=0):
             "f4_two_row_cap": list(info.f4_two_row_cap), "f4_scalar_classes": info.f4_scalar_classes}
 
 
-def qd_round_min(rows, dims, t):
-    """One GPU enumeration round: returns (status, wmin, witness, count)."""
+def qd_round_min(rows, dims, t, partial_words=0):
+    """One GPU enumeration round: returns (status, wmin, witness, count).
+    partial_words = w > 0: tiles evaluate w words first."""
     rows = np.ascontiguousarray(rows, dtype=np.uint8)
     dims = np.ascontiguousarray(dims, dtype=np.int32)
     P = dims.shape[0]
@@ -236,7 +237,7 @@ def qd_round_min(rows, dims, t):
     cnt = ctypes.c_ulonglong(0)
     wit = np.zeros(2 * n, dtype=np.uint8)
     st = _lib.qd_round_min(rows.ctypes.data_as(_u8p), dims.ctypes.data_as(_ip), P, n, t, ctypes.byref(w),
-                           wit.ctypes.data_as(_u8p), ctypes.byref(cnt))
+                           wit.ctypes.data_as(_u8p), ctypes.byref(cnt), partial_words)
     return st, w.value, wit, cnt.value
 
 

@@ -76,6 +76,33 @@ def test_round_min_large_round(Q):
         assert swt(wit) == w
 
 
+@pytest.mark.parametrize("D,w", [(2, 1), (3, 1), (3, 2), (4, 1), (4, 2), (4, 3)])
+def test_round_min_partial_words(Q, D, w):
+    """The partial-weight path of every (D, w): a round evaluated w words
+    first gives the minimum and the count of the full evaluation and of the
+    oracle's plain enumeration.  Dense random packages complete most blocks;
+    packages confined to the first w words (so the full weight is the
+    partial one) skip most of them.  t = 4 over 30 two-row packages is
+    2.2e6 combinations, enough for saved tables and full blocks."""
+    n = 32 * D - 3  # a ragged last word
+    for concentrated in (False, True):
+        rows, dims = W.random_packages(30, n, W.config_seed(26, 10 * D + w), 1.0)
+        if concentrated:
+            keep = np.zeros(2 * n, dtype=np.uint8)
+            keep[:32 * w] = 1
+            keep[n:n + 32 * w] = 1
+            rows = rows * keep
+        ref_w, _, ref_cnt = O.round_min(rows, dims, 4)
+        st0, w0, wit0, c0 = Q.qd_round_min(rows, dims, 4)
+        st1, w1, wit1, c1 = Q.qd_round_min(rows, dims, 4, partial_words=w)
+        print(f"D={D} w={w} concentrated={concentrated} min={ref_w} count={ref_cnt}", flush=True)
+        assert st0 == st1 == 0
+        assert (w0, c0) == (w1, c1) == (ref_w, ref_cnt)
+        assert swt(wit1) == w1
+    # partial_words must be below D
+    assert Q.qd_round_min(rows, dims, 4, partial_words=D)[0] == Q.QD_ERR_INVALID
+
+
 def test_round_beyond_packages(Q):
     rows, dims = W.random_packages(3, 10, W.config_seed(21, 1))
     st, w, wit, cnt = Q.qd_round_min(rows, dims, 4)
