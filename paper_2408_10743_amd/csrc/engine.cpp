@@ -321,13 +321,12 @@ void Executor::prepare(Job &job) {
       if (!check_gamma(g, n)) { job.status = QD_ERR_INTERNAL; return; }
     if (!check_gamma(f2, n)) { job.status = QD_ERR_INTERNAL; return; }
     std::vector<Gamma> iso;
-    const bool f4_scalar =
-        o.scalar_classes == 0 && (job.field == QD_FIELD_F4 || alpha_closed(job.basis, n));
+    const bool f4_linear = job.field == QD_FIELD_F4 || alpha_closed(job.basis, n);
+    const bool f4_scalar = o.scalar_classes == 0 && f4_linear;
     job.pc = choose_plan(f4, f2, iso, n, job.rank, o.diag == QD_DIAG_ISO ? QD_DIAG_AUTO : o.diag, o.max_gamma,
                          f4_scalar);
     // Mixed packages for additive codes with unused qubits (scalar classes
     // need every package to have two rows).
-    const bool f4_linear = job.field == QD_FIELD_F4 || alpha_closed(job.basis, n);
     if (o.mixed_packages >= 0 && !f4_linear && job.rank < n && o.diag != QD_DIAG_F2 && o.diag != QD_DIAG_ISO &&
         (o.mixed_packages == 1 || job.pc.predicted_f4 >= kMixMinWork)) {
       if (!try_mixed_f4(job.basis, n, job.rank, job.pc.d_est, o.max_gamma, f4, job.caps)) {

@@ -245,8 +245,37 @@ Gamma build_f2(const std::vector<BRow> &basis, int n) {
 
 bool check_gamma(const Gamma &g, int n) {
   (void)n;
+  // Per package, the qubits where its rows show symbol 1 (x only), 2 (z
+  // only) and 3 (both); prefix and suffix unions give every other
+  // package's symbols at a pivot in O(1).
+  struct Sym {
+    uint64_t s[3][2];
+  };
+  const size_t P = g.pk.size();
+  auto sym_of = [](const BRow &r, Sym &m) {
+    for (int i = 0; i < 2; ++i) {
+      m.s[0][i] |= r.x[i] & ~r.z[i];
+      m.s[1][i] |= r.z[i] & ~r.x[i];
+      m.s[2][i] |= r.x[i] & r.z[i];
+    }
+  };
+  std::vector<Sym> pre(P + 1, Sym{}), suf(P + 1, Sym{});
+  for (size_t j = 0; j < P; ++j) {
+    Sym m{};
+    sym_of(g.pk[j].r, m);
+    if (g.pk[j].dim == 2) sym_of(g.pk[j].s, m);
+    for (int a = 0; a < 3; ++a)
+      for (int i = 0; i < 2; ++i) pre[j + 1].s[a][i] = pre[j].s[a][i] | m.s[a][i];
+  }
+  for (size_t j = P; j-- > 0;) {
+    Sym m{};
+    sym_of(g.pk[j].r, m);
+    if (g.pk[j].dim == 2) sym_of(g.pk[j].s, m);
+    for (int a = 0; a < 3; ++a)
+      for (int i = 0; i < 2; ++i) suf[j].s[a][i] = suf[j + 1].s[a][i] | m.s[a][i];
+  }
   std::vector<char> seen(kMaxN, 0);
-  for (size_t i = 0; i < g.pk.size(); ++i) {
+  for (size_t i = 0; i < P; ++i) {
     const Package &p = g.pk[i];
     if (p.pivot < 0) continue;
     if (seen[p.pivot]) return false;
@@ -254,13 +283,9 @@ bool check_gamma(const Gamma &g, int n) {
     const int q = p.pivot, sr = qsym(p.r, q);
     if (!sr) return false;
     if (p.dim == 2 && (!qsym(p.s, q) || qsym(p.s, q) == sr)) return false;
-    unsigned other = 0;
-    for (size_t j = 0; j < g.pk.size(); ++j) {
-      if (j == i) continue;
-      other |= 1u << qsym(g.pk[j].r, q);
-      if (g.pk[j].dim == 2) other |= 1u << qsym(g.pk[j].s, q);
-    }
-    other &= 0xEu;
+    unsigned other = 0;  // nonzero symbols of the other packages' rows at q
+    for (int a = 0; a < 3; ++a)
+      if (((pre[i].s[a][q >> 6] | suf[i + 1].s[a][q >> 6]) >> (q & 63)) & 1) other |= 2u << a;
     if (p.dim == 2 && other) return false;
     if (p.dim == 1 && (__builtin_popcount(other) > 1 || (other >> sr) & 1)) return false;
   }
@@ -483,9 +508,20 @@ double iso_work_floor(int n, int rank, int d_est) {
 }
 
 bool alpha_closed(const std::vector<BRow> &basis, int n) {
-  std::vector<BRow> rows = basis;
-  for (const BRow &r : basis) rows.push_back(alpha_row(r));
-  return make_basis(rows, n) == int(basis.size());
+  // In row echelon form every row's first nonzero column (x columns, then
+  // z) is zero in the rows below it, so reducing by the rows in order
+  // clears each pivot for good: v is in the span exactly when it ends zero.
+  std::vector<int> piv(basis.size(), -1);
+  for (size_t k = 0; k < basis.size(); ++k)
+    for (int c = 0; c < 2 * n && piv[k] < 0; ++c)
+      if (rbit(basis[k], c, n)) piv[k] = c;
+  for (const BRow &b : basis) {
+    BRow v = alpha_row(b);
+    for (size_t k = 0; k < basis.size(); ++k)
+      if (piv[k] >= 0 && rbit(v, piv[k], n)) radd(v, basis[k]);
+    if (!rzero(v)) return false;  // a generic binary code fails at the first row
+  }
+  return true;
 }
 
 bool make_scalar_orbits(std::vector<Gamma> &gs) {

@@ -107,6 +107,7 @@ bool make_scalar_orbits(std::vector<Gamma> &gs);
 
 // True when the span of `basis` is closed under alpha (an F4-linear code,
 // whatever the input field): alpha times every basis row lies in the span.
+// `basis` is in the row echelon form make_basis leaves.
 bool alpha_closed(const std::vector<BRow> &basis, int n);
 
 // Partial weights.  A matrix is stored with the qubits that carry none of
