@@ -140,6 +140,12 @@ def leg_batched(Q, W, a):
     budget = int(a.batch_max_work * 4)
     import torch
     torch.cuda.synchronize()
+    # The first call also fills the library's device-memory pool (tables of
+    # every code); the timed call is the second, as the per-code loop below
+    # runs with a warm pool too.
+    t0 = time.perf_counter()
+    Q.qd_distance_batch(codes, budget=budget)
+    t_cold = time.perf_counter() - t0
     t0 = time.perf_counter()
     st, ds, wits, sts, stats = Q.qd_distance_batch(codes, budget=budget)
     t_batch = time.perf_counter() - t0
@@ -158,7 +164,7 @@ def leg_batched(Q, W, a):
         "codes": len(codes), "drawn": drawn, "n_range": [min(ns), max(ns)],
         "exact": sum(1 for x in sts if x == 0), "incomplete": sum(1 for x in sts if x == 1),
         "same_d_as_per_code": ds == ds_p,
-        "batched_s": t_batch, "batched_codewords_per_s": comb_b / t_batch,
+        "batched_s": t_batch, "batched_codewords_per_s": comb_b / t_batch, "batched_first_call_s": t_cold,
         "per_code_s": t_plain, "per_code_codewords_per_s": comb_p / t_plain,
         "speedup": t_plain / t_batch,
     }

@@ -221,3 +221,29 @@ def test_mixed_packages_option_validation(Q):
     for v in (2, -2):
         st, d, _, _ = Q.qd_distance_ex(*W.config1(0), mixed_packages=v)
         assert st == Q.QD_ERR_INVALID and d == -1, v
+
+
+def test_binding_struct_layouts_match_header(Q, tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets (a C program compiled against include/qdist.h prints them)."""
+    import subprocess
+    structs = [Q.qd_options, Q.qd_round_log, Q.qd_stats, Q.qd_result, Q.qd_plan_info]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "qdist.h"', "int main(void) {"]
+    for cls in structs:
+        name = cls.__name__
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    c_side = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cls in structs:
+        name = cls.__name__
+        assert c_side[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert c_side[(name, field)] == getattr(cls, field).offset, (name, field)
