@@ -59,6 +59,13 @@ def test_config4_full_batch(Q):
         assert swt(w) == d and O.in_rowspace(B, w)
         st1, d1, _, s1 = Q.qd_distance_ex(G, f, budget=budget)
         assert st1 == x and d1 == d
+    # the same batch with every word evaluated and two-row packages first
+    # (the paper's construction): the same statuses and distances
+    st2, ds2, wits2, sts2, _ = Q.qd_distance_batch(codes, budget=budget, partial_weight=-1, mixed_packages=-1)
+    assert sts2 == sts
+    for i, (d, d2) in enumerate(zip(ds, ds2)):
+        if sts[i] == 0:
+            assert d == d2, i
     # exact oracle comparison on the cheapest codes of each field
     order = sorted(range(len(codes)), key=lambda i: stats[i].combinations)
     checked = {2: 0, 4: 0}
