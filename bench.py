@@ -180,6 +180,32 @@ def leg_plain(Q, G, field, engine_step_ms, engine_combos):
             "engine_speedup": s.wall_ms / engine_step_ms}
 
 
+def leg_walk(Q, G, field, stream, engine_step_ms, steps):
+    """The plain per-round walk on the same code (qd_options.walk = 1): one
+    launch per (t, Gamma_j) round and a readback of U after each; lanes walk
+    package sets in revolving-door order and element choices in reflected
+    ternary Gray order, every codeword evaluated in full.  One warm-up call,
+    then `steps` timed calls."""
+    runs = []
+    for i in range(steps + 1):
+        st, d, wit, s = Q.qd_distance_ex(G, field, stream=stream, timing=1, walk=1)
+        assert st == 0
+        if i:
+            runs.append(s)
+    combos = sum(s.combinations for s in runs)
+    walked = sum(s.words for s in runs) / runs[0].D  # codewords evaluated (one-row packages repeat)
+    kernel_ms = sum(s.kernel_ms for s in runs)
+    wall_ms = sum(s.wall_ms for s in runs)
+    D = runs[0].D
+    return {"d": d, "ms_per_step": wall_ms / steps, "codewords_per_s": combos / (wall_ms * 1e-3),
+            "kernel_codewords_per_s": combos / (kernel_ms * 1e-3),
+            "walked_per_combination": walked / combos,
+            "launches_per_step": sum(s.launches for s in runs) / steps,
+            # per walked codeword: 2D XOR + D OR + D v_bcnt + 1 min
+            "roofline_frac_4D1_ops": walked * (4 * D + 1) / (kernel_ms * 1e-3) / PEAK_LANE_OPS,
+            "engine_speedup": (wall_ms / steps) / engine_step_ms}
+
+
 def leg_full_weight(Q, G, field, stream, steps):
     """The same code with every word of every codeword evaluated
     (partial_weight = -1): the enumeration rate without partial weights."""
@@ -444,6 +470,7 @@ def main():
     if not a.no_extra:
         out["full_weight"] = leg_full_weight(Q, G, field, stream.cuda_stream, 5)
         out["plain_per_code"] = leg_plain(Q, G, field, wall * 1e3 / a.steps, combos / a.steps)
+        out["walk_per_round"] = leg_walk(Q, G, field, stream.cuda_stream, wall * 1e3 / a.steps, 3)
         out["batched"] = leg_batched(Q, W, a)
         out["serving"] = leg_serving(Q, W, a)
         out["latency"] = leg_latency(Q, W)

@@ -108,6 +108,18 @@ typedef struct qd_options {
                                  qubits) when that lowers the predicted work by 5% or more
                                  and the work reaches 1e10 combinations; 1 the same at any
                                  work; -1 never (two-row packages first, Sec. 2.3) */
+  int walk;                   /* 0: the saved-sum engine.  k >= 1: the plain per-round walk,
+                                 one launch per (t, Gamma_j) round and a readback of U after
+                                 each: every lane unranks its first package set by its
+                                 revolving-door rank (combinatorial number system), steps
+                                 through k sets (k = 1: chosen from the round size) one
+                                 package out and one in, and walks each set's element
+                                 choices in reflected ternary Gray order, one element XOR
+                                 per codeword.  Every codeword of the chosen matrices is
+                                 enumerated (no scalar classes, mixed packages or partial
+                                 weights).  Rounds of more than 8 packages end the call with
+                                 QD_INCOMPLETE; QD_FILTER_STABILIZER is QD_ERR_INVALID.  At
+                                 most 4096 */
 } qd_options;
 
 /* One (t, Gamma_j) round of the enumeration. */
@@ -220,6 +232,16 @@ int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma,
 int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int *wmin,
                  uint8_t *witness, unsigned long long *count,
                  int partial_words);
+
+/* The same round with the plain walk kernel (qd_options.walk = per_lane,
+ * t <= 8): minimum symplectic weight, one codeword reaching it and the
+ * number of combinations, as qd_round_min.  weight_sum (may be NULL)
+ * receives the sum of the weights of every codeword walked: when some
+ * package has two rows, a one-row package is walked as three equal
+ * elements, so a combination with u one-row packages counts 3^u times. */
+int qd_round_walk(const uint8_t *rows, const int *dims, int P, int n, int t, int per_lane,
+                  int *wmin, uint8_t *witness, unsigned long long *count,
+                  unsigned long long *weight_sum);
 
 /* -- Serving: continuous batching of distance requests ------------------------
  * A qd_engine owns a worker thread and a HIP stream.  Requests are checked

@@ -219,16 +219,22 @@ int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma, 
   return QD_OK;
 }
 
-int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int *wmin, uint8_t *witness,
-                 unsigned long long *count, int partial_words) {
+namespace {
+
+// One round over a caller-given package layout (qd_round_min, qd_round_walk).
+int one_round(const uint8_t *rows, const int *dims, int P, int n, int t, int partial_words, int walk, int *wmin,
+              uint8_t *witness, unsigned long long *count, unsigned long long *weight_sum) {
   if (!rows || !dims || !wmin || !count || P <= 0 || P > 2 * kMaxN || t < 1 || n <= 0) return QD_ERR_INVALID;
   if (n > kMaxN) return QD_ERR_TOO_LARGE;
   if (partial_words < 0 || (partial_words > 0 && partial_words >= (n + 31) / 32)) return QD_ERR_INVALID;
+  if (walk < 0 || walk > 4096) return QD_ERR_INVALID;
   Job job;
   job.n = n;
   job.single_round = true;
   job.t = t;
   job.opt.partial_weight = -1;
+  job.opt.walk = walk;
+  job.want_wsum = weight_sum != nullptr;
   job.force_words = partial_words;
   Gamma g;
   for (int i = 0; i < P; ++i) {
@@ -245,8 +251,9 @@ int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int 
   }
   *wmin = n + 1;
   *count = 0;
+  if (weight_sum) *weight_sum = 0;
   if (t > P) return QD_OK;
-  if (t > kTMax) return QD_ERR_TOO_LARGE;
+  if (t > kTMax || (walk > 0 && t > kWalkMaxT)) return QD_ERR_TOO_LARGE;
   job.use.push_back(g);
   Executor::prepare_gammas(job);
   if (job.gd[0].prefix[size_t(P) * job.gd[0].R + t] >= kSat) return QD_ERR_TOO_LARGE;
@@ -259,8 +266,22 @@ int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int 
   if (job.status < 0) return job.status;
   *wmin = job.U;
   *count = job.visited;
+  if (weight_sum) *weight_sum = job.wsum;
   if (witness && job.U <= n) unpack(job.wit, n, witness);
   return QD_OK;
+}
+
+}  // namespace
+
+int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int *wmin, uint8_t *witness,
+                 unsigned long long *count, int partial_words) {
+  return one_round(rows, dims, P, n, t, partial_words, 0, wmin, witness, count, nullptr);
+}
+
+int qd_round_walk(const uint8_t *rows, const int *dims, int P, int n, int t, int per_lane, int *wmin,
+                  uint8_t *witness, unsigned long long *count, unsigned long long *weight_sum) {
+  if (per_lane < 1) return QD_ERR_INVALID;
+  return one_round(rows, dims, P, n, t, 0, per_lane, wmin, witness, count, weight_sum);
 }
 
 const char *qd_strerror(int status) {

@@ -11,6 +11,7 @@
 namespace qd {
 
 hipError_t launch_round(int D, const LaunchParams &lp, hipStream_t s);
+hipError_t launch_walk(int D, const LaunchParams &lp, bool sum, hipStream_t s);
 hipError_t launch_build(int D, const BuildParams &bp, hipStream_t s);
 hipError_t launch_commit(const LaunchParams &lp, hipStream_t s);
 hipError_t launch_scatter(const CopyRec *rec, int n, const unsigned char *base, hipStream_t s);
@@ -37,6 +38,11 @@ constexpr unsigned long long kSpecExtraRatio = 16;
 // Rounds up to this size skip the saved and tops tables: every lane unranks
 // its whole combination (no table-build launch for small codes).
 constexpr unsigned long long kTinyRound = 1ull << 19;
+// Plain walk: waves per round the automatic choice of package sets per
+// lane aims at, and the most sets a lane takes.
+constexpr unsigned long long kWalkWaves = 1ull << 15;
+constexpr unsigned long long kWalkMaxPerLane = 64;
+constexpr int kWalkMaxOption = 4096;
 constexpr size_t kBigClass = size_t(64) << 20;
 constexpr size_t kSlabMax = size_t(16) << 20;   // largest class carved from slabs
 constexpr size_t kSlabBytes = size_t(64) << 20;
@@ -302,9 +308,17 @@ void Executor::prepare(Job &job) {
   if (o.seg_len < 0 || o.seg_len % kBlock || o.saved_depth < -1 || o.max_gamma < 0 || o.tops_mode < 0 ||
       o.tops_mode > 2 || (o.filter != QD_FILTER_NONE && o.filter != QD_FILTER_STABILIZER) ||
       (o.scalar_classes != 0 && o.scalar_classes != -1) || (o.partial_weight < -1 || o.partial_weight > 1) ||
-      (o.mixed_packages < -1 || o.mixed_packages > 1)) {
+      (o.mixed_packages < -1 || o.mixed_packages > 1) || o.walk < 0 || o.walk > kWalkMaxOption ||
+      (o.walk > 0 && o.filter != QD_FILTER_NONE)) {
     job.status = QD_ERR_INVALID;
     return;
+  }
+  if (o.walk > 0) {
+    // The plain walk enumerates every codeword of the paper's constructions
+    // in the matrices' own qubit order.
+    o.scalar_classes = -1;
+    o.mixed_packages = -1;
+    o.partial_weight = -1;
   }
   int rc = load_rows(job.G.data(), job.m, job.n, job.field, job.basis);
   if (rc) { job.status = rc; return; }
@@ -545,8 +559,9 @@ int Executor::flush(hipStream_t s, const unsigned char **base, size_t *desc_off)
   if (!alloc(stage_dev_, need)) return QD_ERR_NOMEM;
   const unsigned char *dev = static_cast<const unsigned char *>(stage_dev_.p);
   for (size_t i = 0; i < descs_.size(); ++i) {
-    descs_[i].groups = reinterpret_cast<const DevGroup *>(dev + desc_groups_[2 * i]);
-    descs_[i].runs = reinterpret_cast<const DevRun *>(dev + desc_groups_[2 * i + 1]);
+    descs_[i].groups = reinterpret_cast<const DevGroup *>(dev + desc_groups_[3 * i]);
+    descs_[i].runs = reinterpret_cast<const DevRun *>(dev + desc_groups_[3 * i + 1]);
+    descs_[i].binom = reinterpret_cast<const unsigned long long *>(dev + desc_groups_[3 * i + 2]);
   }
   const size_t doff = staging_.put(descs_.data(), descs_.size() * sizeof(RoundDesc));
   const size_t boff = staging_.put(bl.data(), bl.size() * sizeof(SavedParams));
@@ -631,6 +646,35 @@ int Executor::schedule(Job &job, int sharing) {
       if (extra + planned > extra_cap) return QD_OK;
       extra += planned;
     }
+    if (job.opt.walk > 0) {
+      // Plain walk: this round alone in the step, in one launch.
+      if (t > kWalkMaxT) {
+        if (job.fl.empty()) job.incomplete = job.done = true;
+        return QD_OK;
+      }
+      Flight f;
+      f.t = t;
+      f.j = job.j;
+      f.walk = true;
+      f.use_tops = false;
+      f.L_before = job.single_round ? -1 : lower_bound(tsim, job.delta, job.halve);
+      f.radix = 1;
+      for (int sz : g.sizes) f.radix = sz == 3 ? 3 : f.radix;
+      const size_t ld = size_t(t) + 1;
+      f.binom.assign(size_t(g.P + 1) * ld, 0);
+      for (int p = 0; p <= g.P; ++p)
+        for (int r = 0; r <= t; ++r)
+          f.binom[p * ld + r] = r == 0 ? 1 : p == 0 ? 0 : f.binom[(p - 1) * ld + r] + f.binom[(p - 1) * ld + r - 1];
+      f.subsets = f.binom[size_t(g.P) * ld + t];
+      f.per_lane = job.opt.walk >= 2
+                       ? static_cast<unsigned long long>(job.opt.walk)
+                       : std::min(kWalkMaxPerLane, std::max<unsigned long long>(1, f.subsets / (kWave * kWalkWaves)));
+      f.tiles = (f.subsets + kWave * f.per_lane - 1) / (kWave * f.per_lane);
+      f.planned = planned;
+      job.fl.push_back(std::move(f));
+      ++job.j;
+      return QD_OK;
+    }
     Flight f;
     f.t = t;
     f.j = job.j;
@@ -713,6 +757,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   const double ts_sched = trace ? now_ms() : 0.0;
   struct Launch {
     int D;
+    bool walk, sum;  // plain walk kernel; with the weight sum
     size_t d0, d1;
     unsigned long long tiles;
     unsigned lds;
@@ -727,11 +772,12 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   descs_.clear();
   desc_groups_.clear();
   unsigned long long max_tiles = 0;
+  for (int wk = 0; wk <= 1; ++wk)
   for (int D = 1; D <= 4; ++D) {
-    Launch L{D, descs_.size(), 0, 0, 0, false};
+    Launch L{D, wk == 1, false, descs_.size(), 0, 0, 0, false};
     for (Job *jp : jobs) {
       Job &job = *jp;
-      if (job.done || job.D != D || job.status) continue;
+      if (job.done || job.D != D || job.status || (job.opt.walk > 0) != (wk == 1)) continue;
       bool first = true;  // the first piece of the code in this launch commits it
       for (size_t fi = 0; fi < job.fl.size(); ++fi) {
         Flight &f = job.fl[fi];
@@ -746,9 +792,11 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         // groups and runs travel with this step's upload (set by flush)
         const size_t go = staging_.put(f.hg.data(), f.hg.size() * sizeof(DevGroup));
         const size_t ro = staging_.put(f.hr.data(), f.hr.size() * sizeof(DevRun));
-        if (go == SIZE_MAX || ro == SIZE_MAX) return QD_ERR_NOMEM;
+        const size_t bo = staging_.put(f.binom.data(), f.binom.size() * sizeof(unsigned long long));
+        if (go == SIZE_MAX || ro == SIZE_MAX || bo == SIZE_MAX) return QD_ERR_NOMEM;
         desc_groups_.push_back(go);
         desc_groups_.push_back(ro);
+        desc_groups_.push_back(bo);
         d.suffix = g.dsuffix;
         d.csize = g.csize;
         d.state = states_ + job.state_slot;
@@ -786,6 +834,15 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         if (first) ++job.S.launches;
         first = false;
         unsigned lds = round_lds_bytes(d.P, d.t, d.u, d.ngroups, d.stage);
+        if (f.walk) {
+          d.subsets = f.subsets;
+          d.per_lane = f.per_lane;
+          d.radix = f.radix;
+          d.wsum = job.want_wsum ? d.counters + 2 : nullptr;  // word 2 of the first counter line
+          L.sum = L.sum || job.want_wsum;
+          d.stage = 1;
+          lds = walk_lds_bytes(d.P, d.t);
+        }
         if (lds > kStageMaxBytes) { d.stage = 0; lds = 0; }
         L.lds = std::max(L.lds, lds);
         L.timed = L.timed || job.opt.timing;
@@ -823,7 +880,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
       lp.tiles = L.tiles;
       lp.slots = static_cast<uint32_t *>(slots_.p);
       if (L.timed && hipEventRecord(events_[2 * i], s) != hipSuccess) return QD_ERR_DEVICE;
-      if (launch_round(L.D, lp, s) != hipSuccess) return QD_ERR_DEVICE;
+      if ((L.walk ? launch_walk(L.D, lp, L.sum, s) : launch_round(L.D, lp, s)) != hipSuccess) return QD_ERR_DEVICE;
       if (L.timed && hipEventRecord(events_[2 * i + 1], s) != hipSuccess) return QD_ERR_DEVICE;
       if (launch_commit(lp, s) != hipSuccess) return QD_ERR_DEVICE;
     }
@@ -902,6 +959,10 @@ void Executor::retire(Job &job) {
     }
     S.wall_ms = t1 - job.t0;
   }
+  if (job.want_wsum && job.data.p && !job.status &&
+      hipMemcpy(&job.wsum, static_cast<unsigned long long *>(job.data.p) + 2, sizeof(job.wsum),
+                hipMemcpyDeviceToHost) != hipSuccess)
+    job.status = QD_ERR_DEVICE;
   for (GammaDev &g : job.gd) {
     g.elems = nullptr; g.csize = nullptr; g.dprefix = g.dsuffix = nullptr;
     g.inv = nullptr; g.logicals = nullptr;

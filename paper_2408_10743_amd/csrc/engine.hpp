@@ -91,6 +91,12 @@ struct Flight {
   unsigned long long tiles = 0, sent = 0, planned = 0;
   int launches = 0;
   float ms = 0.f;
+  // Plain walk (qd_options.walk): one launch per round, one wave per 64
+  // lanes of per_lane package sets each.
+  bool walk = false;
+  int radix = 1;
+  unsigned long long subsets = 0, per_lane = 1;
+  std::vector<unsigned long long> binom;  // C(p, r), p <= P, r <= t
 };
 
 // One code: request, plan, device data and progress through its rounds.
@@ -113,6 +119,8 @@ struct Job {
   bool partial = false; // partial weights (matrices stored in their qubit order)
   std::vector<int> caps; // mixed packages: two-row caps of the F4 matrices (empty: none)
   int force_words = 0;   // > 0: every tile evaluates this many words first (no credit)
+  bool want_wsum = false;        // plain walk: sum the weights of the walked codewords
+  unsigned long long wsum = 0;   // (read back by retire)
   std::vector<BRow> logicals;  // Modified BZ: the admission test's operators
   std::vector<GammaDev> gd;
   int state_slot = -1;
@@ -191,7 +199,7 @@ class Executor {
   uint32_t *zero_table_ = nullptr;  // the saved table of depth 0: one zero entry
   std::vector<SavedParams> builds_[5];  // queued table builds per word count
   std::vector<RoundDesc> descs_;
-  std::vector<size_t> desc_groups_;  // staged offsets of each piece's groups and runs
+  std::vector<size_t> desc_groups_;  // staged offsets of each piece's groups, runs and binomials
   std::vector<hipEvent_t> events_;
 };
 

@@ -1,5 +1,5 @@
-// kernels.hpp -- device data layouts of the enumeration kernel (round.hip),
-// shared with its host-side launch code.
+// kernels.hpp -- device data layouts of the enumeration kernels (round.hip,
+// walk.hip), shared with their host-side launch code.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -20,6 +20,9 @@ constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 // Visited-combination counters are spread over separate 128-byte lines so
 // the waves of a launch do not all update one address.
 constexpr int kCounterStride = 16;  // unsigned long longs per line
+// Deepest round the plain walk kernel (walk.hip) supports: packages per
+// combination, each in a VGPR slot of its lane.
+constexpr int kWalkMaxT = 8;
 
 // One group of a round: top combinations whose smallest package is h,
 // paired with the saved-table prefix of combinations below h.  Groups are
@@ -93,6 +96,12 @@ struct RoundDesc {
   int stage;                           // 1: copy the groups to LDS; 2: also suffix
                                        //    columns and elements (unranking path)
   int commit;                          // 1 for the first piece of its code in the launch
+  // Plain walk kernel (walk.hip) only.
+  const unsigned long long *binom;     // C(p, r) at p * (t + 1) + r, p <= P, r <= t
+  unsigned long long *wsum;            // sum of the walked codewords' weights (NULL: not taken)
+  unsigned long long subsets;          // package sets of the round, C(P, t)
+  unsigned long long per_lane;         // package sets per lane
+  int radix;                           // 3 if some package has three elements, else 1
 };
 
 struct LaunchParams {
@@ -109,6 +118,11 @@ inline unsigned int round_lds_bytes(int P, int t, int u, int ngroups, int stage)
   unsigned int b = static_cast<unsigned int>(ngroups * sizeof(DevGroup));
   if (stage == 2) b += static_cast<unsigned int>((P + 1) * (t - u) * 8 + P * 3 * kElemWords * 4);
   return b;
+}
+
+// LDS bytes a walk kernel launch needs to stage binomials and elements.
+inline unsigned int walk_lds_bytes(int P, int t) {
+  return static_cast<unsigned int>((P + 1) * (t + 1) * 8 + P * 3 * kElemWords * 4);
 }
 
 // XOR of element e of package pkg into a codeword of D words per half.

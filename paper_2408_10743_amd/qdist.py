@@ -49,7 +49,7 @@ class qd_options(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("seg_len", ctypes.c_int),
                 ("saved_depth", ctypes.c_int), ("timing", ctypes.c_int), ("tops_mode", ctypes.c_int),
                 ("filter", ctypes.c_int), ("scalar_classes", ctypes.c_int),
-                ("partial_weight", ctypes.c_int), ("mixed_packages", ctypes.c_int)]
+                ("partial_weight", ctypes.c_int), ("mixed_packages", ctypes.c_int), ("walk", ctypes.c_int)]
 
 
 class qd_round_log(ctypes.Structure):
@@ -118,6 +118,8 @@ _lib.qd_plan.argtypes = [_u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.
                          ctypes.POINTER(qd_plan_info)]
 _lib.qd_round_min.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _u8p,
                               ctypes.POINTER(ctypes.c_ulonglong), ctypes.c_int]
+_lib.qd_round_walk.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _u8p,
+                               ctypes.POINTER(ctypes.c_ulonglong), ctypes.POINTER(ctypes.c_ulonglong)]
 _lib.qd_device_check.argtypes = [ctypes.c_char_p, ctypes.c_int]
 _lib.qd_engine_create.restype = ctypes.c_void_p
 _lib.qd_engine_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
@@ -175,7 +177,7 @@ def qd_distance_ex(G, field=QD_FIELD_F2, **opts):
     """Returns (status, d, witness, qd_stats).  Options: diag, max_gamma,
     budget, cancel (ctypes.c_int), stream (hipStream_t as int), seg_len,
     saved_depth, timing, tops_mode, filter, scalar_classes, partial_weight,
-    mixed_packages."""
+    mixed_packages, walk."""
     G, m, n = _matrix(G, field)
     o, _keep = _options(opts)
     d = ctypes.c_int(-1)
@@ -241,6 +243,23 @@ def qd_round_min(rows, dims, t, partial_words=0):
     return st, w.value, wit, cnt.value
 
 
+def qd_round_walk(rows, dims, t, per_lane=1, weight_sum=False):
+    """One round with the plain walk kernel: returns (status, wmin, witness,
+    count, weight sum or None)."""
+    rows = np.ascontiguousarray(rows, dtype=np.uint8)
+    dims = np.ascontiguousarray(dims, dtype=np.int32)
+    P = dims.shape[0]
+    n = rows.shape[1] // 2
+    w = ctypes.c_int(0)
+    cnt = ctypes.c_ulonglong(0)
+    ws = ctypes.c_ulonglong(0)
+    wit = np.zeros(2 * n, dtype=np.uint8)
+    st = _lib.qd_round_walk(rows.ctypes.data_as(_u8p), dims.ctypes.data_as(_ip), P, n, t, per_lane,
+                            ctypes.byref(w), wit.ctypes.data_as(_u8p), ctypes.byref(cnt),
+                            ctypes.byref(ws) if weight_sum else None)
+    return st, w.value, wit, cnt.value, (ws.value if weight_sum else None)
+
+
 def qd_device_check():
     buf = ctypes.create_string_buffer(64)
     st = _lib.qd_device_check(buf, 64)
@@ -296,5 +315,5 @@ def qd_engine_destroy(engine):
 def exported_symbols():
     """Names of the C ABI entry points declared in include/qdist.h."""
     return ["qd_distance", "qd_distance_ex", "qd_distance_batch", "qd_distance_batch_ex", "qd_plan",
-            "qd_round_min", "qd_strerror", "qd_device_check", "qd_valu_peak", "qd_valu_mix", "qd_engine_create",
+            "qd_round_min", "qd_round_walk", "qd_strerror", "qd_device_check", "qd_valu_peak", "qd_valu_mix", "qd_engine_create",
             "qd_engine_submit", "qd_engine_poll", "qd_engine_outstanding", "qd_engine_destroy"]
