@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "wave.hpp"
 
 namespace qd {
 
@@ -41,11 +42,7 @@ __device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
   return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
-__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = min(v, static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), off)));
-  return v;
-}
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) { return wave_min_u32(v); }
 
 // Weight of (lane codeword) ^ (table entry k); k is wavefront-uniform.
 template <int D>
@@ -201,17 +198,9 @@ __device__ void unrank_top(const unsigned long long *F, int ld, const uint32_t *
   }
 }
 
-__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = max(v, static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), off)));
-  return v;
-}
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) { return wave_max_u32(v); }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), off));
-  return v;
-}
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return wave_sum_u32(v); }
 
 // Modified BZ: a codeword of the span is outside its radical (the
 // stabilizer) when its symplectic product with some logical operator is 1.

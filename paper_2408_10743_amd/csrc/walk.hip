@@ -26,6 +26,7 @@
 #define QD_HD __host__ __device__
 #include "kernels.hpp"
 #include "revdoor.hpp"
+#include "wave.hpp"
 
 namespace qd {
 namespace {
@@ -43,24 +44,10 @@ __device__ __forceinline__ unsigned long long uniform64w(unsigned long long v) {
   return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_reduce_min(T v) {
+// 64-bit sums (combination and codeword counts; once per wave).
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = min(v, static_cast<T>(__shfl_xor(v, off)));
-  return v;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_reduce_max(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = max(v, static_cast<T>(__shfl_xor(v, off)));
-  return v;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_reduce_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += static_cast<T>(__shfl_xor(v, off));
+  for (int off = 32; off > 0; off >>= 1) v += static_cast<unsigned long long>(__shfl_xor(v, off));
   return v;
 }
 
@@ -401,7 +388,7 @@ __global__ __launch_bounds__(256) void qd_walk_kernel(LaunchParams lp) {
   unsigned long long s0 = (g * kWave + lane) * K;
   s0 = min(s0, p.subsets);
   const unsigned long long s1 = min(s0 + K, p.subsets);
-  const uint32_t rw = __builtin_amdgcn_readfirstlane(wave_reduce_max(static_cast<uint32_t>(s1 - s0)));
+  const uint32_t rw = wave_max_u32(static_cast<uint32_t>(s1 - s0));
   uint32_t nstep = 1;
   if (p.radix == 3)
     for (int i = 0; i < p.t; ++i) nstep *= 3;
@@ -409,10 +396,10 @@ __global__ __launch_bounds__(256) void qd_walk_kernel(LaunchParams lp) {
   unsigned long long sets = 0, walked = 0;
   Visit<D, MODE> v;
   walk_range<D, MODE>(p, E, BN, s0, s1, rw, nstep, v, sets, walked);
-  const uint32_t wmin = wave_reduce_min(v.best);
-  const unsigned long long wsets = wave_reduce_sum(sets), wwalked = wave_reduce_sum(walked);
+  const uint32_t wmin = wave_min_u32(v.best);
+  const unsigned long long wsets = wave_sum_u64(sets), wwalked = wave_sum_u64(walked);
   unsigned long long wsum = 0;
-  if constexpr (MODE == kWalkSum) wsum = wave_reduce_sum(v.wsum);
+  if constexpr (MODE == kWalkSum) wsum = wave_sum_u64(v.wsum);
   if (lane == 0) {
     unsigned long long *cnt = p.counters + static_cast<size_t>(g % kCountersPerCode) * kCounterStride;
     atomicAdd(cnt, wsets);
