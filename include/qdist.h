@@ -61,7 +61,8 @@ extern "C" {
                                   counts every codeword, as the paper prescribes. */
 
 #define QD_OK 0
-#define QD_INCOMPLETE 1 /* budget or cancel: *d = U, stats hold L <= d <= U */
+#define QD_INCOMPLETE 1 /* budget, cancel or (plain walk) a round deeper than 8 packages:
+                           *d = U, stats hold L <= d <= U */
 #define QD_ERR_INVALID (-1)
 #define QD_ERR_ZERO_CODE (-2)
 #define QD_ERR_TOO_LARGE (-3)

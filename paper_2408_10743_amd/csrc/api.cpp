@@ -287,7 +287,7 @@ int qd_round_walk(const uint8_t *rows, const int *dims, int P, int n, int t, int
 const char *qd_strerror(int status) {
   switch (status) {
     case QD_OK: return "ok";
-    case QD_INCOMPLETE: return "incomplete: budget or cancel reached before the bounds met";
+    case QD_INCOMPLETE: return "incomplete: budget, cancel or walk depth reached before the bounds met";
     case QD_ERR_INVALID: return "invalid argument";
     case QD_ERR_ZERO_CODE: return "the rows span the zero code";
     case QD_ERR_TOO_LARGE: return "problem too large (n > 128 or round beyond the supported depth)";

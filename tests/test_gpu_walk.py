@@ -141,6 +141,24 @@ def test_walk_distances(Q):
             assert s.L <= d_ref <= s.U
 
 
+def test_walk_depth_limit_gives_bounds(Q):
+    """A round deeper than 8 packages ends the walk with QD_INCOMPLETE and
+    certified bounds: 12 random rows on 128 qubits under the F2
+    construction (one matrix of 12 packages, distance far above the L = 9
+    that rounds t <= 8 certify)."""
+    B = W.additive(128, 12, W.config_seed(85, 0))
+    d_ref = O.brute(B)[0]
+    st, d, wit, s = Q.qd_distance_ex(B, 2, diag=Q.QD_DIAG_F2, walk=1)
+    print(f"depth limit: status={st} L={s.L} U={s.U} d={d_ref}", flush=True)
+    assert st == Q.QD_INCOMPLETE
+    assert s.L == 9 - s.delta[0] and s.L <= d_ref <= s.U == d
+    assert swt(wit) == d and O.in_rowspace(B, wit)
+    assert max(r["t"] for r in s.rounds()) == 8
+    # the engine certifies the same code exactly
+    st2, d2, _, _ = Q.qd_distance_ex(B, 2, diag=Q.QD_DIAG_F2)
+    assert st2 == 0 and d2 == d_ref
+
+
 def test_walk_options(Q):
     G, f = W.config1(0)
     assert Q.qd_distance_ex(G, f, walk=-1)[0] == Q.QD_ERR_INVALID
