@@ -33,7 +33,7 @@ PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # 1 GiB device copy in the same runs), valid only for the kernel source
 # with this fingerprint (sha256 prefixes of round.hip and kernels.hpp, the
 # enumeration kernel and its data layouts).
-TRAFFIC = {"fingerprint": "f3b69f73e357f817eeb55ec984aadd4b", "bytes_per_launch": 843063336}
+TRAFFIC = {"fingerprint": "b79c2dc3b3e6ea2bd261fadf342811a4", "bytes_per_launch": 842924524}
 
 
 def kernel_fingerprint():
@@ -78,6 +78,9 @@ def parse():
                     help="also run 3 device copies of 1 GiB (reference for HBM byte counters)")
     ap.add_argument("--valu-probe", action="store_true",
                     help="only time the VALU instruction mixes of qd_valu_mix and print their rates")
+    ap.add_argument("--walk-only", action="store_true",
+                    help="only run the plain per-round walk on the same code (--steps timed calls after "
+                         "one warm-up call), for a profiler")
     ap.add_argument("--round-sweep", action="store_true",
                     help="only run one large round (48 two-row packages, t = 6) at D = 1..4 words per "
                          "half, for per-D kernel durations from a profiler")
@@ -395,6 +398,9 @@ def main():
         return
     stream = torch.cuda.current_stream()
     G, field = W.config3(a.seed)
+    if a.walk_only:
+        print(json.dumps({"walk_per_round": leg_walk(Q, G, field, stream.cuda_stream, float("nan"), a.steps)}))
+        return
 
     def step():
         st, d, wit, s = Q.qd_distance_ex(G, field, stream=stream.cuda_stream, timing=1)
