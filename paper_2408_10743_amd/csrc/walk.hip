@@ -16,8 +16,9 @@
 // r^s; 1 <-> 2: r).  The walk continues from the digits where the previous
 // set left them (all 2 after an even set, all 0 after an odd one), so the
 // whole lane range is one reflected Gray walk.  Every lane of a wave is at
-// the same step, so the digit that moves is wave-uniform and each step is
-// one XOR per word from VGPRs at a static index, an OR and a v_bcnt per
+// the same step, so the digit that moves is wave-uniform: its row sits at a
+// static VGPR index (digits 0 and 1, 8 of every 9 steps) or is read from
+// LDS (the others).  A step is one XOR per word, an OR and a v_bcnt per
 // word, and a min.  A package with one row is walked as three equal
 // elements (digit moves XOR zero): its codewords are visited three times
 // per digit sweep, counted once.
