@@ -772,12 +772,15 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   descs_.clear();
   desc_groups_.clear();
   unsigned long long max_tiles = 0;
-  for (int wk = 0; wk <= 1; ++wk)
-  for (int D = 1; D <= 4; ++D) {
-    Launch L{D, wk == 1, false, descs_.size(), 0, 0, 0, false};
+  // One launch per word count D for the saved-sum kernel, then per D for
+  // the codes on the plain walk.
+  for (int kind = 0; kind < 8; ++kind) {
+    const int D = kind % 4 + 1;
+    const bool walk = kind >= 4;
+    Launch L{D, walk, false, descs_.size(), 0, 0, 0, false};
     for (Job *jp : jobs) {
       Job &job = *jp;
-      if (job.done || job.D != D || job.status || (job.opt.walk > 0) != (wk == 1)) continue;
+      if (job.done || job.D != D || job.status || (job.opt.walk > 0) != walk) continue;
       bool first = true;  // the first piece of the code in this launch commits it
       for (size_t fi = 0; fi < job.fl.size(); ++fi) {
         Flight &f = job.fl[fi];

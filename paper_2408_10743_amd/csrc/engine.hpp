@@ -1,8 +1,9 @@
 // engine.hpp -- the step executor shared by the single-code, batched and
 // serving entry points.  A step launches, for every active code, the next
 // piece of its current (t, Gamma_j) round; all pieces of codes with the
-// same word count D go into one kernel launch, followed by one commit
-// launch and one readback of every code's state.
+// same word count D go into one kernel launch (the saved-sum kernel, or the
+// plain walk kernel for codes that ask for it), each followed by one commit
+// launch, and the step ends with one readback of every code's state.
 #pragma once
 #include <hip/hip_runtime.h>
 
