@@ -9,6 +9,8 @@ counts 3^u times when some package has two rows), which a skipped or
 repeated codeword would change.  Distances with the walk equal the
 oracle's."""
 import itertools
+import json
+import os
 
 import numpy as np
 import pytest
@@ -139,6 +141,23 @@ def test_walk_distances(Q):
             assert d == d_ref and swt(wit) == d and O.in_rowspace(B, wit)
         else:  # a round deeper than 8 packages: certified bounds only
             assert s.L <= d_ref <= s.U
+
+
+def test_walk_config3(Q):
+    """Config 3 as bench.py's walk leg runs it: the golden distance, every
+    round but the last walked whole, and the same per-round minima and
+    bounds as the saved-sum engine with every word evaluated."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_distances.json")))
+    G, f = W.config3(0)
+    st, d, wit, s = Q.qd_distance_ex(G, f, walk=1, timing=1)
+    st2, d2, _, s2 = Q.qd_distance_ex(G, f, partial_weight=-1, mixed_packages=-1)
+    print(f"config3 walk d={d} in {s.wall_ms:.2f} ms, engine d={d2}", flush=True)
+    assert st == st2 == 0 and d == d2 == gold["config3"][0]
+    assert swt(wit) == d and O.in_rowspace(O.expand(G, f), wit)
+    rw, re_ = s.rounds(), s2.rounds()
+    assert [(r["t"], r["j"], r["L"]) for r in rw] == [(r["t"], r["j"], r["L"]) for r in re_]
+    assert all(r["combinations"] == r["planned"] for r in rw[:-1])
+    assert all(r["launches"] == 1 for r in rw)
 
 
 def test_walk_depth_limit_gives_bounds(Q):
