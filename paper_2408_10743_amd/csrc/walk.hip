@@ -57,8 +57,9 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // digit's first move in the set's even blocks, y: the other; an even set
 // starts with its digits rising, x = r^s, y = r).  The other digits move
 // once per 9 steps and read their row from the staged elements: bits
-// 10 (j - 2) .. of `high` hold slot j's package (8 bits) and whether it has
-// one row (bit 8), so the wave-uniform j selects it by a shift.
+// 10 (j - 2) .. of `high` hold slot j's package (8 bits: a matrix has at
+// most 2 x 128 packages) and whether it has one row (bit 8), so the
+// wave-uniform j selects it by a shift.
 template <int D>
 struct Slots {
   uint32_t x0[2 * D], y0[2 * D], x1[2 * D], y1[2 * D];
@@ -305,6 +306,9 @@ __device__ void walk_range(const RoundDesc &p, const uint32_t *E, const unsigned
           if (k < t && !in_new) out = s.pkg[k];
           if (k < t && !in_old) in = nx[k];
         }
+        // Consecutive ranks always differ by one package each way; should
+        // they not, the codeword is left alone rather than read out of range.
+        if (out < 0 || in < 0) out = in = s.pkg[0];
         const int vend = p.radix == 3 && ((o - 1) & 1u) == 0 ? 2 : 0;
         uint32_t eo[2 * D], ei[2 * D];
         load_elem<D>(E, p.csize, out, vend, eo);
