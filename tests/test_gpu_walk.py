@@ -105,13 +105,13 @@ def test_walk_round_limits(Q):
 
 
 def test_walk_distances(Q):
-    """qd_distance with the walk: config 1 against brute force (F4 and F2
-    constructions), config 2 and small additive codes against the oracle's
+    """qd_distance with the walk: config 1 against brute force (F4, F2 and
+    isometry constructions), config 2 and small additive codes against the oracle's
     BZ; every round but the last is walked whole."""
     for i in range(6):
         G, f = W.config1(i)
         d_ref = O.brute(O.expand(G, f))[0]
-        for diag, walk in [(Q.QD_DIAG_F4, 1), (Q.QD_DIAG_F4, 3), (Q.QD_DIAG_F2, 2)]:
+        for diag, walk in [(Q.QD_DIAG_F4, 1), (Q.QD_DIAG_F4, 3), (Q.QD_DIAG_F2, 2), (Q.QD_DIAG_ISO, 1)]:
             st, d, wit, s = Q.qd_distance_ex(G, f, diag=diag, walk=walk)
             print(f"config1 {i} diag={diag} walk={walk} d={d} ref={d_ref}", flush=True)
             assert st == 0 and d == d_ref and swt(wit) == d
