@@ -178,6 +178,36 @@ def test_walk_depth_limit_gives_bounds(Q):
     assert st2 == 0 and d2 == d_ref
 
 
+def test_walk_and_engine_codes_share_steps(Q):
+    """Requests on the walk and on the saved-sum engine in one serving
+    engine: their pieces run in the same steps (one launch kind each), and
+    every result equals the code alone on its own path."""
+    import time
+    codes = [W.config1(i) for i in range(6)] + [W.config2(i) for i in range(3)]
+    alone = {}
+    for i, (G, f) in enumerate(codes):
+        walk = 1 if i % 2 else 0
+        st, d, _, _ = Q.qd_distance_ex(G, f, walk=walk)
+        assert st == 0
+        alone[i] = d
+    eng = Q.qd_engine_create()
+    assert eng
+    try:
+        for i, (G, f) in enumerate(codes):
+            assert Q.qd_engine_submit(eng, G, f, tag=i, walk=1 if i % 2 else 0) == 0
+        got = {}
+        t0 = time.time()
+        while len(got) < len(codes) and time.time() - t0 < 60:
+            for r, wit in Q.qd_engine_poll(eng, 64, 100):
+                got[r.tag] = (r.status, r.d, swt(wit))
+        print(f"mixed engine: {got}", flush=True)
+        assert len(got) == len(codes)
+        for i in range(len(codes)):
+            assert got[i] == (0, alone[i], alone[i])
+    finally:
+        Q.qd_engine_destroy(eng)
+
+
 def test_walk_options(Q):
     G, f = W.config1(0)
     assert Q.qd_distance_ex(G, f, walk=-1)[0] == Q.QD_ERR_INVALID
