@@ -24,6 +24,11 @@ constexpr unsigned long long kMaxTopEntries = 1ull << 24;  // 512 MB of tops
 constexpr unsigned long long kTilesPerLaunch = 1ull << 21;
 constexpr unsigned long long kTargetTiles = 1ull << 18;    // ~32 tiles per wave slot
 constexpr unsigned kMinSeg = 256, kMaxSeg = 4096;
+// Rounds below kShortRound combinations start from kShortSeg entries per
+// tile: a step of small rounds is bound by each tile's chain of dependent
+// table loads, so shorter tiles finish sooner.
+constexpr unsigned long long kShortRound = 1ull << 24;
+constexpr unsigned kShortSeg = 64;
 // Partial weights for codes whose planned work reaches this many combinations.
 constexpr double kPartialMinWork = 1e8;
 constexpr unsigned kStageMaxBytes = 32768;
@@ -101,7 +106,7 @@ unsigned choose_seg(unsigned long long planned, int sharing) {
   const unsigned long long want = planned / (kWave * target);
   // With many codes in a step the device is filled by their number, so
   // tiles can stay long (the per-tile setup then costs under a few %).
-  unsigned seg = sharing > 8 ? 4 * kMinSeg : kMinSeg;
+  unsigned seg = sharing > 8 ? 4 * kMinSeg : planned < kShortRound ? kShortSeg : kMinSeg;
   while (seg < want && seg < kMaxSeg) seg <<= 1;
   return seg;
 }
