@@ -85,6 +85,16 @@ def test_walk_deep_digits(Q):
         check_round(Q, rows, dims, t, 3, P <= 8)
 
 
+def test_walk_many_packages(Q):
+    """Up to 256 packages: the elements and binomials no longer fit the
+    LDS staging (read from global memory instead), and package numbers above
+    127 sit in the high digits' 8-bit fields."""
+    for P, t, frac, n in [(150, 3, 0.5, 100), (256, 4, 0.0, 128), (96, 4, 0.0, 64)]:
+        rows, dims = W.random_packages(P, n, W.config_seed(86, P + t), frac)
+        print(f"many packages P={P} t={t}", flush=True)
+        check_round(Q, rows, dims, t, 2, False)
+
+
 def test_walk_many_waves(Q):
     """A round of 1.7e8 combinations over several thousand waves."""
     rows, dims = W.random_packages(30, 72, W.config_seed(82, 0), 1.0)
