@@ -88,11 +88,16 @@ def test_walk_deep_digits(Q):
 def test_walk_many_packages(Q):
     """Up to 256 packages: the elements and binomials no longer fit the
     LDS staging (read from global memory instead), and package numbers above
-    127 sit in the high digits' 8-bit fields."""
+    127 sit in the high digits' 8-bit fields.  The saved-sum engine runs the
+    same rounds."""
     for P, t, frac, n in [(150, 3, 0.5, 100), (256, 4, 0.0, 128), (96, 4, 0.0, 64)]:
         rows, dims = W.random_packages(P, n, W.config_seed(86, P + t), frac)
         print(f"many packages P={P} t={t}", flush=True)
         check_round(Q, rows, dims, t, 2, False)
+        # the saved-sum engine on the same round
+        st0, w0, wit0, c0 = Q.qd_round_min(rows, dims, t)
+        wo, _, co = O.round_min(rows, dims, t)
+        assert st0 == 0 and (w0, c0) == (wo, co) and swt(wit0) == w0
 
 
 def test_walk_many_waves(Q):
