@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--walk-only", action="store_true",
                     help="only run the plain per-round walk on the same code (--steps timed calls after "
                          "one warm-up call), for a profiler")
+    ap.add_argument("--latency-only", action="store_true",
+                    help="only run the time-to-exact-d leg on configs 1 and 2, for a profiler")
     ap.add_argument("--round-sweep", action="store_true",
                     help="only run one large round (48 two-row packages, t = 6) at D = 1..4 words per "
                          "half, for per-D kernel durations from a profiler")
@@ -398,6 +400,9 @@ def main():
         return
     stream = torch.cuda.current_stream()
     G, field = W.config3(a.seed)
+    if a.latency_only:
+        print(json.dumps({"latency": leg_latency(Q, W)}))
+        return
     if a.walk_only:
         print(json.dumps({"walk_per_round": leg_walk(Q, G, field, stream.cuda_stream, float("nan"), a.steps)}))
         return
