@@ -235,13 +235,8 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   const uint32_t wg = ((r / kXcdChunk) * 8 + xcd) * kXcdChunk + r % kXcdChunk;
   const unsigned long long wtile = static_cast<unsigned long long>(wg) * kWavesPerGroup;
   if (wtile >= lp.tiles) return;  // whole workgroup: launch padding
-  int lo = 0, hi = lp.ndesc;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (lp.desc[mid].tile_begin <= wtile) lo = mid;
-    else hi = mid;
-  }
-  const RoundDesc &p = lp.desc[lo];
+  const RoundDesc *const descs = lp.desc;
+  const RoundDesc &p = descs[wave_last_le(lp.ndesc, wtile, [descs](int i) { return descs[i].tile_begin; })];
 
   // Unranking reads suffix columns, the group table and the elements with
   // data-dependent addresses: stage them in LDS once per workgroup.
@@ -277,14 +272,8 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   unsigned long long key = uniform64(*reinterpret_cast<volatile unsigned long long *>(&st->key));
   if (static_cast<int>(key >> 32) <= p.L_before) return;  // bound already met
 
-  lo = 0;
-  hi = p.nruns;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (p.runs[mid].tile0 <= g) lo = mid;
-    else hi = mid;
-  }
-  const DevRun &run = p.runs[lo];
+  const DevRun *const runs = p.runs;
+  const DevRun &run = runs[wave_last_le(p.nruns, g, [runs](int i) { return runs[i].tile0; })];
   const unsigned long long rl = g - run.tile0;
   unsigned long long b, s;
   if ((rl >> 32) == 0 && (run.tps >> 32) == 0) {

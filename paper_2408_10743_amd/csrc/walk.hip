@@ -359,13 +359,8 @@ __global__ __launch_bounds__(256) void qd_walk_kernel(LaunchParams lp) {
   extern __shared__ unsigned long long smem[];
   const unsigned long long wtile = static_cast<unsigned long long>(blockIdx.x) * kWavesPerGroup;
   if (wtile >= lp.tiles) return;  // whole workgroup: launch padding
-  int lo = 0, hi = lp.ndesc;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (lp.desc[mid].tile_begin <= wtile) lo = mid;
-    else hi = mid;
-  }
-  const RoundDesc &p = lp.desc[lo];
+  const RoundDesc *const descs = lp.desc;
+  const RoundDesc &p = descs[wave_last_le(lp.ndesc, wtile, [descs](int i) { return descs[i].tile_begin; })];
   // The elements and binomials are read with per-lane addresses when a lane
   // unranks or changes sets: stage them in LDS once per workgroup.
   const uint32_t *E = p.elems;

@@ -47,4 +47,30 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
   return wave_reduce_dpp(v, 0u, [](uint32_t a, uint32_t b) { return a + b; });
 }
 
+// Index of the last of n ascending keys (key(0) <= x) that is <= x, found
+// with one or two rounds of loads spread over the wavefront's lanes (the
+// keys of a chunk of 64, after those of every 64th key when n > 64)
+// instead of a chain of log2(n) dependent loads.  n <= 4096 (larger: a
+// binary search).  Every lane must be active; the result is uniform.
+template <typename Key>
+__device__ __forceinline__ int wave_last_le(int n, unsigned long long x, Key key) {
+  if (n > 64 * 64) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (key(mid) <= x) lo = mid;
+      else hi = mid;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+  }
+  const int lane = static_cast<int>(threadIdx.x & 63);
+  int chunk = 0;
+  if (n > 64) {
+    const int i = lane * 64;
+    chunk = __builtin_amdgcn_readfirstlane(__popcll(__ballot(i < n && key(i) <= x)) - 1);
+  }
+  const int i = chunk * 64 + lane;
+  return __builtin_amdgcn_readfirstlane(chunk * 64 + __popcll(__ballot(i < n && key(i) <= x)) - 1);
+}
+
 }  // namespace qd
