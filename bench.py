@@ -362,7 +362,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the enumeration of one code "
-              f"shards by rank ranges, which this build does not run across GPUs.", file=sys.stderr)
+              f"shards by rank ranges, which this library does not run across GPUs.", file=sys.stderr)
         sys.exit(2)
     import torch
 
