@@ -238,10 +238,9 @@ int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int 
  * package sets per lane, 1..4096, 1 choosing from the round size; others
  * QD_ERR_INVALID; t > 8 is QD_ERR_TOO_LARGE): minimum symplectic weight,
  * one codeword reaching it and the number of combinations, as
- * qd_round_min.  weight_sum (may be NULL) receives the sum of the weights
- * of every codeword walked: when some package has two rows, a one-row
- * package is walked as three equal elements, so a combination with u
- * one-row packages counts 3^u times. */
+ * qd_round_min.  weight_sum (may be NULL) receives the sum of the
+ * symplectic weights of the codewords of every combination of the round
+ * (each walked once). */
 int qd_round_walk(const uint8_t *rows, const int *dims, int P, int n, int t, int per_lane,
                   int *wmin, uint8_t *witness, unsigned long long *count,
                   unsigned long long *weight_sum);

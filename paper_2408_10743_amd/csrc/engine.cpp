@@ -48,6 +48,9 @@ constexpr unsigned long long kTinyRound = 1ull << 19;
 constexpr unsigned long long kWalkWaves = 1ull << 15;
 constexpr unsigned long long kWalkMaxPerLane = 64;
 constexpr int kWalkMaxOption = 4096;
+// Staged offsets per round descriptor: groups, runs, binomials, walk package
+// map and walk parts.
+constexpr size_t kStagedPerDesc = 5;
 constexpr size_t kBigClass = size_t(64) << 20;
 constexpr size_t kSlabMax = size_t(16) << 20;   // largest class carved from slabs
 constexpr size_t kSlabBytes = size_t(64) << 20;
@@ -564,9 +567,12 @@ int Executor::flush(hipStream_t s, const unsigned char **base, size_t *desc_off)
   if (!alloc(stage_dev_, need)) return QD_ERR_NOMEM;
   const unsigned char *dev = static_cast<const unsigned char *>(stage_dev_.p);
   for (size_t i = 0; i < descs_.size(); ++i) {
-    descs_[i].groups = reinterpret_cast<const DevGroup *>(dev + desc_groups_[3 * i]);
-    descs_[i].runs = reinterpret_cast<const DevRun *>(dev + desc_groups_[3 * i + 1]);
-    descs_[i].binom = reinterpret_cast<const unsigned long long *>(dev + desc_groups_[3 * i + 2]);
+    const size_t *o = &desc_groups_[kStagedPerDesc * i];
+    descs_[i].groups = reinterpret_cast<const DevGroup *>(dev + o[0]);
+    descs_[i].runs = reinterpret_cast<const DevRun *>(dev + o[1]);
+    descs_[i].binom = reinterpret_cast<const unsigned long long *>(dev + o[2]);
+    descs_[i].pmap = reinterpret_cast<const unsigned short *>(dev + o[3]);
+    descs_[i].parts = reinterpret_cast<const WalkPart *>(dev + o[4]);
   }
   const size_t doff = staging_.put(descs_.data(), descs_.size() * sizeof(RoundDesc));
   const size_t boff = staging_.put(bl.data(), bl.size() * sizeof(SavedParams));
@@ -663,18 +669,35 @@ int Executor::schedule(Job &job, int sharing) {
       f.walk = true;
       f.use_tops = false;
       f.L_before = job.single_round ? -1 : lower_bound(tsim, job.delta, job.halve);
-      f.radix = 1;
-      for (int sz : g.sizes) f.radix = sz == 3 ? 3 : f.radix;
       const size_t ld = size_t(t) + 1;
       f.binom.assign(size_t(g.P + 1) * ld, 0);
       for (int p = 0; p <= g.P; ++p)
         for (int r = 0; r <= t; ++r)
           f.binom[p * ld + r] = r == 0 ? 1 : p == 0 ? 0 : f.binom[(p - 1) * ld + r] + f.binom[(p - 1) * ld + r - 1];
-      f.subsets = f.binom[size_t(g.P) * ld + t];
+      // Package map: the two-row packages, then the one-row ones.
+      for (int i = 0; i < g.P; ++i)
+        if (g.sizes[i] == 3) f.pmap.push_back(static_cast<unsigned short>(i));
+      f.p2 = int(f.pmap.size());
+      for (int i = 0; i < g.P; ++i)
+        if (g.sizes[i] != 3) f.pmap.push_back(static_cast<unsigned short>(i));
+      const int p1 = g.P - f.p2;
+      auto C = [&](int n, int r) { return r < 0 || r > n ? 0ull : f.binom[size_t(n) * ld + r]; };
+      const unsigned long long sets = f.binom[size_t(g.P) * ld + t];
       f.per_lane = job.opt.walk >= 2
                        ? static_cast<unsigned long long>(job.opt.walk)
-                       : std::min(kWalkMaxPerLane, std::max<unsigned long long>(1, f.subsets / (kWave * kWalkWaves)));
-      f.tiles = (f.subsets + kWave * f.per_lane - 1) / (kWave * f.per_lane);
+                       : std::min(kWalkMaxPerLane, std::max<unsigned long long>(1, sets / (kWave * kWalkWaves)));
+      // Part u: sets of u one-row and t - u two-row packages.
+      f.tiles = 0;
+      for (int u = std::max(0, t - f.p2); u <= std::min(t, p1); ++u) {
+        WalkPart w{};
+        w.tile0 = f.tiles;
+        w.c2 = C(f.p2, t - u);
+        w.subsets = C(p1, u) * w.c2;
+        w.u = u;
+        if (!w.subsets) continue;
+        f.parts.push_back(w);
+        f.tiles += (w.subsets + kWave * f.per_lane - 1) / (kWave * f.per_lane);
+      }
       f.planned = planned;
       job.fl.push_back(std::move(f));
       ++job.j;
@@ -801,10 +824,11 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         const size_t go = staging_.put(f.hg.data(), f.hg.size() * sizeof(DevGroup));
         const size_t ro = staging_.put(f.hr.data(), f.hr.size() * sizeof(DevRun));
         const size_t bo = staging_.put(f.binom.data(), f.binom.size() * sizeof(unsigned long long));
-        if (go == SIZE_MAX || ro == SIZE_MAX || bo == SIZE_MAX) return QD_ERR_NOMEM;
-        desc_groups_.push_back(go);
-        desc_groups_.push_back(ro);
-        desc_groups_.push_back(bo);
+        const size_t mo = staging_.put(f.pmap.data(), f.pmap.size() * sizeof(unsigned short));
+        const size_t po = staging_.put(f.parts.data(), f.parts.size() * sizeof(WalkPart));
+        if (go == SIZE_MAX || ro == SIZE_MAX || bo == SIZE_MAX || mo == SIZE_MAX || po == SIZE_MAX)
+          return QD_ERR_NOMEM;
+        for (size_t off : {go, ro, bo, mo, po}) desc_groups_.push_back(off);
         d.suffix = g.dsuffix;
         d.csize = g.csize;
         d.state = states_ + job.state_slot;
@@ -843,9 +867,9 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         first = false;
         unsigned lds = round_lds_bytes(d.P, d.t, d.u, d.ngroups, d.stage);
         if (f.walk) {
-          d.subsets = f.subsets;
           d.per_lane = f.per_lane;
-          d.radix = f.radix;
+          d.nparts = int(f.parts.size());
+          d.p2 = f.p2;
           d.wsum = job.want_wsum ? d.counters + 2 : nullptr;  // word 2 of the first counter line
           L.sum = L.sum || job.want_wsum;
           d.stage = 1;

@@ -92,12 +92,15 @@ struct Flight {
   unsigned long long tiles = 0, sent = 0, planned = 0;
   int launches = 0;
   float ms = 0.f;
-  // Plain walk (qd_options.walk): one launch per round, one wave per 64
-  // lanes of per_lane package sets each.
+  // Plain walk (qd_options.walk): one launch per round, its sets split
+  // into parts by their one-row packages, one wave per 64 lanes of
+  // per_lane sets each.
   bool walk = false;
-  int radix = 1;
-  unsigned long long subsets = 0, per_lane = 1;
+  unsigned long long per_lane = 1;
+  int p2 = 0;                             // two-row packages of the matrix
   std::vector<unsigned long long> binom;  // C(p, r), p <= P, r <= t
+  std::vector<unsigned short> pmap;       // two-row packages, then one-row ones
+  std::vector<WalkPart> parts;
 };
 
 // One code: request, plan, device data and progress through its rounds.
@@ -200,7 +203,8 @@ class Executor {
   uint32_t *zero_table_ = nullptr;  // the saved table of depth 0: one zero entry
   std::vector<SavedParams> builds_[5];  // queued table builds per word count
   std::vector<RoundDesc> descs_;
-  std::vector<size_t> desc_groups_;  // staged offsets of each piece's groups, runs and binomials
+  std::vector<size_t> desc_groups_;  // staged offsets of each piece's groups, runs, binomials,
+                                     // package map and walk parts (kStagedPerDesc each)
   std::vector<hipEvent_t> events_;
 };
 

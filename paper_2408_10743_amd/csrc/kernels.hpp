@@ -61,6 +61,16 @@ struct DevState {
 // counts combinations, word 1 the words evaluated for them.
 constexpr int kCountersPerCode = 256;
 
+// Part u of a walk round: the package sets with u one-row packages, ranked
+// as (one-row subset, two-row subset), each in revolving-door order.
+struct WalkPart {
+  unsigned long long tile0;            // first wave of the part within the round
+  unsigned long long subsets;          // C(P1, u) C(P2, t - u)
+  unsigned long long c2;               // C(P2, t - u): two-row subsets
+  int u;
+  int pad;
+};
+
 // One piece of one (code, t, Gamma_j) round inside a launch.  A launch
 // covers several pieces (several codes); pieces start at multiples of
 // kWavesPerGroup tiles so a workgroup never spans two of them.
@@ -99,9 +109,10 @@ struct RoundDesc {
   // Plain walk kernel (walk.hip) only.
   const unsigned long long *binom;     // C(p, r) at p * (t + 1) + r, p <= P, r <= t
   unsigned long long *wsum;            // sum of the walked codewords' weights (NULL: not taken)
-  unsigned long long subsets;          // package sets of the round, C(P, t)
+  const unsigned short *pmap;          // the two-row packages (p2 of them), then the one-row ones
+  const WalkPart *parts;               // the round's parts, by first wave
   unsigned long long per_lane;         // package sets per lane
-  int radix;                           // 3 if some package has three elements, else 1
+  int nparts, p2;
 };
 
 struct LaunchParams {

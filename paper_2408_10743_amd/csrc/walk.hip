@@ -6,22 +6,25 @@
 // per-code path the engine is measured against, and a second enumeration
 // of a different order for the tests.
 //
-// Lane l of wave g takes the package sets of revolving-door rank
-// [(64 g + l) K, (64 g + l + 1) K), K sets per lane.  It unranks the first
-// (combinatorial number system, revdoor.hpp) and reaches each next set by
-// one package out and one in.  Within a set the lane walks the element
-// choices in reflected ternary Gray order: slot j of the lane holds one
-// package and digit j its element (0: r, 1: s, 2: r^s), and each step moves
-// one digit by one, which XORs one element into the codeword (0 <-> 1:
-// r^s; 1 <-> 2: r).  The walk continues from the digits where the previous
-// set left them (all 2 after an even set, all 0 after an odd one), so the
-// whole lane range is one reflected Gray walk.  Every lane of a wave is at
+// A round is split into parts by u, the number of one-row packages in a
+// set: part u holds the sets of u one-row and t - u two-row packages, each
+// with 3^(t-u) element choices, and its sets are ranked as (one-row subset,
+// two-row subset), each in revolving-door order (combinatorial number
+// system, revdoor.hpp).  Lane l of the part's wave g takes the sets of rank
+// [(64 g + l) K, (64 g + l + 1) K), K sets per lane: it unranks the first
+// and reaches the next by one two-row package out and one in (when the
+// two-row subset wraps around, the lane forms the set's codeword afresh).
+// Within a set the lane walks the element choices of its two-row packages
+// in reflected ternary Gray order: slot j of the lane holds one of them and
+// digit j its element (0: r, 1: s, 2: r^s), and each step moves one digit
+// by one, which XORs one element into the codeword (0 <-> 1: r^s; 1 <-> 2:
+// r).  The walk continues from the digits where the previous set left them
+// (all 2 after an even set, all 0 after an odd one), so the lane's sets are
+// one reflected Gray walk.  Every lane of a wave is in the same part and at
 // the same step, so the digit that moves is wave-uniform: its row sits at a
 // static VGPR index (digits 0 and 1, 8 of every 9 steps) or is read from
 // LDS (the others).  A step is one XOR per word, an OR and a v_bcnt per
-// word, and a min.  A package with one row is walked as three equal
-// elements (digit moves XOR zero): its codewords are visited three times
-// per digit sweep, counted once.
+// word, and a min, and every codeword is walked once.
 #include <hip/hip_runtime.h>
 
 #define QD_HD __host__ __device__
@@ -52,14 +55,14 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return v;
 }
 
-// A lane's t packages.  Digits 0 and 1 move on 8 of every 9 steps: their
-// rows sit in VGPRs, oriented for the current set (x: the row of the
-// digit's first move in the set's even blocks, y: the other; an even set
-// starts with its digits rising, x = r^s, y = r).  The other digits move
-// once per 9 steps and read their row from the staged elements: bits
-// 10 (j - 2) .. of `high` hold slot j's package (8 bits: a matrix has at
-// most 2 x 128 packages) and whether it has one row (bit 8), so the
-// wave-uniform j selects it by a shift.
+// A lane's two-row packages, one per digit.  Digits 0 and 1 move on 8 of
+// every 9 steps: their rows sit in VGPRs, oriented for the current set (x:
+// the row of the digit's first move in the set's even blocks, y: the other;
+// an even set starts with its digits rising, x = r^s, y = r).  The other
+// digits move once per 9 steps and read their row from the staged
+// elements: bits 8 (j - 2) .. 8 (j - 2) + 7 of `high` hold slot j's package
+// (a matrix has at most 2 x 128 packages), so the wave-uniform j selects it
+// by a shift.
 template <int D>
 struct Slots {
   uint32_t x0[2 * D], y0[2 * D], x1[2 * D], y1[2 * D];
@@ -67,11 +70,10 @@ struct Slots {
   int pkg[kWalkMaxT];
 };
 
-constexpr int kHighBits = 10;
+constexpr int kHighBits = 8;
 
-__device__ __forceinline__ unsigned long long high_field(const unsigned char *csize, int p, int k) {
-  const unsigned long long f = static_cast<unsigned long long>(p) | (csize[p] == 1 ? 0x100ull : 0ull);
-  return f << (kHighBits * (k - 2));
+__device__ __forceinline__ unsigned long long high_field(int p, int k) {
+  return static_cast<unsigned long long>(p) << (kHighBits * (k - 2));
 }
 
 __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
@@ -187,12 +189,10 @@ __device__ __forceinline__ uint32_t flip_elem(uint32_t (&c)[2 * D], const uint32
   return acc;
 }
 
-// Element e of package p (a one-row package has only r).
+// Element e of package p (0: r, 1: s, 2: r^s).
 template <int D>
-__device__ __forceinline__ void load_elem(const uint32_t *E, const unsigned char *csize, int p, int e,
-                                          uint32_t (&out)[2 * D]) {
-  const bool one = csize[p] == 1;
-  const uint32_t *q = E + (static_cast<size_t>(3) * p + (one ? 0 : e)) * kElemWords;
+__device__ __forceinline__ void load_elem(const uint32_t *E, int p, int e, uint32_t (&out)[2 * D]) {
+  const uint32_t *q = E + (static_cast<size_t>(3) * p + e) * kElemWords;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     out[d] = q[d];
@@ -200,21 +200,19 @@ __device__ __forceinline__ void load_elem(const uint32_t *E, const unsigned char
   }
 }
 
-// The rows of package p's digit moves, oriented for a set of parity `odd`.
+// The rows of two-row package p's digit moves, oriented for a set of
+// parity `odd`.
 template <int D>
-__device__ __forceinline__ void load_rows(const uint32_t *E, const unsigned char *csize, int p, bool odd,
-                                          uint32_t (&x)[2 * D], uint32_t (&y)[2 * D]) {
-  const bool one = csize[p] == 1;
+__device__ __forceinline__ void load_rows(const uint32_t *E, int p, bool odd, uint32_t (&x)[2 * D],
+                                          uint32_t (&y)[2 * D]) {
   const uint32_t *qa = E + (static_cast<size_t>(3) * p + 2) * kElemWords;  // r^s
   const uint32_t *qb = E + (static_cast<size_t>(3) * p) * kElemWords;      // r
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    const uint32_t ax = one ? 0u : qa[d], az = one ? 0u : qa[4 + d];
-    const uint32_t bx = one ? 0u : qb[d], bz = one ? 0u : qb[4 + d];
-    x[d] = odd ? bx : ax;
-    x[D + d] = odd ? bz : az;
-    y[d] = odd ? ax : bx;
-    y[D + d] = odd ? az : bz;
+    x[d] = odd ? qb[d] : qa[d];
+    x[D + d] = odd ? qb[4 + d] : qa[4 + d];
+    y[d] = odd ? qa[d] : qb[d];
+    y[D + d] = odd ? qa[4 + d] : qb[4 + d];
   }
 }
 
@@ -241,46 +239,70 @@ __device__ __forceinline__ void step_high(uint32_t (&c)[2 * D], const Slots<D> &
   }
   const bool rise = (((q / 3) + o) & 1u) == 0;
   const bool use_a = (q % 3 == 1) == rise;  // 0 <-> 1 move: r^s; 1 <-> 2: r
-  const uint32_t f = static_cast<uint32_t>(s.high >> (kHighBits * (j - 2))) & 0x3FFu;
-  const uint32_t base = 3u * (f & 0xFFu);
-  // a one-row package moves by its zero element s
-  const uint32_t el = (f & 0x100u) ? base + 1 : (use_a ? base + 2 : base);
-  v.one(flip_elem<D>(c, E, el), c);
+  const uint32_t base = 3u * (static_cast<uint32_t>(s.high >> (kHighBits * (j - 2))) & 0xFFu);
+  v.one(flip_elem<D>(c, E, use_a ? base + 2 : base), c);
 }
 
-// One lane's walk over the package sets [s0, s1) (s0 <= s1; rw >= s1 - s0
-// is the wave's longest range, steps per set nstep = 3^t or 1).  Returns
-// through v; `sets` counts the combinations of the lane's sets and
-// `walked` the codewords it evaluated for them.
-template <int D, int MODE>
-__device__ void walk_range(const RoundDesc &p, const uint32_t *E, const unsigned long long *BN,
-                           unsigned long long s0, unsigned long long s1, uint32_t rw, uint32_t nstep,
-                           Visit<D, MODE> &v, unsigned long long &sets, unsigned long long &walked) {
-  const int t = p.t, ld = p.t + 1;
-  Slots<D> s;
-  uint32_t c[2 * D];
+// The package set of rank `rank` in part w (u one-row and td = t - u
+// two-row packages): the two-row subset in two[0..td-1], the one-row subset
+// in one[0..u-1], as package numbers of the matrix (pm lists the two-row
+// packages, then the one-row ones).
+__device__ __forceinline__ void unrank_set(unsigned long long rank, const WalkPart &w, int td, int p2, int p1,
+                                           const unsigned long long *BN, int ld, const unsigned short *pm,
+                                           int (&two)[kWalkMaxT], int (&one)[kWalkMaxT]) {
+  int a[kWalkMaxT], b[kWalkMaxT];
+  revdoor_unrank(rank % w.c2, td, p2, BN, ld, a);
+  revdoor_unrank(rank / w.c2, w.u, p1, BN, ld, b);
+#pragma unroll
+  for (int k = 0; k < kWalkMaxT; ++k) {
+    two[k] = k < td ? pm[a[k]] : -1;
+    one[k] = k < w.u ? pm[p2 + b[k]] : -1;
+  }
+}
+
+// A set's codeword with every digit at value v, and its rows, from scratch.
+template <int D>
+__device__ __forceinline__ void form_set(const uint32_t *E, const int (&two)[kWalkMaxT],
+                                         const int (&one)[kWalkMaxT], int td, int u, int v, bool odd,
+                                         Slots<D> &s, uint32_t (&c)[2 * D]) {
 #pragma unroll
   for (int i = 0; i < 2 * D; ++i) c[i] = 0;
-  int first[kWalkMaxT];
-  revdoor_unrank(s0 < s1 ? s0 : 0ull, t, p.P, BN, ld, first);
-  int three = 0;  // packages with three elements in the current set
-#pragma unroll
-  for (int i = 0; i < 2 * D; ++i) s.x0[i] = s.y0[i] = s.x1[i] = s.y1[i] = 0;
   s.high = 0;
 #pragma unroll
   for (int k = 0; k < kWalkMaxT; ++k) {
-    s.pkg[k] = k < t ? first[k] : -1;
-    if (k < t) {
-      if (k >= 2) s.high |= high_field(p.csize, s.pkg[k], k);
-      if (k == 0) load_rows<D>(E, p.csize, s.pkg[k], false, s.x0, s.y0);
-      if (k == 1) load_rows<D>(E, p.csize, s.pkg[k], false, s.x1, s.y1);
-      uint32_t e[2 * D];
-      load_elem<D>(E, p.csize, s.pkg[k], 0, e);
+    s.pkg[k] = two[k];
+    uint32_t e[2 * D];
+    if (k < td) {
+      if (k >= 2) s.high |= high_field(two[k], k);
+      if (k == 0) load_rows<D>(E, two[k], odd, s.x0, s.y0);
+      if (k == 1) load_rows<D>(E, two[k], odd, s.x1, s.y1);
+      load_elem<D>(E, two[k], v, e);
 #pragma unroll
       for (int i = 0; i < 2 * D; ++i) c[i] ^= e[i];
-      three += p.csize[s.pkg[k]] == 3;
+    }
+    if (k < u) {
+      load_elem<D>(E, one[k], 0, e);
+#pragma unroll
+      for (int i = 0; i < 2 * D; ++i) c[i] ^= e[i];
     }
   }
+}
+
+// One lane's walk over the sets [s0, s1) of part w (s0 <= s1; rw >= s1 - s0
+// is the wave's longest range; nstep = 3^td steps per set).  Returns through
+// v; `walked` counts the codewords of the lane's sets.
+template <int D, int MODE>
+__device__ void walk_range(const RoundDesc &p, const WalkPart &w, const uint32_t *E, const unsigned long long *BN,
+                           unsigned long long s0, unsigned long long s1, uint32_t rw, int td, uint32_t nstep,
+                           Visit<D, MODE> &v, unsigned long long &walked) {
+  const int ld = p.t + 1, u = w.u, p2 = p.p2, p1 = p.P - p.p2;
+  Slots<D> s;
+  uint32_t c[2 * D];
+  int two[kWalkMaxT], one[kWalkMaxT];
+  unrank_set(s0 < s1 ? s0 : 0ull, w, td, p2, p1, BN, ld, p.pmap, two, one);
+#pragma unroll
+  for (int i = 0; i < 2 * D; ++i) s.x0[i] = s.y0[i] = s.x1[i] = s.y1[i] = 0;
+  form_set<D>(E, two, one, td, u, 0, false, s, c);
   for (uint32_t o = 0; o < rw; ++o) {
     v.live = s0 + o < s1;
     if (o > 0) {
@@ -290,49 +312,57 @@ __device__ void walk_range(const RoundDesc &p, const uint32_t *E, const unsigned
       swap_rows<D>(s.x0, s.y0);  // the set's digits run the other way
       swap_rows<D>(s.x1, s.y1);
       if (v.live) {
-        // Next set in revolving-door order: one package out, one in.  The
-        // digits stand where the previous set's walk left them.
-        int nx[kWalkMaxT];
-        revdoor_unrank(s0 + o, t, p.P, BN, ld, nx);
-        int out = -1, in = -1;
+        // Next set: the digits stand where the previous set's walk left
+        // them.  Within one one-row subset, consecutive two-row subsets
+        // differ by one package out and one in.
+        const int vend = ((o - 1) & 1u) == 0 && td > 0 ? 2 : 0;
+        const bool odd = (o & 1u) != 0;
+        int nt[kWalkMaxT], no[kWalkMaxT];
+        unrank_set(s0 + o, w, td, p2, p1, BN, ld, p.pmap, nt, no);
+        int out = -1, in = -1, changed = 0;
+        bool same_one = true;
 #pragma unroll
         for (int k = 0; k < kWalkMaxT; ++k) {
           bool in_new = false, in_old = false;
 #pragma unroll
           for (int k2 = 0; k2 < kWalkMaxT; ++k2) {
-            in_new = in_new || (k < t && k2 < t && s.pkg[k] == nx[k2]);
-            in_old = in_old || (k < t && k2 < t && nx[k] == s.pkg[k2]);
+            in_new = in_new || (k < td && k2 < td && s.pkg[k] == nt[k2]);
+            in_old = in_old || (k < td && k2 < td && nt[k] == s.pkg[k2]);
           }
-          if (k < t && !in_new) out = s.pkg[k];
-          if (k < t && !in_old) in = nx[k];
+          if (k < td && !in_new) {
+            out = s.pkg[k];
+            ++changed;
+          }
+          if (k < td && !in_old) in = nt[k];
+          same_one = same_one && (k >= u || one[k] == no[k]);
         }
-        // Consecutive ranks always differ by one package each way; should
-        // they not, the codeword is left alone rather than read out of range.
-        if (out < 0 || in < 0) out = in = s.pkg[0];
-        const int vend = p.radix == 3 && ((o - 1) & 1u) == 0 ? 2 : 0;
-        uint32_t eo[2 * D], ei[2 * D];
-        load_elem<D>(E, p.csize, out, vend, eo);
-        load_elem<D>(E, p.csize, in, vend, ei);
+        if (changed == 1 && same_one && out >= 0 && in >= 0) {
+          uint32_t eo[2 * D], ei[2 * D];
+          load_elem<D>(E, out, vend, eo);
+          load_elem<D>(E, in, vend, ei);
 #pragma unroll
-        for (int i = 0; i < 2 * D; ++i) c[i] ^= eo[i] ^ ei[i];
-        three += (p.csize[in] == 3) - (p.csize[out] == 3);
+          for (int i = 0; i < 2 * D; ++i) c[i] ^= eo[i] ^ ei[i];
 #pragma unroll
-        for (int k = 0; k < kWalkMaxT; ++k)
-          if (k < t && s.pkg[k] == out) {
-            s.pkg[k] = in;
-            if (k >= 2)
-              s.high = (s.high & ~(0x3FFull << (kHighBits * (k - 2)))) | high_field(p.csize, in, k);
-            if (k == 0) load_rows<D>(E, p.csize, in, (o & 1u) != 0, s.x0, s.y0);
-            if (k == 1) load_rows<D>(E, p.csize, in, (o & 1u) != 0, s.x1, s.y1);
-          }
+          for (int k = 0; k < kWalkMaxT; ++k)
+            if (k < td && s.pkg[k] == out) {
+              s.pkg[k] = in;
+              if (k >= 2) s.high = (s.high & ~(0xFFull << (kHighBits * (k - 2)))) | high_field(in, k);
+              if (k == 0) load_rows<D>(E, in, odd, s.x0, s.y0);
+              if (k == 1) load_rows<D>(E, in, odd, s.x1, s.y1);
+            }
+        } else {
+          form_set<D>(E, nt, no, td, u, vend, odd, s, c);
+#pragma unroll
+          for (int k = 0; k < kWalkMaxT; ++k) one[k] = no[k];
+        }
       }
     }
     v.one(weight_of<D>(c), c);
-    if (nstep == 3) {  // t = 1: digit 0 only
+    if (nstep == 3) {  // td = 1: digit 0 only
       v.one(flip<D>(c, s.x0), c);
       v.one(flip<D>(c, s.y0), c);
     } else if (nstep >= 9) {
-      // Blocks k = 0 .. nb - 1 (nb = 3^(t-2) is odd), step 9 (k + 1) after
+      // Blocks k = 0 .. nb - 1 (nb = 3^(td-2) is odd), step 9 (k + 1) after
       // every block but the last.
       const uint32_t nb = nstep / 9;
       uint32_t k = 0;
@@ -344,12 +374,7 @@ __device__ void walk_range(const RoundDesc &p, const uint32_t *E, const unsigned
       }
       block8<D, MODE, false>(c, s, v);
     }
-    if (v.live) {
-      unsigned long long comb = 1;
-      for (int i = 0; i < three; ++i) comb *= 3;
-      sets += comb;
-      walked += nstep;
-    }
+    if (v.live) walked += nstep;
     v.end_set();
   }
 }
@@ -384,20 +409,23 @@ __global__ __launch_bounds__(256) void qd_walk_kernel(LaunchParams lp) {
   unsigned long long key = uniform64w(*reinterpret_cast<volatile unsigned long long *>(&st->key));
   if (static_cast<int>(key >> 32) <= p.L_before) return;  // bound already met
 
+  // The wave's part (sets of u one-row packages) and the lane's sets in it.
+  const WalkPart *const parts = p.parts;
+  const WalkPart w = parts[wave_last_le(p.nparts, g, [parts](int i) { return parts[i].tile0; })];
+  const int td = p.t - w.u;  // digits: two-row packages per set
   const unsigned long long K = p.per_lane;
-  unsigned long long s0 = (g * kWave + lane) * K;
-  s0 = min(s0, p.subsets);
-  const unsigned long long s1 = min(s0 + K, p.subsets);
+  unsigned long long s0 = ((g - w.tile0) * kWave + lane) * K;
+  s0 = min(s0, w.subsets);
+  const unsigned long long s1 = min(s0 + K, w.subsets);
   const uint32_t rw = wave_max_u32(static_cast<uint32_t>(s1 - s0));
   uint32_t nstep = 1;
-  if (p.radix == 3)
-    for (int i = 0; i < p.t; ++i) nstep *= 3;
+  for (int i = 0; i < td; ++i) nstep *= 3;
 
-  unsigned long long sets = 0, walked = 0;
+  unsigned long long walked = 0;
   Visit<D, MODE> v;
-  walk_range<D, MODE>(p, E, BN, s0, s1, rw, nstep, v, sets, walked);
+  walk_range<D, MODE>(p, w, E, BN, s0, s1, rw, td, nstep, v, walked);
   const uint32_t wmin = wave_min_u32(v.best);
-  const unsigned long long wsets = wave_sum_u64(sets), wwalked = wave_sum_u64(walked);
+  const unsigned long long wsets = wave_sum_u64(walked), wwalked = wsets;
   unsigned long long wsum = 0;
   if constexpr (MODE == kWalkSum) wsum = wave_sum_u64(v.wsum);
   if (lane == 0) {
@@ -414,8 +442,8 @@ __global__ __launch_bounds__(256) void qd_walk_kernel(LaunchParams lp) {
   // (U, slot) with one 64-bit atomicMin.
   Visit<D, kWalkFind> f;
   f.target = wmin;
-  unsigned long long fs = 0, fw = 0;
-  walk_range<D, kWalkFind>(p, E, BN, s0, s1, rw, nstep, f, fs, fw);
+  unsigned long long fw = 0;
+  walk_range<D, kWalkFind>(p, w, E, BN, s0, s1, rw, td, nstep, f, fw);
   const unsigned long long mask = __ballot(f.found);
   if (mask == 0) return;  // the walk stopped early: U already meets the bound
   const int winner = __ffsll(static_cast<long long>(mask)) - 1;

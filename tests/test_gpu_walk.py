@@ -4,10 +4,9 @@ Gray order, one launch per round.
 
 Round minima and combination counts equal the oracle's plain enumeration
 of the same round.  The sum of the weights of every codeword walked equals
-a sum enumerated here with numpy (a combination with u one-row packages
-counts 3^u times when some package has two rows), which a skipped or
-repeated codeword would change.  Distances with the walk equal the
-oracle's."""
+the sum over the round's combinations enumerated here with numpy, which a
+skipped or repeated codeword would change.  Distances with the walk equal
+the oracle's."""
 import itertools
 import json
 import os
@@ -34,13 +33,13 @@ def swt(v):
     return int(np.count_nonzero(v[:n] | v[n:]))
 
 
-def walked_weight_sum(rows, dims, t):
+def round_weight_sum(rows, dims, t):
+    """Sum of the symplectic weights of every combination of the round."""
     n = rows.shape[1] // 2
-    three = any(d == 2 for d in dims)
     els = []
     for i, d in enumerate(dims):
         r, s = rows[2 * i], rows[2 * i + 1]
-        els.append(np.stack([r, s, r ^ s]) if d == 2 else np.stack([r] * (3 if three else 1)))
+        els.append(np.stack([r, s, r ^ s]) if d == 2 else r[None, :])
     total = 0
     for S in itertools.combinations(range(len(dims)), t):
         acc = np.zeros((1, 2 * n), dtype=np.uint8)
@@ -57,7 +56,7 @@ def check_round(Q, rows, dims, t, per_lane, with_sum):
     assert (w, cnt) == (wo, co)
     assert swt(wit) == w and O.in_rowspace(rows, wit)
     if with_sum:
-        assert ws == walked_weight_sum(rows, dims, t)
+        assert ws == round_weight_sum(rows, dims, t)
 
 
 @pytest.mark.parametrize("n", [5, 31, 33, 64, 72, 100, 128])
