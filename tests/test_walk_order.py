@@ -3,7 +3,8 @@ compiled with the host compiler and checked against the recursive
 definition of the order written out here: the t-subsets of {0..p-1}
 without p-1 in their own order, then those with p-1, the rest running
 backwards through the (t-1)-subsets of {0..p-2}.  Also: consecutive
-subsets differ by one element out and one in, and rank inverts unrank."""
+subsets, and the last and the first, differ by one element out and one
+in, and rank inverts unrank."""
 import os
 import subprocess
 import tempfile
@@ -77,8 +78,10 @@ def test_unrank_follows_the_definition(driver, P):
 
 
 def test_one_out_one_in(driver):
-    for P, t in [(12, 3), (12, 6), (16, 8), (20, 2)]:
+    """Consecutive subsets differ by one element each way, and so do the
+    last and the first (the order is cyclic)."""
+    for P, t in [(12, 3), (12, 6), (16, 8), (20, 2), (9, 1), (7, 6)]:
         subsets, _ = run(driver, P, t)
         assert len(set(subsets)) == len(subsets)
-        for a, b in zip(subsets, subsets[1:]):
+        for a, b in zip(subsets, subsets[1:] + subsets[:1]):
             assert len(set(a) - set(b)) == 1 and len(set(b) - set(a)) == 1, (a, b)
