@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--walk-only", action="store_true",
                     help="only run the plain per-round walk on the same code (--steps timed calls after "
                          "one warm-up call), for a profiler")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only run the config-4 batch leg (two batched calls and the per-code loop), for a profiler")
     ap.add_argument("--latency-only", action="store_true",
                     help="only run the time-to-exact-d leg on configs 1 and 2, for a profiler")
     ap.add_argument("--round-sweep", action="store_true",
@@ -400,6 +402,9 @@ def main():
         return
     stream = torch.cuda.current_stream()
     G, field = W.config3(a.seed)
+    if a.batch_only:
+        print(json.dumps({"batched": leg_batched(Q, W, a)}))
+        return
     if a.latency_only:
         print(json.dumps({"latency": leg_latency(Q, W)}))
         return

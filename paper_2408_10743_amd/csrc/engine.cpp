@@ -51,6 +51,9 @@ constexpr int kWalkMaxOption = 4096;
 // Staged offsets per round descriptor: groups, runs, binomials, walk package
 // map and walk parts.
 constexpr size_t kStagedPerDesc = 5;
+// Saved tables of at least this many entries are built from the next
+// smaller one.
+constexpr unsigned long long kExtendMinEntries = 1ull << 17;
 constexpr size_t kBigClass = size_t(64) << 20;
 constexpr size_t kSlabMax = size_t(16) << 20;   // largest class carved from slabs
 constexpr size_t kSlabBytes = size_t(64) << 20;
@@ -516,9 +519,19 @@ int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops) {
   PoolBuf &buf = tops ? g.tops[u] : g.table[u];
   if (buf.p) return QD_OK;
   const unsigned long long nent = tops ? g.suffix[u] : g.prefix[size_t(g.P) * g.R + u];
+  // A large saved table is built from the one of depth u - 1 (queued first
+  // if it is not there yet): one element XOR one smaller entry instead of
+  // unranking u packages.
+  const uint32_t *src = nullptr;
+  int level = 0;
+  if (!tops && u >= 2 && nent >= kExtendMinEntries) {
+    if (const int rc = ensure_table(job, g, u - 1, false)) return rc;
+    src = static_cast<const uint32_t *>(g.table[u - 1].p);
+    level = g.table_level[u - 1] + 1;  // 0 when it was built by an earlier step
+  }
   const unsigned long long padded = (nent + kBuildGroup - 1) / kBuildGroup * kBuildGroup;
   if (!alloc(buf, size_t(padded) * (tops ? kElemWords : 2 * job.D) * 4)) return QD_ERR_NOMEM;
-  SavedParams sp;
+  SavedParams sp{};
   sp.elems = g.elems;
   sp.prefix = g.dprefix;
   sp.suffix = g.dsuffix;
@@ -531,6 +544,12 @@ int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops) {
   sp.R = g.R;
   sp.u = u;
   sp.tops = tops ? 1 : 0;
+  sp.src = src;
+  sp.level = level;
+  if (!tops) {
+    g.table_level[u] = level;
+    level_marks_.push_back(&g.table_level[u]);
+  }
   builds_[job.D].push_back(sp);
   return QD_OK;
 }
@@ -548,19 +567,32 @@ int Executor::flush(hipStream_t s, const unsigned char **base, size_t *desc_off)
     recs_.push_back({states_ + slot, off, sizeof(DevState), 0, 0, 0});
   }
   dirty_slots_.clear();
+  // One build launch per (wave, word count D): a table built from a smaller
+  // one goes in a later wave than its source.
   std::vector<SavedParams> bl;
-  std::vector<std::pair<size_t, size_t>> ranges;
-  for (int D = 1; D <= 4; ++D) {
-    const size_t b0 = bl.size();
-    unsigned long long first = 0;
-    for (SavedParams &sp : builds_[D]) {
-      sp.first = first;
-      first += sp.nent_padded;
-      bl.push_back(sp);
+  struct BuildRange {
+    int D;
+    size_t b0, b1;
+  };
+  std::vector<BuildRange> ranges;
+  int waves = 0;
+  for (int D = 1; D <= 4; ++D)
+    for (const SavedParams &sp : builds_[D]) waves = std::max(waves, sp.level + 1);
+  for (int lv = 0; lv < waves; ++lv)
+    for (int D = 1; D <= 4; ++D) {
+      const size_t b0 = bl.size();
+      unsigned long long first = 0;
+      for (SavedParams sp : builds_[D]) {
+        if (sp.level != lv) continue;
+        sp.first = first;
+        first += sp.nent_padded;
+        bl.push_back(sp);
+      }
+      if (bl.size() > b0) ranges.push_back({D, b0, bl.size()});
     }
-    ranges.push_back({b0, bl.size()});
-    builds_[D].clear();
-  }
+  for (int D = 1; D <= 4; ++D) builds_[D].clear();
+  for (int *m : level_marks_) *m = -1;
+  level_marks_.clear();
   if (staging_.size() == 0 && descs_.empty() && bl.empty() && recs_.empty()) return QD_OK;
   const size_t need = staging_.size() + align16(descs_.size() * sizeof(RoundDesc)) +
                       align16(bl.size() * sizeof(SavedParams)) + align16(recs_.size() * sizeof(CopyRec));
@@ -587,20 +619,18 @@ int Executor::flush(hipStream_t s, const unsigned char **base, size_t *desc_off)
       launch_scatter(reinterpret_cast<const CopyRec *>(dev + roff), int(recs_.size()), dev, s) != hipSuccess)
     return QD_ERR_DEVICE;
   recs_.clear();
-  for (int D = 1; D <= 4; ++D) {
-    const auto r = ranges[D - 1];
-    if (r.first == r.second) continue;
+  for (const BuildRange &r : ranges) {
     BuildParams bp;
-    bp.req = reinterpret_cast<const SavedParams *>(dev + boff) + r.first;
-    bp.nreq = int(r.second - r.first);
+    bp.req = reinterpret_cast<const SavedParams *>(dev + boff) + r.b0;
+    bp.nreq = int(r.b1 - r.b0);
     bp.threads = 0;
     unsigned lds = 0;
-    for (size_t i = r.first; i < r.second; ++i) {
+    for (size_t i = r.b0; i < r.b1; ++i) {
       bp.threads += bl[i].nent_padded;
       lds = std::max(lds, build_lds_bytes(bl[i].P, bl[i].u));
     }
     bp.lds = lds <= kStageMaxBytes ? lds : 0u;
-    if (launch_build(D, bp, s) != hipSuccess) return QD_ERR_DEVICE;
+    if (launch_build(r.D, bp, s) != hipSuccess) return QD_ERR_DEVICE;
   }
   *base = dev;
   *desc_off = doff;

@@ -63,6 +63,9 @@ struct GammaDev {
   const uint32_t *logicals = nullptr;    // Modified BZ operators in the stored order
   const unsigned long long *dprefix = nullptr, *dsuffix = nullptr;
   PoolBuf table[kTMax + 1], tops[kTMax + 1];
+  // Launch wave of a saved-table build queued for the next flush (-1: none).
+  int table_level[kTMax + 1];
+  GammaDev() { for (int &l : table_level) l = -1; }
 };
 
 // Pinned host bytes gathered between device steps and sent in one copy.
@@ -202,6 +205,7 @@ class Executor {
   PoolBuf slots_;
   uint32_t *zero_table_ = nullptr;  // the saved table of depth 0: one zero entry
   std::vector<SavedParams> builds_[5];  // queued table builds per word count
+  std::vector<int *> level_marks_;      // table_level entries to clear after the flush
   std::vector<RoundDesc> descs_;
   std::vector<size_t> desc_groups_;  // staged offsets of each piece's groups, runs, binomials,
                                      // package map and walk parts (kStagedPerDesc each)

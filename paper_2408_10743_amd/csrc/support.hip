@@ -45,7 +45,28 @@ __global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
   uint32_t x[D], z[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) x[d] = z[d] = 0;
-  if (k < p.nent) {
+  if (k < p.nent && p.src) {
+    // The largest package and its element, then entry `rest` of the table of
+    // depth u - 1 (built by an earlier launch).
+    const int r = p.u;
+    int a = r - 1, b = p.P - 1;
+    while (a < b) {
+      const int mid = (a + b + 1) >> 1;
+      if (E(mid, r) <= k) a = mid;
+      else b = mid - 1;
+    }
+    unsigned long long rest = k - E(a, r);
+    const unsigned long long f = E(a, r - 1);
+    int c = 0;
+    while (rest >= f && c < 2) { rest -= f; ++c; }
+    xor_elem<D>(p.elems, a, c, x, z);
+    const uint32_t *q = p.src + (rest / kBlock) * (2 * D * kBlock) + (rest % kBlock);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      x[d] ^= q[d * kBlock];
+      z[d] ^= q[(D + d) * kBlock];
+    }
+  } else if (k < p.nent) {
     unsigned long long rest = k;
     int hi2 = p.P;
     for (int r = p.u; r > 0; --r) {

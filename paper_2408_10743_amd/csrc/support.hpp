@@ -22,6 +22,11 @@ struct SavedParams {
   unsigned long long first;            // first thread of this table in the launch
   int P, R, u;
   int tops;                            // 1: build the tops table
+  // Saved table of depth u - 1, complete before this build (NULL: unrank
+  // every package).  Entry k of depth u is one element of its largest
+  // package XOR an entry of depth u - 1, in the same order.
+  const uint32_t *src;
+  int level;                           // host: launch wave (a build after its source's)
 };
 
 // Threads per workgroup of the table builder; a workgroup never spans two
