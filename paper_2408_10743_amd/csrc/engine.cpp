@@ -51,8 +51,8 @@ constexpr int kWalkMaxOption = 4096;
 // Staged offsets per round descriptor: groups, runs, binomials, walk package
 // map and walk parts.
 constexpr size_t kStagedPerDesc = 5;
-// Saved tables of at least this many entries are built from the next
-// smaller one.
+// Tables of at least this many entries are built from the next smaller
+// one of their kind.
 constexpr unsigned long long kExtendMinEntries = 1ull << 17;
 constexpr size_t kBigClass = size_t(64) << 20;
 constexpr size_t kSlabMax = size_t(16) << 20;   // largest class carved from slabs
@@ -519,15 +519,16 @@ int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops) {
   PoolBuf &buf = tops ? g.tops[u] : g.table[u];
   if (buf.p) return QD_OK;
   const unsigned long long nent = tops ? g.suffix[u] : g.prefix[size_t(g.P) * g.R + u];
-  // A large saved table is built from the one of depth u - 1 (queued first
-  // if it is not there yet): one element XOR one smaller entry instead of
-  // unranking u packages.
+  // A large table is built from the one of its kind of depth u - 1 (queued
+  // first if it is not there yet): one element XOR one smaller entry
+  // instead of unranking u packages.
+  int *levels = tops ? g.tops_level : g.table_level;
   const uint32_t *src = nullptr;
   int level = 0;
-  if (!tops && u >= 2 && nent >= kExtendMinEntries) {
-    if (const int rc = ensure_table(job, g, u - 1, false)) return rc;
-    src = static_cast<const uint32_t *>(g.table[u - 1].p);
-    level = g.table_level[u - 1] + 1;  // 0 when it was built by an earlier step
+  if (u >= 2 && nent >= kExtendMinEntries) {
+    if (const int rc = ensure_table(job, g, u - 1, tops)) return rc;
+    src = static_cast<const uint32_t *>((tops ? g.tops : g.table)[u - 1].p);
+    level = levels[u - 1] + 1;  // 0 when it was built by an earlier step
   }
   const unsigned long long padded = (nent + kBuildGroup - 1) / kBuildGroup * kBuildGroup;
   if (!alloc(buf, size_t(padded) * (tops ? kElemWords : 2 * job.D) * 4)) return QD_ERR_NOMEM;
@@ -546,10 +547,8 @@ int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops) {
   sp.tops = tops ? 1 : 0;
   sp.src = src;
   sp.level = level;
-  if (!tops) {
-    g.table_level[u] = level;
-    level_marks_.push_back(&g.table_level[u]);
-  }
+  levels[u] = level;
+  level_marks_.push_back(&levels[u]);
   builds_[job.D].push_back(sp);
   return QD_OK;
 }

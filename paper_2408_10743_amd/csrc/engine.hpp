@@ -63,9 +63,12 @@ struct GammaDev {
   const uint32_t *logicals = nullptr;    // Modified BZ operators in the stored order
   const unsigned long long *dprefix = nullptr, *dsuffix = nullptr;
   PoolBuf table[kTMax + 1], tops[kTMax + 1];
-  // Launch wave of a saved-table build queued for the next flush (-1: none).
-  int table_level[kTMax + 1];
-  GammaDev() { for (int &l : table_level) l = -1; }
+  // Launch wave of a table build queued for the next flush (-1: none).
+  int table_level[kTMax + 1], tops_level[kTMax + 1];
+  GammaDev() {
+    for (int &l : table_level) l = -1;
+    for (int &l : tops_level) l = -1;
+  }
 };
 
 // Pinned host bytes gathered between device steps and sent in one copy.

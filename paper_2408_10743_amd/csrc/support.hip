@@ -46,8 +46,8 @@ __global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
 #pragma unroll
   for (int d = 0; d < D; ++d) x[d] = z[d] = 0;
   if (k < p.nent && p.src) {
-    // The largest package and its element, then entry `rest` of the table of
-    // depth u - 1 (built by an earlier launch).
+    // The first package in build order and its element, then entry `rest`
+    // of the table of depth u - 1 (built by an earlier launch).
     const int r = p.u;
     int a = r - 1, b = p.P - 1;
     while (a < b) {
@@ -59,12 +59,21 @@ __global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
     const unsigned long long f = E(a, r - 1);
     int c = 0;
     while (rest >= f && c < 2) { rest -= f; ++c; }
-    xor_elem<D>(p.elems, a, c, x, z);
-    const uint32_t *q = p.src + (rest / kBlock) * (2 * D * kBlock) + (rest % kBlock);
+    xor_elem<D>(p.elems, p.tops ? p.P - 1 - a : a, c, x, z);
+    if (p.tops) {
+      const uint32_t *q = p.src + rest * kElemWords;
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      x[d] ^= q[d * kBlock];
-      z[d] ^= q[(D + d) * kBlock];
+      for (int d = 0; d < D; ++d) {
+        x[d] ^= q[d];
+        z[d] ^= q[4 + d];
+      }
+    } else {
+      const uint32_t *q = p.src + (rest / kBlock) * (2 * D * kBlock) + (rest % kBlock);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        x[d] ^= q[d * kBlock];
+        z[d] ^= q[(D + d) * kBlock];
+      }
     }
   } else if (k < p.nent) {
     unsigned long long rest = k;

@@ -22,9 +22,10 @@ struct SavedParams {
   unsigned long long first;            // first thread of this table in the launch
   int P, R, u;
   int tops;                            // 1: build the tops table
-  // Saved table of depth u - 1, complete before this build (NULL: unrank
-  // every package).  Entry k of depth u is one element of its largest
-  // package XOR an entry of depth u - 1, in the same order.
+  // Table of the same kind of depth u - 1, complete before this build
+  // (NULL: unrank every package).  Entry k of depth u is one element of its
+  // first package in build order (the largest; for tops the smallest) XOR an
+  // entry of depth u - 1, in the same order.
   const uint32_t *src;
   int level;                           // host: launch wave (a build after its source's)
 };
