@@ -74,6 +74,19 @@ extern "C" {
 #define QD_MAX_GAMMA 8
 #define QD_MAX_LOG 96
 
+/* Resume point of a call that ended with QD_INCOMPLETE (its budget or
+ * cancel flag stopped it before a round, or the plain walk reached a round
+ * deeper than it supports): the rounds before (t, j) ran in full and found
+ * U and a codeword of that weight.  A call on the same input with options
+ * that give the same generator matrices (checked by `structure`) starts at
+ * round (t, j) with these bounds and reaches the same distance. */
+typedef struct qd_resume {
+  int t, j;                   /* first round not run: qd_stats.next_t, next_j */
+  int U;                      /* upper bound found: qd_stats.U (n + 1: none) */
+  const uint8_t *witness;     /* 2n bytes of weight U as returned (NULL when U = n + 1) */
+  unsigned long long structure; /* qd_stats.structure of that call */
+} qd_resume;
+
 /* Options of qd_distance_ex.  Zero-initialized means "library defaults". */
 typedef struct qd_options {
   int diag;                   /* QD_DIAG_AUTO, QD_DIAG_F2, QD_DIAG_F4 or QD_DIAG_ISO */
@@ -121,6 +134,10 @@ typedef struct qd_options {
                                  weights).  Rounds of more than 8 packages end the call with
                                  QD_INCOMPLETE; QD_FILTER_STABILIZER is QD_ERR_INVALID.  At
                                  most 4096 */
+  const qd_resume *resume;    /* continue an incomplete call (NULL: from the first round).
+                                 Read during the call only.  A code whose matrices do not
+                                 match resume->structure, or an invalid point or witness:
+                                 QD_ERR_INVALID */
 } qd_options;
 
 /* One (t, Gamma_j) round of the enumeration. */
@@ -163,6 +180,8 @@ typedef struct qd_stats {
   int scalar_classes;         /* 1: one codeword per F4 scalar class was enumerated */
   int two_row_cap[QD_MAX_GAMMA]; /* mixed packages: matrix j has at most this many two-row
                                  packages pivoted inside its set (-1: no cap) */
+  int next_t, next_j;         /* first round not run (with QD_INCOMPLETE: the resume point) */
+  unsigned long long structure; /* hash of the generator matrices enumerated (qd_resume) */
   int nlog;                   /* rounds run (entries in log, capped at QD_MAX_LOG) */
   qd_round_log log[QD_MAX_LOG];
 } qd_stats;

@@ -312,6 +312,16 @@ void Executor::prepare(Job &job) {
   job.t0 = now_ms();
   qd_options &o = job.opt;
   std::memset(&job.S, 0, sizeof(job.S));
+  if (o.resume) {  // the caller's memory is read here only
+    const qd_resume &r = *o.resume;
+    job.has_resume = true;
+    job.r_t = r.t;
+    job.r_j = r.j;
+    job.r_U = r.U;
+    job.r_structure = r.structure;
+    if (r.witness) job.r_wit.assign(r.witness, r.witness + 2 * size_t(std::max(job.n, 0)));
+    o.resume = nullptr;
+  }
   if (o.diag != QD_DIAG_AUTO && o.diag != QD_DIAG_F2 && o.diag != QD_DIAG_F4 && o.diag != QD_DIAG_ISO) {
     job.status = QD_ERR_INVALID;
     return;
@@ -428,6 +438,63 @@ void Executor::prepare_gammas(Job &job) {
     }
     esym_tables(g.sizes, g.R - 1, g.prefix, g.suffix);
   }
+  // FNV-1a over the matrices: construction, and every package's dimension,
+  // pivot and rows.
+  unsigned long long hsh = 14695981039346656037ull;
+  auto mix = [&hsh](unsigned long long v) {
+    for (int b = 0; b < 8; ++b) {
+      hsh ^= (v >> (8 * b)) & 0xFF;
+      hsh *= 1099511628211ull;
+    }
+  };
+  mix(static_cast<unsigned long long>(job.pc.diag));
+  mix(job.halve ? 1 : 0);
+  mix(job.scalar ? 1 : 0);
+  for (const Gamma &gm : job.use) {
+    mix(gm.pk.size());
+    mix(static_cast<unsigned long long>(gm.delta));
+    for (const Package &p : gm.pk) {
+      mix(static_cast<unsigned long long>(p.dim));
+      mix(static_cast<unsigned long long>(static_cast<long long>(p.pivot)));
+      for (int w = 0; w < 2; ++w) {
+        mix(p.r.x[w]);
+        mix(p.r.z[w]);
+        mix(p.s.x[w]);
+        mix(p.s.z[w]);
+      }
+    }
+  }
+  job.S.structure = hsh;
+  if (job.has_resume) apply_resume(job);
+}
+
+// Starts a job at the resume point of an earlier call on the same matrices:
+// rounds before (t, j) count as run, U and its witness as found.
+void Executor::apply_resume(Job &job) {
+  const int n = job.n, h = int(job.use.size());
+  bool ok = job.r_structure == job.S.structure && job.r_j >= 0 && job.r_j < h && job.r_t >= 1 &&
+            job.r_t <= kTMax + 1 && job.r_U >= 1 && job.r_U <= n + 1;
+  BRow w;
+  if (ok && job.r_U <= n) {
+    ok = job.r_wit.size() == 2 * size_t(n);
+    for (int q = 0; ok && q < n; ++q) {
+      if (job.r_wit[q] > 1 || job.r_wit[n + q] > 1) ok = false;
+      if (job.r_wit[q]) w.x[q >> 6] |= 1ull << (q & 63);
+      if (job.r_wit[n + q]) w.z[q >> 6] |= 1ull << (q & 63);
+    }
+    ok = ok && rweight(w) == job.r_U && in_span(job.basis, n, w);
+  }
+  if (!ok) {
+    job.status = QD_ERR_INVALID;
+    return;
+  }
+  job.t = job.r_t;
+  job.j = job.r_j;
+  for (int jj = 0; jj < h; ++jj) job.tdone[jj] = std::min(job.use[jj].P(), jj < job.r_j ? job.r_t : job.r_t - 1);
+  job.L = lower_bound(job.tdone, job.delta, job.halve);
+  job.U = job.r_U;
+  if (job.r_U <= n) job.wit = w;
+  if (job.L >= job.U) job.done = true;
 }
 
 size_t Executor::footprint(const Job &job) {
@@ -461,7 +528,7 @@ int Executor::admit(Job &job, hipStream_t s) {
   free_slots_.pop_back();
   DevState &hs = hstates_[job.state_slot];
   std::memset(&hs, 0, sizeof(hs));
-  hs.key = (static_cast<unsigned long long>(job.n + 1) << 32) | kNoSlot;
+  hs.key = (static_cast<unsigned long long>(job.U) << 32) | kNoSlot;  // n + 1, or a resumed U
   dirty_slots_.push_back(job.state_slot);
   // Block layout: counters | per Gamma_j elements, sizes, qubit order and
   // logical operators (both in its stored order), each 16-byte aligned as
@@ -1003,6 +1070,12 @@ void Executor::retire(Job &job) {
     qd_stats &S = job.S;
     S.L = job.L;
     S.U = job.U;
+    S.next_t = job.t;
+    S.next_j = job.j;
+    if (S.next_j >= int(job.use.size())) {
+      S.next_j = 0;
+      ++S.next_t;
+    }
     S.combinations = job.visited;
     // The witness must have weight U and lie in the row space.
     bool wit_ok = job.U <= job.n && rweight(job.wit) == job.U && in_span(job.basis, job.n, job.wit);

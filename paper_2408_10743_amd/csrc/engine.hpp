@@ -129,6 +129,11 @@ struct Job {
   bool partial = false; // partial weights (matrices stored in their qubit order)
   std::vector<int> caps; // mixed packages: two-row caps of the F4 matrices (empty: none)
   int force_words = 0;   // > 0: every tile evaluates this many words first (no credit)
+  // Resume point (copied from qd_options.resume by prepare)
+  bool has_resume = false;
+  int r_t = 0, r_j = 0, r_U = 0;
+  std::vector<uint8_t> r_wit;
+  unsigned long long r_structure = 0;
   bool want_wsum = false;        // plain walk: sum the weights of the walked codewords
   unsigned long long wsum = 0;   // (read back by retire)
   std::vector<BRow> logicals;  // Modified BZ: the admission test's operators
@@ -164,6 +169,8 @@ class Executor {
   static void prepare(Job &job);
   // The part of prepare() after the generator matrices are chosen.
   static void prepare_gammas(Job &job);
+  // Starts a prepared job at its resume point (qd_options.resume).
+  static void apply_resume(Job &job);
   // Device upload of a prepared job (needs a free state slot).
   int admit(Job &job, hipStream_t s);
   // One step over the given jobs; finished jobs get done = true.

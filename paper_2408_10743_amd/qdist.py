@@ -43,13 +43,19 @@ class QdError(RuntimeError):
         self.status = status
 
 
+class qd_resume(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int), ("j", ctypes.c_int), ("U", ctypes.c_int),
+                ("witness", ctypes.POINTER(ctypes.c_uint8)), ("structure", ctypes.c_ulonglong)]
+
+
 class qd_options(ctypes.Structure):
     _fields_ = [("diag", ctypes.c_int), ("max_gamma", ctypes.c_int),
                 ("budget", ctypes.c_ulonglong), ("cancel", ctypes.POINTER(ctypes.c_int)),
                 ("stream", ctypes.c_void_p), ("seg_len", ctypes.c_int),
                 ("saved_depth", ctypes.c_int), ("timing", ctypes.c_int), ("tops_mode", ctypes.c_int),
                 ("filter", ctypes.c_int), ("scalar_classes", ctypes.c_int),
-                ("partial_weight", ctypes.c_int), ("mixed_packages", ctypes.c_int), ("walk", ctypes.c_int)]
+                ("partial_weight", ctypes.c_int), ("mixed_packages", ctypes.c_int), ("walk", ctypes.c_int),
+                ("resume", ctypes.POINTER(qd_resume))]
 
 
 class qd_round_log(ctypes.Structure):
@@ -70,6 +76,7 @@ class qd_stats(ctypes.Structure):
                 ("wall_ms", ctypes.c_double),
                 ("launches", ctypes.c_int), ("logical_pairs", ctypes.c_int),
                 ("scalar_classes", ctypes.c_int), ("two_row_cap", ctypes.c_int * QD_MAX_GAMMA),
+                ("next_t", ctypes.c_int), ("next_j", ctypes.c_int), ("structure", ctypes.c_ulonglong),
                 ("nlog", ctypes.c_int),
                 ("log", qd_round_log * QD_MAX_LOG)]
 
@@ -150,13 +157,28 @@ def _matrix(G, field):
     return G, m, n
 
 
+def resume_point(stats, witness):
+    """The resume point (t, j, U, witness, structure) of a call that ended
+    with QD_INCOMPLETE, from its qd_stats and returned witness."""
+    return (stats.next_t, stats.next_j, stats.U, None if stats.U > stats.n else witness, stats.structure)
+
+
 def _options(opts):
     o = qd_options()
-    keep = None
+    keep = []  # objects the options point into, alive until the call returns
     for k, v in (opts or {}).items():
         if k == "cancel":
-            keep = v  # a ctypes.c_int the caller keeps alive
+            keep.append(v)  # a ctypes.c_int the caller keeps alive
             o.cancel = ctypes.pointer(v)
+        elif k == "resume":  # (t, j, U, witness array or None, structure)
+            t, j, U, wit, structure = v
+            r = qd_resume(t, j, U, None, structure)
+            if wit is not None:
+                wbuf = np.ascontiguousarray(wit, dtype=np.uint8)
+                r.witness = wbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+                keep.append(wbuf)
+            keep.append(r)
+            o.resume = ctypes.pointer(r)
         elif k == "stream":
             o.stream = ctypes.c_void_p(int(v))
         else:
@@ -177,7 +199,7 @@ def qd_distance_ex(G, field=QD_FIELD_F2, **opts):
     """Returns (status, d, witness, qd_stats).  Options: diag, max_gamma,
     budget, cancel (ctypes.c_int), stream (hipStream_t as int), seg_len,
     saved_depth, timing, tops_mode, filter, scalar_classes, partial_weight,
-    mixed_packages, walk."""
+    mixed_packages, walk, resume (a resume_point tuple)."""
     G, m, n = _matrix(G, field)
     o, _keep = _options(opts)
     d = ctypes.c_int(-1)

@@ -223,11 +223,24 @@ def test_mixed_packages_option_validation(Q):
         assert st == Q.QD_ERR_INVALID and d == -1, v
 
 
+def test_resume_rejects_foreign_points(Q):
+    """A resume point whose structure hash is not the code's, or whose round
+    or bound is out of range, is rejected on the host before any device
+    work."""
+    G, f = W.config1(0)
+    n = 20
+    wit = np.zeros(2 * n, dtype=np.uint8)
+    for point in [(2, 0, n + 1, None, 0), (2, 0, n + 1, None, 12345), (0, 0, n + 1, None, 0),
+                  (2, 0, 3, wit, 0)]:
+        st, d, _, _ = Q.qd_distance_ex(G, f, resume=point)
+        assert st == Q.QD_ERR_INVALID and d == -1, point
+
+
 def test_binding_struct_layouts_match_header(Q, tmp_path):
     """Every struct the binding mirrors has the header's size and field
     offsets (a C program compiled against include/qdist.h prints them)."""
     import subprocess
-    structs = [Q.qd_options, Q.qd_round_log, Q.qd_stats, Q.qd_result, Q.qd_plan_info]
+    structs = [Q.qd_resume, Q.qd_options, Q.qd_round_log, Q.qd_stats, Q.qd_result, Q.qd_plan_info]
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "qdist.h"', "int main(void) {"]
     for cls in structs:
         name = cls.__name__
