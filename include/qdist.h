@@ -93,8 +93,11 @@ typedef struct qd_options {
   int max_gamma;              /* 0: planner decides; else at most this many matrices */
   unsigned long long budget;  /* stop before a round that would exceed this many
                                  combinations in total (0: no limit) -> QD_INCOMPLETE */
-  const volatile int *cancel; /* host flag polled before each device step, which carries
-                                 one or more consecutive rounds (NULL: none) */
+  const volatile int *cancel; /* host flag polled before each device step (NULL: none).
+                                 With a flag a step carries at most 2^15 tiles of the
+                                 code, so a long round spans several steps; a set flag
+                                 stops the call before its first unfinished round
+                                 (QD_INCOMPLETE, resumable) */
   void *stream;               /* hipStream_t for all work (NULL: the library's own) */
   int seg_len;                /* tuning override: table entries per tile, multiple of 8 (0: auto) */
   int saved_depth;            /* tuning override: max packages in the saved-sum table (0: auto;

@@ -43,6 +43,9 @@ constexpr unsigned long long kSpecExtraRatio = 16;
 // Rounds up to this size skip the saved and tops tables: every lane unranks
 // its whole combination (no table-build launch for small codes).
 constexpr unsigned long long kTinyRound = 1ull << 19;
+// With a cancel flag, a code's step carries at most this many tiles (a long
+// round then spans several steps, and the flag is seen between them).
+constexpr unsigned long long kCancelTilesPerStep = 1ull << 15;
 // Plain walk: waves per round the automatic choice of package sets per
 // lane aims at, and the most sets a lane takes.
 constexpr unsigned long long kWalkWaves = 1ull << 15;
@@ -873,6 +876,22 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   if (const int rc = settle()) return rc;
   int sharing = 0;
   for (Job *jp : jobs) sharing += !jp->done && !jp->status;
+  // A code cancelled with rounds still in flight stops before the first of
+  // them; U and its witness are the best the device has found so far.
+  for (Job *jp : jobs) {
+    Job &job = *jp;
+    if (job.done || job.status || job.fl.empty() || !job.opt.cancel || !*job.opt.cancel) continue;
+    const DevState &hs = hstates_[job.state_slot];
+    if (int(hs.key >> 32) < job.U) {
+      job.U = int(hs.key >> 32);
+      job.wit = from_words(hs.wit);
+    }
+    job.t = job.fl[0].t;
+    job.j = job.fl[0].j;
+    drop_flights(job);
+    job.done = true;
+    job.incomplete = job.L < job.U;  // a U found mid-round may already meet L
+  }
   for (Job *jp : jobs) {
     if (jp->done || !jp->fl.empty() || jp->status) continue;
     const int rc = schedule(*jp, sharing);
@@ -906,10 +925,13 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
       Job &job = *jp;
       if (job.done || job.D != D || job.status || (job.opt.walk > 0) != walk) continue;
       bool first = true;  // the first piece of the code in this launch commits it
+      unsigned long long job_left = job.opt.cancel ? kCancelTilesPerStep : ~0ull;  // tiles this step
       for (size_t fi = 0; fi < job.fl.size(); ++fi) {
         Flight &f = job.fl[fi];
         const unsigned long long left = f.tiles - f.sent;
-        const unsigned long long take = std::min(left, kTilesPerLaunch - std::min(kTilesPerLaunch, L.tiles));
+        const unsigned long long take =
+            std::min({left, kTilesPerLaunch - std::min(kTilesPerLaunch, L.tiles), job_left});
+        job_left -= take;
         if (take == 0) continue;
         GammaDev &g = job.gd[f.j];
         RoundDesc d{};

@@ -1,9 +1,12 @@
 """Resuming incomplete calls (qd_options.resume): a call stopped by its
-budget, or by the plain walk's depth limit, continues from its next round
-with the bounds it had, and reaches the distance of an uninterrupted call
-with the same rounds in total."""
+budget, its cancel flag (also in the middle of a round) or the plain walk's
+depth limit continues from its first unfinished round with the bounds it
+had, and reaches the distance of an uninterrupted call (with the same
+rounds in total when it stopped between rounds)."""
+import ctypes
 import json
 import os
+import threading
 
 import numpy as np
 import pytest
@@ -84,3 +87,38 @@ def test_resume_rejects_other_matrices_and_witnesses(Q):
     # the right point still works
     st2, d2, w2, _ = Q.qd_distance_ex(G, f, resume=point)
     assert st2 == 0 and d2 == O.distance(G, f)[0]
+
+
+def test_cancel_before_the_first_round_then_resume(Q):
+    G, f = W.config1(3)
+    d_ref = O.brute(O.expand(G, f))[0]
+    flag = ctypes.c_int(1)
+    st, d, w, s = Q.qd_distance_ex(G, f, cancel=flag)
+    assert st == Q.QD_INCOMPLETE and (s.next_t, s.next_j) == (1, 0) and s.U == 21 and s.combinations == 0
+    st2, d2, w2, _ = Q.qd_distance_ex(G, f, resume=Q.resume_point(s, w))
+    assert st2 == 0 and d2 == d_ref and swt(w2) == d2
+
+
+def test_cancel_mid_round_then_resume(Q):
+    """With a cancel flag a long round spans several steps; a flag set while
+    config 3 runs stops it at a step boundary with valid bounds and a resume
+    point, and the resumed call reaches d."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_distances.json")))
+    G, f = W.config3(0)
+    d_ref = gold["config3"][0]
+    for delay in (0.0005, 0.002):
+        flag = ctypes.c_int(0)
+        timer = threading.Timer(delay, lambda: setattr(flag, "value", 1))
+        timer.start()
+        st, d, w, s = Q.qd_distance_ex(G, f, cancel=flag)
+        timer.join()
+        print(f"cancel after {delay * 1e3:.1f} ms: status {st} L={s.L} U={s.U} next=({s.next_t},{s.next_j}) "
+              f"{s.wall_ms:.2f} ms", flush=True)
+        if st == 0:  # finished before the flag was seen
+            assert d == d_ref
+            continue
+        assert st == Q.QD_INCOMPLETE and s.L <= d_ref <= s.U
+        if s.U <= s.n:
+            assert swt(w) == s.U and O.in_rowspace(O.expand(G, f), w)
+        st2, d2, w2, s2 = Q.qd_distance_ex(G, f, resume=Q.resume_point(s, w))
+        assert st2 == 0 and d2 == d_ref and swt(w2) == d2
