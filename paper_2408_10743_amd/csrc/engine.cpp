@@ -23,10 +23,10 @@ constexpr unsigned long long kMaxTableBytes = 1ull << 29;
 constexpr unsigned long long kMaxTopEntries = 1ull << 24;  // 512 MB of tops
 constexpr unsigned long long kTilesPerLaunch = 1ull << 21;
 constexpr unsigned long long kTargetTiles = 1ull << 18;    // ~32 tiles per wave slot
-constexpr unsigned kMinSeg = 256, kMaxSeg = 4096;
-// Rounds below kShortRound combinations start from kShortSeg entries per
-// tile: a step of small rounds is bound by each tile's chain of dependent
-// table loads, so shorter tiles finish sooner.
+constexpr unsigned kMinSeg = 1024, kMaxSeg = 4096;
+// Rounds below kShortRound combinations of a step with few codes start from
+// kShortSeg entries per tile: such a step is bound by each tile's chain of
+// dependent table loads, so shorter tiles finish sooner.
 constexpr unsigned long long kShortRound = 1ull << 24;
 constexpr unsigned kShortSeg = 64;
 // Partial weights for codes whose planned work reaches this many combinations.
@@ -110,12 +110,13 @@ int saved_depth(const GammaDev &g, int D, int t, int cap) {
 // Table entries per tile: long enough to amortize a tile's setup, short
 // enough that the round gives its share (1/sharing) of about kTargetTiles
 // tiles per step, where `sharing` codes run their rounds in the same steps.
-unsigned choose_seg(unsigned long long planned, int sharing) {
+unsigned choose_seg(unsigned long long planned, int sharing, unsigned long_seg) {
   const unsigned long long target = std::max<unsigned long long>(kTargetTiles / std::max(sharing, 1), 1024);
   const unsigned long long want = planned / (kWave * target);
-  // With many codes in a step the device is filled by their number, so
-  // tiles can stay long (the per-tile setup then costs under a few %).
-  unsigned seg = sharing > 8 ? 4 * kMinSeg : planned < kShortRound ? kShortSeg : kMinSeg;
+  // Large rounds start from long_seg entries, and every round of a step
+  // with many codes (their number fills the device) from kMinSeg: the
+  // per-tile setup then costs a few % at most.
+  unsigned seg = sharing > 8 ? kMinSeg : planned < kShortRound ? kShortSeg : long_seg;
   while (seg < want && seg < kMaxSeg) seg <<= 1;
   return seg;
 }
@@ -243,7 +244,7 @@ size_t Staging::put(const void *src, size_t bytes) {
 
 // -- Executor ------------------------------------------------------------------
 
-Executor::Executor(hipStream_t stream) : spec_combos_(kSpecCombos) {
+Executor::Executor(hipStream_t stream) : spec_combos_(kSpecCombos), long_seg_(kMinSeg) {
   int dev = 0, cnt = 0;
   hipDeviceProp_t prop;
   if (hipGetDeviceCount(&cnt) != hipSuccess || cnt <= 0 || hipGetDevice(&dev) != hipSuccess ||
@@ -811,7 +812,7 @@ int Executor::schedule(Job &job, int sharing) {
     f.L_before = job.single_round ? -1 : lower_bound(tsim, job.delta, job.halve);
     const int cap = job.opt.saved_depth < 0 ? 0 : job.opt.saved_depth ? job.opt.saved_depth : kDefaultSavedDepth;
     f.u = saved_depth(g, job.D, t, cap);
-    f.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : choose_seg(planned, sharing);
+    f.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : choose_seg(planned, sharing, long_seg_);
     const int tm = job.opt.tops_mode;
     f.use_tops = tm == 1 || (tm == 0 && g.suffix[t - f.u] <= kMaxTopEntries);
     if (planned <= kTinyRound && job.opt.saved_depth == 0 && tm == 0) {

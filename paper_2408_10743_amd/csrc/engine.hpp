@@ -163,6 +163,9 @@ class Executor {
   // Combinations of one code's consecutive rounds that one step may carry
   // (more: fewer steps; less: shorter steps, e.g. for serving).
   void set_spec_combos(unsigned long long c) { spec_combos_ = c; }
+  // Table entries per tile that large rounds start from (steps of fewer
+  // than 9 codes): shorter tiles end steps sooner, e.g. for serving.
+  void set_long_seg(unsigned seg) { long_seg_ = seg; }
 
   // Host-side preparation of a job (input check, basis, diagonalizations,
   // plan).  Thread-safe; touches no device state.
@@ -193,6 +196,7 @@ class Executor {
 
   bool ok_ = false;
   unsigned long long spec_combos_;
+  unsigned long_seg_;
   bool own_stream_ = false;
   hipStream_t stream_ = nullptr;
   DevPool pool_;
