@@ -22,7 +22,7 @@ struct SavedParams {
   unsigned long long first;            // first thread of this table in the launch
   int P, R, u;
   int tops;                            // 1: build the tops table
-  // Table of the same kind of depth u - 1, complete before this build
+  // Table of the same kind of depth u - 1, complete before this table is built
   // (NULL: unrank every package).  Entry k of depth u is one element of its
   // first package in build order (the largest; for tops the smallest) XOR an
   // entry of depth u - 1, in the same order.
