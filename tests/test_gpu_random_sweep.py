@@ -5,8 +5,9 @@ Codes: additive with n = 3..60 and 2..20 rows (fewer, as many or more rows
 than qubits, ragged word counts), F4-linear with k = 1..10.  Paths: the
 automatic plan, each construction (F2, F4, isometry), partial weights
 forced, mixed packages forced, and the plain walk; all codes also once as
-a single batch.  Every result is an integer and must match exactly, with
-a witness of weight d in the row space."""
+a single batch.  Larger codes, beyond brute force, against the oracle's
+BZ.  Every result is an integer and must match exactly, with a witness of
+weight d in the row space."""
 import numpy as np
 import pytest
 
@@ -84,3 +85,34 @@ def test_sweep_as_one_batch(Q):
         B = O.expand(G, f)
         assert s == 0 and d == O.brute(B)[0]
         assert swt(wit) == d and O.in_rowspace(B, wit)
+
+
+def test_sweep_larger_codes_against_oracle_bz(Q):
+    """Codes beyond brute force (additive, 22..30 rows and up to 120 qubits;
+    F4-linear with k = 11..15), against the oracle's BZ, which the CPU tests
+    pin to brute force: the automatic plan, F2, the isometry, the plain
+    walk, 64-entry tiles and every word evaluated."""
+    paths = [{}, {"diag": Q.QD_DIAG_F2}, {"diag": Q.QD_DIAG_ISO}, {"walk": 1}, {"seg_len": 64},
+             {"partial_weight": 0}]
+    checked = 0
+    for s in range(60):
+        rng = W.SplitMix64(W.config_seed(92, s))
+        if s % 4 == 3:
+            n = rng.uniform_int(30, 64)
+            G, f = W.f4_linear(n, rng.uniform_int(11, 15), rng.next()), 4
+        else:
+            n = rng.uniform_int(40, 120)
+            m = rng.uniform_int(22, 30)
+            G, f = W.additive(n, m, rng.next()), 2
+        B = O.expand(G, f)
+        d_ref = O.distance(G, f)[0]
+        for opts in paths:
+            st, d, wit, st_ = Q.qd_distance_ex(G, f, **opts)
+            if st == Q.QD_INCOMPLETE and opts.get("walk"):
+                assert st_.L <= d_ref <= st_.U, (s, opts)  # the walk's depth limit
+                continue
+            assert st == 0 and d == d_ref, (s, opts, st, d, d_ref)
+            assert swt(wit) == d and O.in_rowspace(B, wit), (s, opts)
+        checked += 1
+    print(f"larger codes: {checked} x {len(paths)} paths", flush=True)
+    assert checked == 60
