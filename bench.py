@@ -62,17 +62,17 @@ def algorithmic_ops(words, combos):
 
 def parse():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=30.0)
+    ap.add_argument("--gpus", type=int, default=1, help="GPUs (only 1 is supported)")
+    ap.add_argument("--steps", type=int, default=10, help="timed calls on the main code")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed calls before them")
+    ap.add_argument("--seed", type=int, default=0, help="seed of the main code (n = 72, m = 72)")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
+    ap.add_argument("--cpu-seconds", type=float, default=30.0, help="time limit of the CPU oracle sample")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched, plain, serving and latency legs")
-    ap.add_argument("--batch-codes", type=int, default=512)
-    ap.add_argument("--batch-max-work", type=float, default=1e11)
-    ap.add_argument("--serve-requests", type=int, default=300)
-    ap.add_argument("--stab-codes", type=int, default=64)
+    ap.add_argument("--batch-codes", type=int, default=512, help="codes in the batched leg")
+    ap.add_argument("--batch-max-work", type=float, default=1e11, help="largest predicted work of a batched code")
+    ap.add_argument("--serve-requests", type=int, default=300, help="requests in the serving leg")
+    ap.add_argument("--stab-codes", type=int, default=64, help="stabilizer codes in the modified-BZ leg")
     ap.add_argument("--serve-rate", type=float, default=0.0, help="requests/s (0: 60%% of measured capacity)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 3 device copies of 1 GiB (reference for HBM byte counters)")
