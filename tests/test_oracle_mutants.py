@@ -17,6 +17,7 @@ from oracle import oracle as O
 from paper_2408_10743_amd import workloads as W
 
 from test_oracle_pins import GOLD, f4_to_bin, py_exhaustive, swt, esym
+from test_oracle_rowspace_pins import all_vectors, py_span
 
 SRC = os.path.join(os.path.dirname(O.__file__), "qdo.c")
 
@@ -54,6 +55,10 @@ MUTANTS = {
     "mixed_one_row_clears_only_sr": ("        if (sv == sr || sv == (sr ^ beta))\n          row_add(R + (size_t)v * len, R + (size_t)r * len, len);\n      }\n      cand[r] = 0;",
                                      "        if (sv == sr)\n          row_add(R + (size_t)v * len, R + (size_t)r * len, len);\n      }\n      cand[r] = 0;"),
     "mixed_cap_counts_from_one": ("  int n2 = 0;\n  int *done", "  int n2 = 1;\n  int *done"),
+    "in_rowspace_always_member": ("  return r0 == r1 ? 1 : 0;", "  return 1;"),
+    "in_rowspace_compares_wrong_rank": ("  int r1 = reduce_basis(M, m + 1, n, NULL);", "  int r1 = reduce_basis(M, m, n, NULL);"),
+    "symplectic_weight_and": ("    if (v[i] || v[n + i]) ++w;", "    if (v[i] && v[n + i]) ++w;"),
+    "symplectic_weight_x_only": ("    if (v[i] || v[n + i]) ++w;", "    if (v[i]) ++w;"),
 }
 
 
@@ -133,6 +138,19 @@ def quick_pins():
             two = sum(1 for d, p in zip(g["dims"], g["pivots"]) if d == 2 and p >= 0)
             if two != 2:  # a random code has room for both two-row packages
                 return False
+        # membership: every vector of F2^6 against the span written out
+        for s in range(6):
+            B = W.additive(3, 1 + s % 4, W.config_seed(82, s))
+            span = py_span(B)
+            for v in all_vectors(3):
+                if O.in_rowspace(B, v) != (v.tobytes() in span):
+                    return False
+        # symplectic weight: C(n, w) 3^w vectors of weight w
+        hist = [0] * 4
+        for v in all_vectors(3):
+            hist[O.symplectic_weight(v, 3)] += 1
+        if hist != [math.comb(3, w) * 3 ** w for w in range(4)]:
+            return False
         rows, dims = W.random_packages(6, 20, W.config_seed(15, 0), 0.5)
         sizes = [3 if d == 2 else 1 for d in dims]
         for t in range(1, 7):
