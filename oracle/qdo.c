@@ -666,6 +666,69 @@ int qdo_round(const uint8_t *rows, const int *dims, int P, int n, int t,
   return round_impl(rows, dims, P, n, t, nthreads, NULL, 0, wmin, witness, count);
 }
 
+/* Weight distribution of one round: hist[w] = number of combinations of t
+ * distinct packages, one nonzero element of each (Sec. 2.3), whose sum has
+ * symplectic weight w (Sec. 2).  Plain recursion over the same choices as
+ * qdo_round, one tally per combination. */
+typedef struct {
+  int P, t, W;
+  const int *ne;
+  const uint64_t *el;
+  unsigned long long *hist;  /* n+1 counters of this worker */
+} hist_ctx;
+
+static void hist_rec(hist_ctx *c, int start, int depth, const uint64_t *cur) {
+  int W2 = 2 * c->W;
+  if (depth == c->t) {
+    ++c->hist[packed_swt(cur, c->W)];
+    return;
+  }
+  uint64_t nxt[8];
+  for (int i = start; i <= c->P - (c->t - depth); ++i)
+    for (int e = 0; e < c->ne[i]; ++e) {
+      const uint64_t *x = c->el + (size_t)(i * 3 + e) * W2;
+      for (int k = 0; k < W2; ++k) nxt[k] = cur[k] ^ x[k];
+      hist_rec(c, i + 1, depth + 1, nxt);
+    }
+}
+
+int qdo_round_hist(const uint8_t *rows, const int *dims, int P, int n, int t,
+                   int nthreads, unsigned long long *hist) {
+  if (!rows || !dims || P < 0 || n <= 0 || n > 256 || t < 1 || !hist)
+    return QDO_ERR_INVALID;
+  int W = words_of(n);
+  int *ne = (int *)malloc(sizeof(int) * (P + 1));
+  uint64_t *el = package_elements(rows, dims, P, n, ne);
+  if (!ne || !el) { free(ne); free(el); return QDO_ERR_NOMEM; }
+  for (int w = 0; w <= n; ++w) hist[w] = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic)
+  for (int i0 = 0; i0 < P; ++i0) {
+    if (i0 > P - t) continue;
+    unsigned long long *mine = (unsigned long long *)calloc((size_t)n + 1, sizeof(unsigned long long));
+    hist_ctx c;
+    c.P = P; c.t = t; c.W = W; c.ne = ne; c.el = el; c.hist = mine;
+    uint64_t cur[8];
+    for (int e = 0; e < ne[i0]; ++e) {
+      const uint64_t *x = el + (size_t)(i0 * 3 + e) * 2 * W;
+      for (int k = 0; k < 2 * W; ++k) cur[k] = x[k];
+      hist_rec(&c, i0 + 1, 1, cur);
+    }
+#pragma omp critical
+    {
+      for (int w = 0; w <= n; ++w) hist[w] += mine[w];
+    }
+    free(mine);
+  }
+  free(ne);
+  free(el);
+  return QDO_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Brouwer-Zimmermann (Sec. 2.1).                                           */
 /* U: smallest weight seen (starts at the sentinel n+1).                   */

@@ -94,6 +94,12 @@ int qdo_round(const uint8_t *rows, const int *dims, int P, int n, int t,
               int nthreads, int *wmin, uint8_t *witness,
               unsigned long long *count);
 
+/* Weight distribution of the same round: hist[w] (n+1 entries) counts the
+ * combinations whose sum has symplectic weight w.  Sum of hist = the
+ * count of qdo_round; its least nonzero index below n+1 = its minimum. */
+int qdo_round_hist(const uint8_t *rows, const int *dims, int P, int n, int t,
+                   int nthreads, unsigned long long *hist);
+
 /* Brouwer-Zimmermann over a given list of generator matrices (Sec. 2.1).
  * Gamma_j has P[j] packages starting at package offset off[j] of rows/dims,
  * delta[j] of which are not pivoted inside its own qubit set.

@@ -18,6 +18,7 @@ from paper_2408_10743_amd import workloads as W
 
 from test_oracle_pins import GOLD, f4_to_bin, py_exhaustive, swt, esym
 from test_oracle_rowspace_pins import all_vectors, py_span
+from test_oracle_round_hist_pins import py_hist, _pauli_packages
 
 SRC = os.path.join(os.path.dirname(O.__file__), "qdo.c")
 
@@ -59,6 +60,11 @@ MUTANTS = {
     "in_rowspace_compares_wrong_rank": ("  int r1 = reduce_basis(M, m + 1, n, NULL);", "  int r1 = reduce_basis(M, m, n, NULL);"),
     "symplectic_weight_and": ("    if (v[i] || v[n + i]) ++w;", "    if (v[i] && v[n + i]) ++w;"),
     "symplectic_weight_x_only": ("    if (v[i] || v[n + i]) ++w;", "    if (v[i]) ++w;"),
+    "hist_repeats_a_package": ("      hist_rec(c, i + 1, depth + 1, nxt);", "      hist_rec(c, i, depth + 1, nxt);"),
+    "hist_drops_weight_n": ("      for (int w = 0; w <= n; ++w) hist[w] += mine[w];",
+                            "      for (int w = 0; w < n; ++w) hist[w] += mine[w];"),
+    "hist_skips_third_element": ("    for (int e = 0; e < c->ne[i]; ++e) {\n      const uint64_t *x = c->el + (size_t)(i * 3 + e) * W2;\n      for (int k = 0; k < W2; ++k) nxt[k] = cur[k] ^ x[k];\n      hist_rec",
+                                 "    for (int e = 0; e < c->ne[i] && e < 2; ++e) {\n      const uint64_t *x = c->el + (size_t)(i * 3 + e) * W2;\n      for (int k = 0; k < W2; ++k) nxt[k] = cur[k] ^ x[k];\n      hist_rec"),
 }
 
 
@@ -156,6 +162,18 @@ def quick_pins():
         for t in range(1, 7):
             if O.round_min(rows, dims, t)[2] != esym(sizes, t):
                 return False
+        # round weight distributions: Python enumeration and the full space
+        for s in range(4):
+            rows, dims = W.random_packages(5, 9 + 20 * s, W.config_seed(84, s), 0.6)
+            for t in range(1, 6):
+                if [int(x) for x in O.round_hist(rows, dims, t)] != [int(x) for x in py_hist(rows, dims, t)]:
+                    return False
+        rows, dims = _pauli_packages(4, 4, 2)
+        tot = [0] * 5
+        for t in range(1, 5):
+            tot = [a + int(b) for a, b in zip(tot, O.round_hist(rows, dims, t))]
+        if tot != [0] + [math.comb(4, w) * 3 ** w for w in range(1, 5)]:
+            return False
         return True
     except O.OracleError:
         return False
