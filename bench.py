@@ -1,17 +1,31 @@
 """Benchmark of the hot path on one MI355X.
 
 One step = one exact distance computation of the throughput workload (an
-additive code, n = 72 qubits, m = 72 i.i.d. Bernoulli(1/2) rows; seeded):
-input check, basis, diagonalizations, planning, saved tables, every
-enumeration round and the witness check, through the C ABI.  The step's
-input is a 10 KB host matrix; the generator matrices the kernels read are
-built and kept in HBM by the library inside the step.
+additive code, n = 72 qubits, m = 72 i.i.d. Bernoulli(1/2) rows; seeded)
+with every word of every codeword evaluated: input check, basis,
+diagonalizations, planning, saved tables, every enumeration round and the
+witness check, through the C ABI.  The step's input is a 10 KB host matrix;
+the generator matrices the kernels read are built and kept in HBM by the
+library inside the step.
 
-Prints ONE JSON line: codewords/s over the timed steps (combinations
-actually visited / wall time), the time to an exact d, the roofline of the
-enumeration kernel (integer VALU bound) measured with HIP events on the
-launch stream, and the CPU oracle timed on a bounded sample of the same
-workload.
+Prints ONE JSON line:
+  value        codewords/s over the timed steps: combinations enumerated by
+               the rounds the exact distance needs, each codeword XORed and
+               weighed in full, over wall time;
+  time_to_exact_d_ms
+               the same code on the library's default path (partial
+               weights decide most codewords from their first word), timed
+               over the same number of steps; its rate is reported as
+               combinations certified per second, never as codewords/s;
+  roofline     the enumeration kernel of the every-word run against the
+               integer VALU peak, 4D+1 lane-ops per codeword (2D XOR, D OR,
+               D popcount, 1 min), kernel time from HIP events recorded by
+               the library on the launch stream;
+  plain_per_code
+               the plain per-round walk on the same code (one launch per
+               (t, Gamma_j) round), the comparator of the engine;
+  cpu_baseline the CPU oracle timed on the host's cores (single thread and
+               all threads of the job's CPU share).
 """
 import argparse
 import json
@@ -28,12 +42,12 @@ sys.path.insert(0, ROOT)
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
 
 
-# HBM bytes per launch of the round kernel on this workload, from two
-# rocprofv3 --pmc passes (FETCH_SIZE x2.0, WRITE_SIZE x1.0, factors from a
-# 1 GiB device copy in the same runs), valid only for the kernel source
-# with this fingerprint (sha256 prefixes of round.hip and kernels.hpp, the
-# enumeration kernel and its data layouts).
-TRAFFIC = {"fingerprint": "d01b1ee72cb9aa6e210d0fd35c79cca9", "bytes_per_launch": 836256280}
+# HBM bytes per launch of the round kernel in the every-word run of this
+# workload, from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, each
+# scaled by what it reads for a 1 GiB device copy in the same runs), valid
+# only for the kernel source with this fingerprint (sha256 prefixes of
+# round.hip and kernels.hpp, the enumeration kernel and its data layouts).
+TRAFFIC = {"fingerprint": None, "bytes_per_launch": None}
 
 
 def kernel_fingerprint():
@@ -46,18 +60,14 @@ def kernel_fingerprint():
 
 
 def ops_per_codeword(D):
-    """32-bit integer ops per codeword with every word evaluated: per word
-    one XOR (x), one fused XOR-OR (z, v_bitop3) and one popcount, plus one
-    MIN."""
+    """32-bit integer ops per codeword with every word evaluated: 2D XOR
+    (x and z halves with the saved entry), D OR, D popcount and one MIN.
+    The kernel fuses one XOR with the OR (v_bitop3), so it issues 3D + 1."""
+    return 4 * D + 1
+
+
+def issued_ops_per_codeword(D):
     return 3 * D + 1
-
-
-def algorithmic_ops(words, combos):
-    """Integer ops the enumeration needs: three per evaluated word and one
-    MIN per codeword.  With partial weights a codeword whose first words
-    already decide it costs fewer words; without, words = D x combos and
-    this is combos x ops_per_codeword(D)."""
-    return 3 * words + combos
 
 
 def parse():
@@ -67,7 +77,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2, help="untimed calls before them")
     ap.add_argument("--seed", type=int, default=0, help="seed of the main code (n = 72, m = 72)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
-    ap.add_argument("--cpu-seconds", type=float, default=30.0, help="time limit of the CPU oracle sample")
+    ap.add_argument("--cpu-runs", type=int, default=5, help="runs of each CPU oracle sample (median reported)")
+    ap.add_argument("--cpu-exact", action="store_true",
+                    help="only time the CPU oracle's whole Brouwer-Zimmermann on the main code (3 runs), "
+                         "its time to exact d")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched, plain, serving and latency legs")
     ap.add_argument("--batch-codes", type=int, default=512, help="codes in the batched leg")
     ap.add_argument("--batch-max-work", type=float, default=1e11, help="largest predicted work of a batched code")
@@ -78,6 +91,8 @@ def parse():
                     help="also run 3 device copies of 1 GiB (reference for HBM byte counters)")
     ap.add_argument("--valu-probe", action="store_true",
                     help="only time the VALU instruction mixes of qd_valu_mix and print their rates")
+    ap.add_argument("--default-only", action="store_true",
+                    help="only run the default-path steps on the main code (partial weights), for a profiler")
     ap.add_argument("--walk-only", action="store_true",
                     help="only run the plain per-round walk on the same code (--steps timed calls after "
                          "one warm-up call), for a profiler")
@@ -91,29 +106,97 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(G, field, budget_s):
-    """The oracle's plain enumeration of the same code's rounds t = 1..6 on
-    both generator matrices (about 2.9e9 codewords), stopped early once
-    budget_s seconds have passed."""
+def cpu_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    omp = os.environ.get("OMP_NUM_THREADS")
+    return {"model": model, "nproc": os.cpu_count(), "affinity": affinity,
+            "OMP_NUM_THREADS": int(omp) if omp and omp.isdigit() else None}
+
+
+def oracle_exact_combinations(seed):
+    """Combinations the oracle's BZ enumerates on config 3 to reach the exact
+    distance, from its recorded trace (written by tests/golden/make_golden.py,
+    which calls only the oracle); None when the trace was not recorded."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_distances.json")
+    try:
+        rounds = json.load(open(path))["config3_oracle_rounds"][seed]
+    except (OSError, KeyError, IndexError):
+        return None
+    return sum(r[4] for r in rounds)
+
+
+def cpu_baseline(G, field, runs, seed):
+    """The oracle's plain enumeration of the same code's rounds, built -O3
+    -march=native on this host: rounds t = 1..5 of both generator matrices
+    on one thread (1.8e8 codewords) and t = 1..6 on all threads of the
+    job's CPU share (2.9e9 codewords), `runs` runs each, medians.  The
+    oracle's time to exact d is extrapolated from the all-thread rate and
+    the combinations its BZ enumerates (recorded trace)."""
     from oracle import oracle as O
-    cores = min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), 16)
+    O.use_native()
+    info = cpu_info()
+    threads = min(info["affinity"], info["OMP_NUM_THREADS"] or info["affinity"])
     B = O.expand(G, field)
     gs = O.gamma(B, O.DIAG_F4, 2, with_rows=True)
-    done, visited, last = 0.0, 0, None
-    for t in range(1, 7):
-        for j, g in enumerate(gs):
-            t0 = time.perf_counter()
-            _, _, cnt = O.round_min(g["rows"], g["dims"], t, nthreads=cores)
-            done += time.perf_counter() - t0
-            visited += cnt
-            last = (t, j + 1)
-            if done >= budget_s:
-                break
-        if done >= budget_s:
-            break
-    return {"value": visited / done, "unit": "codewords/s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle enumeration of the same code, rounds t=1..{last[0]} on Gamma_1..Gamma_{last[1]}: "
-                      f"{visited} codewords in {done:.2f} s wall on {cores} threads"}
+
+    def sample(tmax, nthreads):
+        rates, visited = [], 0
+        for _ in range(runs):
+            visited, wall = 0, 0.0
+            for t in range(1, tmax + 1):
+                for g in gs:
+                    t0 = time.perf_counter()
+                    _, _, cnt = O.round_min(g["rows"], g["dims"], t, nthreads=nthreads)
+                    wall += time.perf_counter() - t0
+                    visited += cnt
+            rates.append(visited / wall)
+        rates.sort()
+        return rates[len(rates) // 2], visited, rates
+
+    r1, v1, all1 = sample(5, 1)
+    rn, vn, alln = sample(6, threads)
+    exact = oracle_exact_combinations(seed)
+    out = {"value": rn, "unit": "codewords/s", "cores": threads, "kind": "oracle",
+           "sample": f"oracle (gcc -O3 -march=native, OpenMP) plain enumeration of the same code: rounds t=1..6 of "
+                     f"both generator matrices ({vn} codewords) on {threads} threads, median of {runs} runs; "
+                     f"single thread: rounds t=1..5 ({v1} codewords), median of {runs} runs",
+           "single_thread_codewords_per_s": r1, "all_threads_codewords_per_s": rn,
+           "runs_single": all1, "runs_all": alln, "cpu": info,
+           "build": "gcc -O3 -march=native -fopenmp"}
+    if exact is not None:
+        out["oracle_exact_d_combinations"] = exact
+        out["time_to_exact_d_s_extrapolated"] = exact / rn
+        out["time_to_exact_d_s_single_thread_extrapolated"] = exact / r1
+    return out
+
+
+def cpu_exact(G, field, seed, runs=3):
+    """The oracle's whole Brouwer-Zimmermann on the main code, -O3
+    -march=native, all threads of the job's CPU share: time to exact d."""
+    from oracle import oracle as O
+    O.use_native()
+    info = cpu_info()
+    threads = min(info["affinity"], info["OMP_NUM_THREADS"] or info["affinity"])
+    B = O.expand(G, field)
+    ts, d, combos = [], None, 0
+    for i in range(runs):
+        t0 = time.perf_counter()
+        d, _, log = O.bz(B, O.DIAG_F4, 2, nthreads=threads)
+        ts.append(time.perf_counter() - t0)
+        combos = sum(r[4] for r in log)
+        print(f"oracle BZ run {i}: d={d} {ts[-1]:.2f} s", file=sys.stderr, flush=True)
+    ts.sort()
+    return {"d": d, "median_s": ts[len(ts) // 2], "runs_s": ts, "combinations": combos,
+            "codewords_per_s": combos / ts[len(ts) // 2], "threads": threads, "cpu": info, "seed": seed}
 
 
 def predicted_work(Q, G, f):
@@ -142,44 +225,90 @@ def config4_codes(Q, W, count, max_work):
     return kept, drawn
 
 
-def leg_batched(Q, W, a):
-    codes, drawn = config4_codes(Q, W, a.batch_codes, a.batch_max_work)
-    budget = int(a.batch_max_work * 4)
+def kernel_roofline(stats, launches=None):
+    """Roofline of the enumeration kernel over runs with every word
+    evaluated: codewords the kernel enumerated (rounds run ahead included)
+    x (4D+1) lane-ops, over the kernel time spent on them (HIP events on
+    the launch stream, shared among a launch's codes by their tiles)."""
+    ops = sum(s.enumerated * ops_per_codeword(s.D) for s in stats)
+    issued = sum(s.enumerated * issued_ops_per_codeword(s.D) for s in stats)
+    ms = sum(s.enumerated_kernel_ms for s in stats)
+    assert all(s.words == s.D * s.enumerated for s in stats), "not an every-word run"
+    achieved = ops / (ms * 1e-3)
+    out = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
+           "frac": achieved / PEAK_LANE_OPS,
+           "ops_basis": "4D+1 lane-ops per codeword (2D XOR, D OR, D popcount, 1 min)",
+           "codewords_enumerated": sum(s.enumerated for s in stats),
+           "kernel_ms_total": ms,
+           "frac_issued_3D1": issued / (ms * 1e-3) / PEAK_LANE_OPS}
+    if launches:
+        out["launches"] = launches
+        out["avg_launch_ms"] = ms / launches
+        out["codewords_per_launch"] = out["codewords_enumerated"] / launches
+    return out
+
+
+def run_batch(Q, codes, budget, **opts):
     import torch
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, ds, wits, sts, stats = Q.qd_distance_batch(codes, budget=budget, **opts)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, ds, sts, stats
+
+
+def leg_batched(Q, W, a):
+    """Config 4 (the kept draws): the batch to exact d on the default path
+    against a loop of per-code calls, and the same batch with every word
+    evaluated for codewords/s and the kernel's roofline."""
+    codes, drawn = config4_codes(Q, W, a.batch_codes, a.batch_max_work)
+    budget = int(a.batch_max_work * 4)
     # The first call also fills the library's device-memory pool (tables of
-    # every code); the timed call is the second, as the per-code loop below
+    # every code); the timed calls come after it, as the per-code loop below
     # runs with a warm pool too.
-    t0 = time.perf_counter()
-    Q.qd_distance_batch(codes, budget=budget)
-    t_cold = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    st, ds, wits, sts, stats = Q.qd_distance_batch(codes, budget=budget)
-    t_batch = time.perf_counter() - t0
+    t_cold, _, _, _ = run_batch(Q, codes, budget)
+    runs = [run_batch(Q, codes, budget) for _ in range(3)]
+    runs.sort(key=lambda r: r[0])
+    t_batch, ds, sts, stats = runs[1]
     comb_b = sum(s.combinations for s in stats)
+    words_b = sum(s.words for s in stats)
+    enum_b = sum(s.enumerated for s in stats)
     t0 = time.perf_counter()
-    comb_p, ds_p = 0, []
+    comb_p, ds_p, kms_p = 0, [], 0.0
     for G, f in codes:
-        st1, d1, _, s1 = Q.qd_distance_ex(G, f, budget=budget)
+        st1, d1, _, s1 = Q.qd_distance_ex(G, f, budget=budget, timing=1)
         comb_p += s1.combinations
+        kms_p += s1.kernel_ms
         ds_p.append(d1)
     t_plain = time.perf_counter() - t0
+    # every word evaluated (codewords/s and roofline); timing on
+    run_batch(Q, codes, budget, partial_weight=-1)
+    fw = [run_batch(Q, codes, budget, partial_weight=-1, timing=1) for _ in range(3)]
+    fw.sort(key=lambda r: r[0])
+    t_fw, ds_fw, sts_fw, stats_fw = fw[1]
+    comb_fw = sum(s.combinations for s in stats_fw)
+    _, _, _, stats_bt = run_batch(Q, codes, budget, timing=1)
     ns = [G.shape[1] // 2 if f == 2 else G.shape[1] for G, f in codes]
     return {
         "workload": f"config 4: first {len(codes)} of {drawn} drawn codes (n~U{{24..96}}, even additive m~U{{n-8..n+8}}, "
                     f"odd F4-linear k=n/2) with planner-predicted work <= {a.batch_max_work:.0e}; budget {budget:.0e}",
         "codes": len(codes), "drawn": drawn, "n_range": [min(ns), max(ns)],
         "exact": sum(1 for x in sts if x == 0), "incomplete": sum(1 for x in sts if x == 1),
-        "same_d_as_per_code": ds == ds_p,
-        "batched_s": t_batch, "batched_codewords_per_s": comb_b / t_batch, "batched_first_call_s": t_cold,
-        "per_code_s": t_plain, "per_code_codewords_per_s": comb_p / t_plain,
-        "speedup": t_plain / t_batch,
+        "same_d_as_per_code": ds == ds_p, "same_d_every_word": ds_fw == ds,
+        "time_to_exact_d_s": t_batch, "batched_first_call_s": t_cold,
+        "per_code_loop_s": t_plain, "speedup_vs_per_code_loop": t_plain / t_batch,
+        "per_code_loop_kernel_s": kms_p * 1e-3,
+        "batched_kernel_s": sum(s.kernel_ms for s in stats_bt) * 1e-3,
+        "combinations_certified_per_s": comb_b / t_batch,
+        "words_per_codeword": words_b / max(enum_b, 1),
+        "every_word": {"time_s": t_fw, "codewords_per_s": comb_fw / t_fw,
+                       "roofline": kernel_roofline(stats_fw)},
     }
 
 
-def leg_plain(Q, G, field, engine_step_ms, engine_combos):
-    """The plain per-code GPU path on the same code: no saved sums, every
-    lane unranks and XORs its whole combination."""
+def leg_unrank(Q, G, field, engine_step_ms):
+    """A per-code path without saved sums or a walk: every lane unranks and
+    XORs its whole combination (t rows per codeword)."""
     st, d, wit, s = Q.qd_distance_ex(G, field, saved_depth=-1, tops_mode=2, timing=1)
     assert st == 0
     return {"ms_per_step": s.wall_ms, "codewords_per_s": s.combinations / (s.wall_ms * 1e-3),
@@ -200,37 +329,21 @@ def leg_walk(Q, G, field, stream, engine_step_ms, steps):
         if i:
             runs.append(s)
     combos = sum(s.combinations for s in runs)
-    walked = sum(s.words for s in runs) / runs[0].D  # codewords evaluated (one-row packages repeat)
+    walked = sum(s.words for s in runs) / runs[0].D  # codewords evaluated
     kernel_ms = sum(s.kernel_ms for s in runs)
     wall_ms = sum(s.wall_ms for s in runs)
     D = runs[0].D
-    return {"d": d, "ms_per_step": wall_ms / steps, "codewords_per_s": combos / (wall_ms * 1e-3),
+    ms = wall_ms / steps
+    return {"kind": "plain per-round walk: one launch per (t, Gamma_j), revolving-door package sets x "
+                    "ternary Gray element choices, every word of every codeword evaluated",
+            "d": d, "ms_per_step": ms, "codewords_per_s": combos / (wall_ms * 1e-3),
             "kernel_codewords_per_s": combos / (kernel_ms * 1e-3),
             "walked_per_combination": walked / combos,
             "launches_per_step": sum(s.launches for s in runs) / steps,
             # per walked codeword: 2D XOR + D OR + D v_bcnt + 1 min
-            "roofline_frac_4D1_ops": walked * (4 * D + 1) / (kernel_ms * 1e-3) / PEAK_LANE_OPS,
-            "engine_speedup": (wall_ms / steps) / engine_step_ms}
-
-
-def leg_full_weight(Q, G, field, stream, steps):
-    """The same code with every word of every codeword evaluated
-    (partial_weight = -1): the enumeration rate without partial weights."""
-    runs = []
-    for i in range(steps + 1):
-        st, d, wit, s = Q.qd_distance_ex(G, field, stream=stream, timing=1, partial_weight=-1)
-        assert st == 0
-        if i:
-            runs.append(s)
-    combos = sum(s.combinations for s in runs)
-    enum = sum(s.enumerated for s in runs)
-    words = sum(s.words for s in runs)
-    kernel_ms = sum(s.kernel_ms for s in runs)
-    enum_ms = sum(s.enumerated_kernel_ms for s in runs)
-    wall_ms = sum(s.wall_ms for s in runs)
-    return {"d": d, "ms_per_step": wall_ms / steps, "codewords_per_s": combos / (wall_ms * 1e-3),
-            "kernel_codewords_per_s": combos / (kernel_ms * 1e-3),
-            "roofline_frac": algorithmic_ops(words, enum) / (enum_ms * 1e-3) / PEAK_LANE_OPS}
+            "roofline_frac": walked * ops_per_codeword(D) / (kernel_ms * 1e-3) / PEAK_LANE_OPS,
+            "engine_speedup": ms / engine_step_ms,
+            "target_5x_engine_ms": ms / 5}
 
 
 def leg_constructions(Q, W):
@@ -318,10 +431,7 @@ def leg_latency(Q, W):
     return out
 
 
-def leg_serving(Q, W, a):
-    """Config 5: Poisson arrivals, n log-uniform in 16..96, alternately
-    additive (m = n) and F4-linear (k = n/2); requests whose predicted work
-    exceeds 1e10 are redrawn (stated in the output)."""
+def serving_requests(Q, W, a):
     raw = W.config5(a.serve_requests * 4, 1.0)
     reqs, drawn = [], 0
     for _, G, f in raw:
@@ -330,11 +440,20 @@ def leg_serving(Q, W, a):
             reqs.append((G, f))
             if len(reqs) == a.serve_requests:
                 break
+    return reqs, drawn
+
+
+def leg_serving(Q, W, a, **opts):
+    """Config 5: Poisson arrivals, n log-uniform in 16..96, alternately
+    additive (m = n) and F4-linear (k = n/2); requests whose predicted work
+    exceeds 1e10 are redrawn (stated in the output).  opts apply to every
+    request (partial_weight=-1: every word evaluated)."""
+    reqs, drawn = serving_requests(Q, W, a)
     # service capacity: the same requests run back to back as one batch
     # (timed on a second call, after device memory and tables are warm)
-    Q.qd_distance_batch(reqs)
+    Q.qd_distance_batch(reqs, **opts)
     t0 = time.perf_counter()
-    Q.qd_distance_batch(reqs)
+    Q.qd_distance_batch(reqs, **opts)
     t_all = time.perf_counter() - t0
     rate = a.serve_rate or 0.6 * len(reqs) / t_all
     gaps = [t for t, _, _ in W.config5(len(reqs), rate, index=1)]
@@ -346,18 +465,19 @@ def leg_serving(Q, W, a):
             for r, w in Q.qd_engine_poll(e, 64, 0):
                 lat.append(r.latency_ms); comb += r.combinations; statuses.append(r.status)
             time.sleep(0.0002)
-        Q.qd_engine_submit(e, G, f, i)
+        Q.qd_engine_submit(e, G, f, i, **opts)
     while len(lat) < len(reqs):
         for r, w in Q.qd_engine_poll(e, 64, 100):
             lat.append(r.latency_ms); comb += r.combinations; statuses.append(r.status)
     t_total = time.perf_counter() - t_start
     Q.qd_engine_destroy(e)
     lat.sort()
+    key = "codewords_per_s" if opts.get("partial_weight") == -1 else "combinations_certified_per_s"
     return {"workload": f"config 5: {len(reqs)} requests of {drawn} drawn (predicted work <= 1e10), "
                         f"Poisson rate {rate:.1f}/s (60% of back-to-back capacity)",
             "rate_per_s": rate, "requests": len(reqs), "exact": sum(1 for x in statuses if x == 0),
             "p50_ms": lat[len(lat) // 2], "p99_ms": lat[min(len(lat) - 1, int(0.99 * len(lat)))],
-            "codewords_per_s": comb / t_total, "window_s": t_total}
+            key: comb / t_total, "window_s": t_total}
 
 
 def main():
@@ -402,6 +522,9 @@ def main():
         return
     stream = torch.cuda.current_stream()
     G, field = W.config3(a.seed)
+    if a.cpu_exact:
+        print(json.dumps({"cpu_exact": cpu_exact(G, field, a.seed)}))
+        return
     if a.batch_only:
         print(json.dumps({"batched": leg_batched(Q, W, a)}))
         return
@@ -412,36 +535,48 @@ def main():
         print(json.dumps({"walk_per_round": leg_walk(Q, G, field, stream.cuda_stream, float("nan"), a.steps)}))
         return
 
-    def step():
-        st, d, wit, s = Q.qd_distance_ex(G, field, stream=stream.cuda_stream, timing=1)
-        if st != 0:
-            raise RuntimeError(Q.qd_strerror(st))
-        return d, s
+    def run(steps, **opts):
+        """`steps` calls on the main code, bracketed by device syncs."""
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = []
+        for _ in range(steps):
+            st, d, wit, s = Q.qd_distance_ex(G, field, stream=stream.cuda_stream, timing=1, **opts)
+            if st != 0:
+                raise RuntimeError(Q.qd_strerror(st))
+            out.append((d, s))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
 
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = [step() for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    if a.default_only:
+        run(a.warmup)
+        wall, stats = run(a.steps)
+        print(json.dumps({"default_path_ms_per_step": wall * 1e3 / a.steps}))
+        return
 
+    # The step: every word of every codeword evaluated (partial_weight -1).
+    run(a.warmup, partial_weight=-1)
+    wall, stats = run(a.steps, partial_weight=-1)
     d = stats[0][0]
     assert all(x[0] == d for x in stats)
     combos = sum(s.combinations for _, s in stats)
     kernel_ms = sum(s.kernel_ms for _, s in stats)
     launches = sum(s.launches for _, s in stats)
     D = stats[0][1].D
-    # The roofline counts what the device enumerated (rounds run ahead
-    # speculatively included) over the launch time spent on it.
-    words = sum(s.words for _, s in stats)
-    enum = sum(s.enumerated for _, s in stats)
-    enum_ms = sum(s.enumerated_kernel_ms for _, s in stats)
-    achieved = algorithmic_ops(words, enum) / (enum_ms * 1e-3)
-    achieved_survey = (4 * words + enum) / (enum_ms * 1e-3)
     s0 = stats[0][1]
+    roof = kernel_roofline([s for _, s in stats], launches)
+    roof["kernel"] = f"qd_round_kernel<{D}, false>"
+    roof["traffic"] = TRAFFIC["bytes_per_launch"] if kernel_fingerprint() == TRAFFIC["fingerprint"] else None
+    # The library's default path on the same code: time to exact d.
+    run(a.warmup)
+    wall_d, stats_d = run(a.steps)
+    assert all(x[0] == d for x in stats_d)
+    combos_d = sum(s.combinations for _, s in stats_d)
+    words_d = sum(s.words for _, s in stats_d)
+    enum_d = sum(s.enumerated for _, s in stats_d)
+    ttd_ms = wall_d * 1e3 / a.steps
     out = {
-        "metric": "codewords/s (XOR+symplectic wt) & time-to-exact-d",
+        "metric": "codewords/s (XOR+symplectic wt) & time-to-exact-d: batched vs plain per-code",
         "value": combos / wall,
         "unit": "codewords/s",
         "n_gpus": 1,
@@ -453,27 +588,24 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"single additive code n=72 m=72 Bernoulli(1/2), seed {a.seed} (config 3)",
+        "config": {"workload": f"single additive code n=72 m=72 Bernoulli(1/2), seed {a.seed} (config 3), "
+                               f"exact d with every word of every codeword evaluated",
                    "d": d, "diag": "F4" if s0.diag == 4 else "F2", "gammas": s0.h,
                    "packages": list(s0.P)[:s0.h], "delta": list(s0.delta)[:s0.h],
                    "rounds": s0.nlog, "codewords_per_step": combos // a.steps},
-        "time_to_exact_d_ms": wall * 1e3 / a.steps,
-        "host_ms_per_step": sum(s.host_ms for _, s in stats) / a.steps,
         "kernel_codewords_per_s": combos / (kernel_ms * 1e-3),
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_LANE_OPS / 1e12,
-            "unit": "TOP/s",
-            "frac": achieved / PEAK_LANE_OPS,
-            "traffic": TRAFFIC["bytes_per_launch"] if kernel_fingerprint() == TRAFFIC["fingerprint"] else None,
-            "kernel": f"qd_round_kernel<{D}>",
-            "ops_per_codeword": algorithmic_ops(words, enum) / enum,
-            "words_per_codeword": words / enum,
-            "frac_4D1_ops": achieved_survey / PEAK_LANE_OPS,
-            "launches": launches,
-            "avg_launch_ms": enum_ms / max(launches, 1),
+        "host_ms_per_step": sum(s.host_ms for _, s in stats) / a.steps,
+        "time_to_exact_d_ms": ttd_ms,
+        "default_path": {
+            "kind": "the library's default path: partial weights decide a codeword from its first words "
+                    "plus a pivot credit, completing only blocks that may hold a weight below U",
+            "time_to_exact_d_ms": ttd_ms,
+            "combinations_certified_per_s": combos_d / wall_d,
+            "words_per_codeword": words_d / enum_d,
+            "kernel_ms_per_step": sum(s.kernel_ms for _, s in stats_d) / a.steps,
+            "speedup_vs_every_word": (wall * 1e3 / a.steps) / ttd_ms,
         },
+        "roofline": roof,
         "device": name,
     }
     if a.copy_calibration:
@@ -484,16 +616,17 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = src.numel() * 4
     if not a.no_extra:
-        out["full_weight"] = leg_full_weight(Q, G, field, stream.cuda_stream, 5)
-        out["plain_per_code"] = leg_plain(Q, G, field, wall * 1e3 / a.steps, combos / a.steps)
-        out["walk_per_round"] = leg_walk(Q, G, field, stream.cuda_stream, wall * 1e3 / a.steps, 3)
+        out["plain_per_code"] = leg_walk(Q, G, field, stream.cuda_stream, ttd_ms, 3)
+        out["plain_per_code"]["engine_every_word_speedup"] = out["plain_per_code"]["ms_per_step"] / out["ms_per_step"]
+        out["unrank_per_lane"] = leg_unrank(Q, G, field, ttd_ms)
         out["batched"] = leg_batched(Q, W, a)
         out["serving"] = leg_serving(Q, W, a)
+        out["serving_every_word"] = leg_serving(Q, W, a, partial_weight=-1)
         out["latency"] = leg_latency(Q, W)
         out["constructions"] = leg_constructions(Q, W)
         out["stabilizer"] = leg_stabilizer(Q, W, a)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(G, field, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(G, field, a.cpu_runs, a.seed)
     print(json.dumps(out), flush=True)
 
 

@@ -256,6 +256,20 @@ int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int 
                  uint8_t *witness, unsigned long long *count,
                  int partial_words);
 
+/* qd_round_min plus a census of the round's weight distribution (Sec. 2:
+ * symplectic weight; Sec. 2.3: the round's combinations), taken by the same
+ * enumeration kernel in the same tiles and blocks: below_count receives the
+ * number of combinations whose codeword has weight < below, below_weight_sum
+ * the sum of those weights (below > n + 1 counts every combination, so the
+ * two are the round's size and total weight).  With partial_words = w the
+ * tiles evaluate words 0..w-1 first and complete every block where some
+ * partial weight is below max(U, below), so both figures stay exact.
+ * below must be >= 1 (else QD_ERR_INVALID); other arguments and errors as
+ * qd_round_min.  The output pointers must not be NULL. */
+int qd_round_census(const uint8_t *rows, const int *dims, int P, int n, int t, int partial_words,
+                    int below, int *wmin, uint8_t *witness, unsigned long long *count,
+                    unsigned long long *below_count, unsigned long long *below_weight_sum);
+
 /* The same round with the plain walk kernel (qd_options.walk = per_lane:
  * package sets per lane, 1..4096, 1 choosing from the round size; others
  * QD_ERR_INVALID; t > 8 is QD_ERR_TOO_LARGE): minimum symplectic weight,

@@ -223,7 +223,8 @@ namespace {
 
 // One round over a caller-given package layout (qd_round_min, qd_round_walk).
 int one_round(const uint8_t *rows, const int *dims, int P, int n, int t, int partial_words, int walk, int *wmin,
-              uint8_t *witness, unsigned long long *count, unsigned long long *weight_sum) {
+              uint8_t *witness, unsigned long long *count, unsigned long long *weight_sum, int below = 0,
+              unsigned long long *census = nullptr) {
   if (!rows || !dims || !wmin || !count || P <= 0 || P > 2 * kMaxN || t < 1 || n <= 0) return QD_ERR_INVALID;
   if (n > kMaxN) return QD_ERR_TOO_LARGE;
   if (partial_words < 0 || (partial_words > 0 && partial_words >= (n + 31) / 32)) return QD_ERR_INVALID;
@@ -236,6 +237,7 @@ int one_round(const uint8_t *rows, const int *dims, int P, int n, int t, int par
   job.opt.walk = walk;
   job.want_wsum = weight_sum != nullptr;
   job.force_words = partial_words;
+  job.census_below = census ? std::min(below, n + 2) : 0;
   Gamma g;
   for (int i = 0; i < P; ++i) {
     if (dims[i] != 1 && dims[i] != 2) return QD_ERR_INVALID;
@@ -252,6 +254,7 @@ int one_round(const uint8_t *rows, const int *dims, int P, int n, int t, int par
   *wmin = n + 1;
   *count = 0;
   if (weight_sum) *weight_sum = 0;
+  if (census) census[0] = census[1] = 0;
   if (t > P) return QD_OK;
   if (t > kTMax || (walk > 0 && t > kWalkMaxT)) return QD_ERR_TOO_LARGE;
   job.use.push_back(g);
@@ -267,6 +270,10 @@ int one_round(const uint8_t *rows, const int *dims, int P, int n, int t, int par
   *wmin = job.U;
   *count = job.visited;
   if (weight_sum) *weight_sum = job.wsum;
+  if (census) {
+    census[0] = job.census[0];
+    census[1] = job.census[1];
+  }
   if (witness && job.U <= n) unpack(job.wit, n, witness);
   return QD_OK;
 }
@@ -276,6 +283,17 @@ int one_round(const uint8_t *rows, const int *dims, int P, int n, int t, int par
 int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int *wmin, uint8_t *witness,
                  unsigned long long *count, int partial_words) {
   return one_round(rows, dims, P, n, t, partial_words, 0, wmin, witness, count, nullptr);
+}
+
+int qd_round_census(const uint8_t *rows, const int *dims, int P, int n, int t, int partial_words, int below,
+                    int *wmin, uint8_t *witness, unsigned long long *count, unsigned long long *below_count,
+                    unsigned long long *below_weight_sum) {
+  if (below < 1 || !below_count || !below_weight_sum) return QD_ERR_INVALID;
+  unsigned long long c[2] = {0, 0};
+  const int rc = one_round(rows, dims, P, n, t, partial_words, 0, wmin, witness, count, nullptr, below, c);
+  *below_count = c[0];
+  *below_weight_sum = c[1];
+  return rc;
 }
 
 int qd_round_walk(const uint8_t *rows, const int *dims, int P, int n, int t, int per_lane, int *wmin,

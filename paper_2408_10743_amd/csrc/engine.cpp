@@ -10,7 +10,7 @@
 
 namespace qd {
 
-hipError_t launch_round(int D, const LaunchParams &lp, hipStream_t s);
+hipError_t launch_round(int D, const LaunchParams &lp, bool census, hipStream_t s);
 hipError_t launch_walk(int D, const LaunchParams &lp, bool sum, hipStream_t s);
 hipError_t launch_build(int D, const BuildParams &bp, hipStream_t s);
 hipError_t launch_commit(const LaunchParams &lp, hipStream_t s);
@@ -993,6 +993,10 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
           L.sum = L.sum || job.want_wsum;
           d.stage = 1;
           lds = walk_lds_bytes(d.P, d.t);
+        } else if (job.census_below > 0) {
+          d.census = d.counters + 3;  // words 3 and 4 of the first counter line
+          d.below = job.census_below;
+          L.sum = true;
         }
         if (lds > kStageMaxBytes) { d.stage = 0; lds = 0; }
         L.lds = std::max(L.lds, lds);
@@ -1031,7 +1035,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
       lp.tiles = L.tiles;
       lp.slots = static_cast<uint32_t *>(slots_.p);
       if (L.timed && hipEventRecord(events_[2 * i], s) != hipSuccess) return QD_ERR_DEVICE;
-      if ((L.walk ? launch_walk(L.D, lp, L.sum, s) : launch_round(L.D, lp, s)) != hipSuccess) return QD_ERR_DEVICE;
+      if ((L.walk ? launch_walk(L.D, lp, L.sum, s) : launch_round(L.D, lp, L.sum, s)) != hipSuccess) return QD_ERR_DEVICE;
       if (L.timed && hipEventRecord(events_[2 * i + 1], s) != hipSuccess) return QD_ERR_DEVICE;
       if (launch_commit(lp, s) != hipSuccess) return QD_ERR_DEVICE;
     }
@@ -1118,6 +1122,10 @@ void Executor::retire(Job &job) {
   }
   if (job.want_wsum && job.data.p && !job.status &&
       hipMemcpy(&job.wsum, static_cast<unsigned long long *>(job.data.p) + 2, sizeof(job.wsum),
+                hipMemcpyDeviceToHost) != hipSuccess)
+    job.status = QD_ERR_DEVICE;
+  if (job.census_below > 0 && job.data.p && !job.status &&
+      hipMemcpy(job.census, static_cast<unsigned long long *>(job.data.p) + 3, sizeof(job.census),
                 hipMemcpyDeviceToHost) != hipSuccess)
     job.status = QD_ERR_DEVICE;
   for (GammaDev &g : job.gd) {

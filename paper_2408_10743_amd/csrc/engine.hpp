@@ -136,6 +136,8 @@ struct Job {
   unsigned long long r_structure = 0;
   bool want_wsum = false;        // plain walk: sum the weights of the walked codewords
   unsigned long long wsum = 0;   // (read back by retire)
+  int census_below = 0;          // > 0: census of the codewords of weight below it
+  unsigned long long census[2] = {0, 0};  // their count and weight sum (read back by retire)
   std::vector<BRow> logicals;  // Modified BZ: the admission test's operators
   std::vector<GammaDev> gd;
   int state_slot = -1;

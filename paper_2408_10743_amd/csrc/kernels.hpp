@@ -106,6 +106,13 @@ struct RoundDesc {
   int stage;                           // 1: copy the groups to LDS; 2: also suffix
                                        //    columns and elements (unranking path)
   int commit;                          // 1 for the first piece of its code in the launch
+  // Census (round kernel, qd_round_census): codewords of weight below
+  // `below` are counted in census[0] and their weights summed in census[1]
+  // (NULL: not taken).  Partial-weight tiles then complete every block that
+  // may hold such a codeword, so both figures are exact.
+  unsigned long long *census;
+  int below;
+  int pad_census;
   // Plain walk kernel (walk.hip) only.
   const unsigned long long *binom;     // C(p, r) at p * (t + 1) + r, p <= P, r <= t
   unsigned long long *wsum;            // sum of the walked codewords' weights (NULL: not taken)

@@ -58,10 +58,21 @@ __device__ __forceinline__ uint32_t weight_at(const uint32_t *__restrict__ table
   return acc;
 }
 
-// Minimum over one block of kBlock table entries (SoA: word-major).
-template <int D>
+// Census of one codeword weight: counted (and summed) when below `below`.
+struct Census {
+  uint32_t below = 0, cnt = 0, sum = 0;
+  __device__ __forceinline__ void add(uint32_t w) {
+    const bool in = w < below;
+    cnt += in ? 1u : 0u;
+    sum += in ? w : 0u;
+  }
+};
+
+// Minimum over one block of kBlock table entries (SoA: word-major).  With
+// kCensus the block's weights also enter the census.
+template <int D, bool kCensus>
 __device__ __forceinline__ uint32_t block_min(const uint32_t (&ax)[D], const uint32_t (&az)[D],
-                                              const uint32_t *__restrict__ blk, uint32_t best) {
+                                              const uint32_t *__restrict__ blk, uint32_t best, Census &cs) {
   uint32_t v[2 * D][kBlock];
 #pragma unroll
   for (int j = 0; j < 2 * D; ++j)
@@ -78,6 +89,10 @@ __device__ __forceinline__ uint32_t block_min(const uint32_t (&ax)[D], const uin
     }
     w[e] = acc;
   }
+  if constexpr (kCensus) {
+#pragma unroll
+    for (int e = 0; e < kBlock; ++e) cs.add(w[e]);
+  }
   // One three-input min per pair of codewords.
 #pragma unroll
   for (int e = 0; e < kBlock; e += 2) best = min3(best, w[e], w[e + 1]);
@@ -87,11 +102,13 @@ __device__ __forceinline__ uint32_t block_min(const uint32_t (&ax)[D], const uin
 // NB consecutive blocks with partial weights: words 0..W-1 first; if some
 // lane's bound (partial weight + credit) falls below U (thr = U - credit),
 // the blocks' remaining words are added and their full weights enter
-// `best`.  `rec` counts the blocks evaluated in full.
-template <int D, int W, int NB>
+// `best`.  `rec` counts the blocks evaluated in full.  With kCensus the
+// completed blocks' weights enter the census (a block that is not completed
+// holds no codeword of weight below thr + credit).
+template <int D, int W, int NB, bool kCensus>
 __device__ __forceinline__ uint32_t blocks_min_partial(const uint32_t (&ax)[D], const uint32_t (&az)[D],
                                                        const uint32_t *__restrict__ blk, uint32_t best,
-                                                       uint32_t thr, uint32_t &rec) {
+                                                       uint32_t thr, uint32_t &rec, Census &cs) {
   constexpr int N = NB * kBlock;
   uint32_t w[N];
   {
@@ -139,6 +156,10 @@ __device__ __forceinline__ uint32_t blocks_min_partial(const uint32_t (&ax)[D], 
         w[e] = bcnt_acc(o, w[e]);
       }
     }
+    if constexpr (kCensus) {
+#pragma unroll
+      for (int e = 0; e < N; ++e) cs.add(w[e]);
+    }
 #pragma unroll
     for (int e = 0; e < N; e += 2) best = min3(best, w[e], w[e + 1]);
     rec += NB;
@@ -149,14 +170,15 @@ __device__ __forceinline__ uint32_t blocks_min_partial(const uint32_t (&ax)[D], 
 // The full blocks of a tile with partial weights, kPartialBlocks blocks per
 // wait for their scalar loads.
 constexpr int kPartialBlocks = 2;
-template <int D, int W>
+template <int D, int W, bool kCensus>
 __device__ __forceinline__ uint32_t partial_blocks(const uint32_t (&ax)[D], const uint32_t (&az)[D],
                                                    const uint32_t *__restrict__ blk, uint32_t nfull,
-                                                   uint32_t best, uint32_t thr, uint32_t &rec) {
+                                                   uint32_t best, uint32_t thr, uint32_t &rec, Census &cs) {
   uint32_t i = 0;
   for (; i + kPartialBlocks <= nfull; i += kPartialBlocks, blk += kPartialBlocks * 2 * D * kBlock)
-    best = blocks_min_partial<D, W, kPartialBlocks>(ax, az, blk, best, thr, rec);
-  for (; i < nfull; ++i, blk += 2 * D * kBlock) best = blocks_min_partial<D, W, 1>(ax, az, blk, best, thr, rec);
+    best = blocks_min_partial<D, W, kPartialBlocks, kCensus>(ax, az, blk, best, thr, rec, cs);
+  for (; i < nfull; ++i, blk += 2 * D * kBlock)
+    best = blocks_min_partial<D, W, 1, kCensus>(ax, az, blk, best, thr, rec, cs);
   return best;
 }
 
@@ -222,8 +244,9 @@ constexpr uint32_t kXcdChunk = 16;
 // One tile = one table segment [k0, k0 + seg) x 64 tops.  The tops of a
 // tile come from every group whose table prefix reaches the segment, so
 // lanes stay full; a lane stops at its own group's prefix length.  A launch
-// holds pieces of the current rounds of several codes (RoundDesc).
-template <int D>
+// holds pieces of the current rounds of several codes (RoundDesc).  With
+// kCensus every piece also takes the census of its codewords below p.below.
+template <int D, bool kCensus>
 __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   extern __shared__ unsigned long long smem[];
   // Consecutive workgroups land on different XCDs (round robin).  Deal them
@@ -323,36 +346,52 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   const uint32_t nfull = sfull / kBlock;
   const uint32_t *blk = p.table + (k0 / kBlock) * (2 * D * kBlock);
   // Words evaluated per codeword in the full blocks: the smallest w whose
-  // cap admits the U this tile started with (D: no partial weights).
-  const int U0 = static_cast<int>(key >> 32);
+  // cap admits the U this tile started with (D: no partial weights).  A
+  // census raises that threshold to its own bound, so that every block that
+  // may hold a codeword below it is completed.
+  Census cs;
+  if constexpr (kCensus) cs.below = static_cast<uint32_t>(p.below);
+  const int U0 = kCensus ? max(static_cast<int>(key >> 32), p.below) : static_cast<int>(key >> 32);
   int W = D;
 #pragma unroll
   for (int w = D - 1; w >= 1; --w)
     if (U0 <= p.cap[w - 1]) W = w;
   uint32_t rec = 0;  // full blocks evaluated in full
   if (W == D) {
-    for (uint32_t i = 0; i < nfull; ++i, blk += 2 * D * kBlock) best = block_min<D>(ax, az, blk, best);
+    for (uint32_t i = 0; i < nfull; ++i, blk += 2 * D * kBlock) best = block_min<D, kCensus>(ax, az, blk, best, cs);
   } else {
     const int c = p.credit[W - 1];
     const uint32_t thr = U0 > c ? static_cast<uint32_t>(U0 - c) : 0u;
     if constexpr (D >= 2) {
-      if (W == 1) best = partial_blocks<D, 1>(ax, az, blk, nfull, best, thr, rec);
+      if (W == 1) best = partial_blocks<D, 1, kCensus>(ax, az, blk, nfull, best, thr, rec, cs);
     }
     if constexpr (D >= 3) {
-      if (W == 2) best = partial_blocks<D, 2>(ax, az, blk, nfull, best, thr, rec);
+      if (W == 2) best = partial_blocks<D, 2, kCensus>(ax, az, blk, nfull, best, thr, rec, cs);
     }
     if constexpr (D >= 4) {
-      if (W == 3) best = partial_blocks<D, 3>(ax, az, blk, nfull, best, thr, rec);
+      if (W == 3) best = partial_blocks<D, 3, kCensus>(ax, az, blk, nfull, best, thr, rec, cs);
     }
   }
   for (uint32_t i = nfull * kBlock; i < send; ++i) {
     const uint32_t w = weight_at<D>(p.table, k0 + i, ax, az);
-    if (i < span) best = min(best, w);
+    if (i < span) {
+      best = min(best, w);
+      if constexpr (kCensus) cs.add(w);
+    }
   }
   if (!active) best = 0xFFFFFFFFu;
   const uint32_t wmin = wave_min(best);
   const uint32_t visited = wave_sum(active ? span : 0u);
   const unsigned long long nact = __popcll(__ballot(active));  // outside the lane-0 branch
+  if constexpr (kCensus) {
+    // Per lane at most seg entries of weight <= 128: the wave sums fit 32 bits.
+    const uint32_t ccnt = wave_sum(active ? cs.cnt : 0u);
+    const uint32_t csum = wave_sum(active ? cs.sum : 0u);
+    if (lane == 0 && p.census) {
+      atomicAdd(p.census, static_cast<unsigned long long>(ccnt));
+      atomicAdd(p.census + 1, static_cast<unsigned long long>(csum));
+    }
+  }
   if (lane == 0) {
     // Words: D per visited codeword, less D - W for those of the full
     // blocks that the partial weights decided.
@@ -434,15 +473,19 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
 
 // -- launch (host) -------------------------------------------------------------
 
-hipError_t launch_round(int D, const LaunchParams &lp, hipStream_t s) {
+hipError_t launch_round(int D, const LaunchParams &lp, bool census, hipStream_t s) {
   unsigned long long wgs = lp.tiles / kWavesPerGroup;
   wgs = (wgs + 8 * kXcdChunk - 1) / (8 * kXcdChunk) * (8 * kXcdChunk);  // the XCD dealing is a bijection
   dim3 grid(static_cast<uint32_t>(wgs)), block(kWave * kWavesPerGroup);
-  switch (D) {
-    case 1: hipLaunchKernelGGL(qd_round_kernel<1>, grid, block, lp.lds, s, lp); break;
-    case 2: hipLaunchKernelGGL(qd_round_kernel<2>, grid, block, lp.lds, s, lp); break;
-    case 3: hipLaunchKernelGGL(qd_round_kernel<3>, grid, block, lp.lds, s, lp); break;
-    case 4: hipLaunchKernelGGL(qd_round_kernel<4>, grid, block, lp.lds, s, lp); break;
+  switch (D * 2 + (census ? 1 : 0)) {
+    case 2: hipLaunchKernelGGL((qd_round_kernel<1, false>), grid, block, lp.lds, s, lp); break;
+    case 3: hipLaunchKernelGGL((qd_round_kernel<1, true>), grid, block, lp.lds, s, lp); break;
+    case 4: hipLaunchKernelGGL((qd_round_kernel<2, false>), grid, block, lp.lds, s, lp); break;
+    case 5: hipLaunchKernelGGL((qd_round_kernel<2, true>), grid, block, lp.lds, s, lp); break;
+    case 6: hipLaunchKernelGGL((qd_round_kernel<3, false>), grid, block, lp.lds, s, lp); break;
+    case 7: hipLaunchKernelGGL((qd_round_kernel<3, true>), grid, block, lp.lds, s, lp); break;
+    case 8: hipLaunchKernelGGL((qd_round_kernel<4, false>), grid, block, lp.lds, s, lp); break;
+    case 9: hipLaunchKernelGGL((qd_round_kernel<4, true>), grid, block, lp.lds, s, lp); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

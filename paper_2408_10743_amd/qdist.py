@@ -125,6 +125,9 @@ _lib.qd_plan.argtypes = [_u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.
                          ctypes.POINTER(qd_plan_info)]
 _lib.qd_round_min.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _u8p,
                               ctypes.POINTER(ctypes.c_ulonglong), ctypes.c_int]
+_lib.qd_round_census.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 _ip, _u8p, ctypes.POINTER(ctypes.c_ulonglong), ctypes.POINTER(ctypes.c_ulonglong),
+                                 ctypes.POINTER(ctypes.c_ulonglong)]
 _lib.qd_round_walk.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _u8p,
                                ctypes.POINTER(ctypes.c_ulonglong), ctypes.POINTER(ctypes.c_ulonglong)]
 _lib.qd_device_check.argtypes = [ctypes.c_char_p, ctypes.c_int]
@@ -265,6 +268,22 @@ def qd_round_min(rows, dims, t, partial_words=0):
     return st, w.value, wit, cnt.value
 
 
+def qd_round_census(rows, dims, t, below, partial_words=0):
+    """One GPU enumeration round with a census: returns (status, wmin,
+    witness, count, below_count, below_weight_sum)."""
+    rows = np.ascontiguousarray(rows, dtype=np.uint8)
+    dims = np.ascontiguousarray(dims, dtype=np.int32)
+    P = dims.shape[0]
+    n = rows.shape[1] // 2
+    w = ctypes.c_int(0)
+    cnt, bc, bs = ctypes.c_ulonglong(0), ctypes.c_ulonglong(0), ctypes.c_ulonglong(0)
+    wit = np.zeros(2 * n, dtype=np.uint8)
+    st = _lib.qd_round_census(rows.ctypes.data_as(_u8p), dims.ctypes.data_as(_ip), P, n, t, partial_words, below,
+                              ctypes.byref(w), wit.ctypes.data_as(_u8p), ctypes.byref(cnt), ctypes.byref(bc),
+                              ctypes.byref(bs))
+    return st, w.value, wit, cnt.value, bc.value, bs.value
+
+
 def qd_round_walk(rows, dims, t, per_lane=1, weight_sum=False):
     """One round with the plain walk kernel: returns (status, wmin, witness,
     count, weight sum or None)."""
@@ -337,5 +356,5 @@ def qd_engine_destroy(engine):
 def exported_symbols():
     """Names of the C ABI entry points declared in include/qdist.h."""
     return ["qd_distance", "qd_distance_ex", "qd_distance_batch", "qd_distance_batch_ex", "qd_plan",
-            "qd_round_min", "qd_round_walk", "qd_strerror", "qd_device_check", "qd_valu_peak", "qd_valu_mix", "qd_engine_create",
+            "qd_round_min", "qd_round_census", "qd_round_walk", "qd_strerror", "qd_device_check", "qd_valu_peak", "qd_valu_mix", "qd_engine_create",
             "qd_engine_submit", "qd_engine_poll", "qd_engine_outstanding", "qd_engine_destroy"]

@@ -91,9 +91,11 @@ def test_sweep_larger_codes_against_oracle_bz(Q):
     """Codes beyond brute force (additive, 22..30 rows and up to 120 qubits;
     F4-linear with k = 11..15), against the oracle's BZ, which the CPU tests
     pin to brute force: the automatic plan, F2, the isometry, the plain
-    walk, 64-entry tiles and every word evaluated."""
+    walk, 64-entry tiles, every word evaluated (partial_weight -1) and
+    partial weights forced on every code with two or more words per half
+    (partial_weight 1)."""
     paths = [{}, {"diag": Q.QD_DIAG_F2}, {"diag": Q.QD_DIAG_ISO}, {"walk": 1}, {"seg_len": 64},
-             {"partial_weight": 0}]
+             {"partial_weight": -1}, {"partial_weight": 1}]
     checked = 0
     for s in range(60):
         rng = W.SplitMix64(W.config_seed(92, s))
