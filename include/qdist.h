@@ -270,6 +270,28 @@ int qd_round_census(const uint8_t *rows, const int *dims, int P, int n, int t, i
                     int below, int *wmin, uint8_t *witness, unsigned long long *count,
                     unsigned long long *below_count, unsigned long long *below_weight_sum);
 
+/* Device bytes of the fixed array qd_round_min_noalloc works in (per GPU). */
+#define QD_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * qd_round_min with every device buffer it needs (elements, e_r tables,
+ * saved and tops tables, tile plans, state, counters, witness slots) carved
+ * from one fixed device array of QD_NOALLOC_SCRATCH_BYTES that each GPU
+ * holds from the first call until the process ends.  It calls no hipMalloc,
+ * hipFree, hipHostMalloc, stream or event creation; inputs are read from
+ * host memory and uploaded from pageable memory.  Tables are kept to a
+ * quarter of the array (shallower saved tables, unranked tops); a round
+ * whose plan still does not fit returns QD_ERR_TOO_LARGE with no result
+ * (its planning step fails before it uploads or launches).  stream: the HIP stream to run on (NULL: the null stream); the call
+ * returns after the stream has finished its work.  Calls on one GPU share
+ * its array and run one at a time within a process (they serialize on a
+ * lock); every call re-initializes what it reads.  Outputs, partial_words
+ * and errors as qd_round_min; QD_ERR_DEVICE without a gfx950 device. */
+int qd_round_min_noalloc(const uint8_t *rows, const int *dims, int P, int n, int t, int *wmin,
+                         uint8_t *witness, unsigned long long *count, int partial_words,
+                         void *stream);
+
 /* The same round with the plain walk kernel (qd_options.walk = per_lane:
  * package sets per lane, 1..4096, 1 choosing from the round size; others
  * QD_ERR_INVALID; t > 8 is QD_ERR_TOO_LARGE): minimum symplectic weight,

@@ -107,6 +107,71 @@ int time_probe(F launch, double ops_per_iter, double *lane_ops_per_s) {
 }
 }  // namespace
 
+namespace qd {
+
+// One round over a caller-given package layout (qd_round_min,
+// qd_round_census, qd_round_walk, qd_round_min_noalloc) on `arena_ex`, or on
+// the device's default executor when it is NULL.
+int one_round(const uint8_t *rows, const int *dims, int P, int n, int t, int partial_words, int walk, int *wmin,
+              uint8_t *witness, unsigned long long *count, unsigned long long *weight_sum, int below,
+              unsigned long long *census, Executor *arena_ex) {
+  if (!rows || !dims || !wmin || !count || P <= 0 || P > 2 * kMaxN || t < 1 || n <= 0) return QD_ERR_INVALID;
+  if (n > kMaxN) return QD_ERR_TOO_LARGE;
+  if (partial_words < 0 || (partial_words > 0 && partial_words >= (n + 31) / 32)) return QD_ERR_INVALID;
+  if (walk < 0 || walk > 4096) return QD_ERR_INVALID;
+  Job job;
+  job.n = n;
+  job.single_round = true;
+  job.t = t;
+  job.opt.partial_weight = -1;
+  job.opt.walk = walk;
+  job.want_wsum = weight_sum != nullptr;
+  job.force_words = partial_words;
+  job.census_below = census ? std::min(below, n + 2) : 0;
+  Gamma g;
+  for (int i = 0; i < P; ++i) {
+    if (dims[i] != 1 && dims[i] != 2) return QD_ERR_INVALID;
+    Package pk;
+    pk.dim = dims[i];
+    pk.pivot = -1;
+    std::vector<BRow> two;
+    const int rc = load_rows(rows + size_t(2 * i) * 2 * n, 2, n, QD_FIELD_F2, two);
+    if (rc) return rc;
+    pk.r = two[0];
+    if (pk.dim == 2) pk.s = two[1];
+    g.pk.push_back(pk);
+  }
+  *wmin = n + 1;
+  *count = 0;
+  if (weight_sum) *weight_sum = 0;
+  if (census) census[0] = census[1] = 0;
+  if (t > P) return QD_OK;
+  if (t > kTMax || (walk > 0 && t > kWalkMaxT)) return QD_ERR_TOO_LARGE;
+  job.use.push_back(g);
+  Executor::prepare_gammas(job);
+  if (job.gd[0].prefix[size_t(P) * job.gd[0].R + t] >= kSat) return QD_ERR_TOO_LARGE;
+  Executor *ex = arena_ex;
+  std::unique_lock<std::mutex> lk;
+  if (!ex) {
+    const int rc = default_executor(&ex, &lk);
+    if (rc) return rc;
+  }
+  std::vector<Job *> v{&job};
+  run_jobs(*ex, v, ex->stream());
+  if (job.status < 0) return job.status == QD_ERR_NOMEM && arena_ex ? QD_ERR_TOO_LARGE : job.status;
+  *wmin = job.U;
+  *count = job.visited;
+  if (weight_sum) *weight_sum = job.wsum;
+  if (census) {
+    census[0] = job.census[0];
+    census[1] = job.census[1];
+  }
+  if (witness && job.U <= n) unpack(job.wit, n, witness);
+  return QD_OK;
+}
+
+}  // namespace qd
+
 extern "C" {
 
 int qd_distance_ex(const uint8_t *G, int m, int n, int field, const qd_options *opt, int *d, uint8_t *witness,
@@ -219,70 +284,10 @@ int qd_plan(const uint8_t *G, int m, int n, int field, int diag, int max_gamma, 
   return QD_OK;
 }
 
-namespace {
-
-// One round over a caller-given package layout (qd_round_min, qd_round_walk).
-int one_round(const uint8_t *rows, const int *dims, int P, int n, int t, int partial_words, int walk, int *wmin,
-              uint8_t *witness, unsigned long long *count, unsigned long long *weight_sum, int below = 0,
-              unsigned long long *census = nullptr) {
-  if (!rows || !dims || !wmin || !count || P <= 0 || P > 2 * kMaxN || t < 1 || n <= 0) return QD_ERR_INVALID;
-  if (n > kMaxN) return QD_ERR_TOO_LARGE;
-  if (partial_words < 0 || (partial_words > 0 && partial_words >= (n + 31) / 32)) return QD_ERR_INVALID;
-  if (walk < 0 || walk > 4096) return QD_ERR_INVALID;
-  Job job;
-  job.n = n;
-  job.single_round = true;
-  job.t = t;
-  job.opt.partial_weight = -1;
-  job.opt.walk = walk;
-  job.want_wsum = weight_sum != nullptr;
-  job.force_words = partial_words;
-  job.census_below = census ? std::min(below, n + 2) : 0;
-  Gamma g;
-  for (int i = 0; i < P; ++i) {
-    if (dims[i] != 1 && dims[i] != 2) return QD_ERR_INVALID;
-    Package pk;
-    pk.dim = dims[i];
-    pk.pivot = -1;
-    std::vector<BRow> two;
-    const int rc = load_rows(rows + size_t(2 * i) * 2 * n, 2, n, QD_FIELD_F2, two);
-    if (rc) return rc;
-    pk.r = two[0];
-    if (pk.dim == 2) pk.s = two[1];
-    g.pk.push_back(pk);
-  }
-  *wmin = n + 1;
-  *count = 0;
-  if (weight_sum) *weight_sum = 0;
-  if (census) census[0] = census[1] = 0;
-  if (t > P) return QD_OK;
-  if (t > kTMax || (walk > 0 && t > kWalkMaxT)) return QD_ERR_TOO_LARGE;
-  job.use.push_back(g);
-  Executor::prepare_gammas(job);
-  if (job.gd[0].prefix[size_t(P) * job.gd[0].R + t] >= kSat) return QD_ERR_TOO_LARGE;
-  Executor *ex = nullptr;
-  std::unique_lock<std::mutex> lk;
-  int rc = default_executor(&ex, &lk);
-  if (rc) return rc;
-  std::vector<Job *> v{&job};
-  run_jobs(*ex, v, ex->stream());
-  if (job.status < 0) return job.status;
-  *wmin = job.U;
-  *count = job.visited;
-  if (weight_sum) *weight_sum = job.wsum;
-  if (census) {
-    census[0] = job.census[0];
-    census[1] = job.census[1];
-  }
-  if (witness && job.U <= n) unpack(job.wit, n, witness);
-  return QD_OK;
-}
-
-}  // namespace
 
 int qd_round_min(const uint8_t *rows, const int *dims, int P, int n, int t, int *wmin, uint8_t *witness,
                  unsigned long long *count, int partial_words) {
-  return one_round(rows, dims, P, n, t, partial_words, 0, wmin, witness, count, nullptr);
+  return one_round(rows, dims, P, n, t, partial_words, 0, wmin, witness, count, nullptr, 0, nullptr, nullptr);
 }
 
 int qd_round_census(const uint8_t *rows, const int *dims, int P, int n, int t, int partial_words, int below,
@@ -290,7 +295,7 @@ int qd_round_census(const uint8_t *rows, const int *dims, int P, int n, int t, i
                     unsigned long long *below_weight_sum) {
   if (below < 1 || !below_count || !below_weight_sum) return QD_ERR_INVALID;
   unsigned long long c[2] = {0, 0};
-  const int rc = one_round(rows, dims, P, n, t, partial_words, 0, wmin, witness, count, nullptr, below, c);
+  const int rc = one_round(rows, dims, P, n, t, partial_words, 0, wmin, witness, count, nullptr, below, c, nullptr);
   *below_count = c[0];
   *below_weight_sum = c[1];
   return rc;
@@ -299,7 +304,7 @@ int qd_round_census(const uint8_t *rows, const int *dims, int P, int n, int t, i
 int qd_round_walk(const uint8_t *rows, const int *dims, int P, int n, int t, int per_lane, int *wmin,
                   uint8_t *witness, unsigned long long *count, unsigned long long *weight_sum) {
   if (per_lane < 1) return QD_ERR_INVALID;
-  return one_round(rows, dims, P, n, t, 0, per_lane, wmin, witness, count, weight_sum);
+  return one_round(rows, dims, P, n, t, 0, per_lane, wmin, witness, count, weight_sum, 0, nullptr, nullptr);
 }
 
 const char *qd_strerror(int status) {

@@ -101,9 +101,9 @@ bool in_span(const std::vector<BRow> &basis, int n, const BRow &v) {
 
 // Saved-table depth for round t: u = t-2, so every top keeps two packages
 // (a group then fills many lanes), within the cap and the table-size limit.
-int saved_depth(const GammaDev &g, int D, int t, int cap) {
+int saved_depth(const GammaDev &g, int D, int t, int cap, unsigned long long max_bytes) {
   int u = std::min(std::max(t - 2, 0), cap);
-  while (u > 0 && g.prefix[size_t(g.P) * g.R + u] * 8ull * D > kMaxTableBytes) --u;
+  while (u > 0 && g.prefix[size_t(g.P) * g.R + u] * 8ull * D > max_bytes) --u;
   return u;
 }
 
@@ -181,6 +181,14 @@ DevPool::~DevPool() {
 // blocks), so a batch of small codes costs few hipMalloc calls; larger
 // classes are allocations of their own.
 void *DevPool::get(size_t bytes, size_t *cls) {
+  if (arena_) {
+    const size_t c = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+    if (c > arena_cap_ - arena_off_) return nullptr;
+    void *p = arena_ + arena_off_;
+    arena_off_ += c;
+    *cls = c;
+    return p;
+  }
   const size_t c = size_class(std::max<size_t>(bytes, 1));
   auto &v = free_[c];
   if (v.empty()) {
@@ -215,13 +223,14 @@ void *DevPool::get(size_t bytes, size_t *cls) {
 }
 
 void DevPool::put(void *p, size_t cls) {
-  if (p) free_[cls].push_back(p);
+  if (p && !arena_) free_[cls].push_back(p);
 }
 
 // -- Staging -------------------------------------------------------------------
 
 Staging::~Staging() {
-  if (p_) (void)hipHostFree(p_);
+  if (p_ && pageable_) std::free(p_);
+  else if (p_) (void)hipHostFree(p_);
 }
 
 size_t Staging::put(const void *src, size_t bytes) {
@@ -229,9 +238,15 @@ size_t Staging::put(const void *src, size_t bytes) {
   if (end > cap_) {
     size_t cap = std::max<size_t>(cap_ ? 2 * cap_ : size_t(1) << 20, end);
     unsigned char *q = nullptr;
-    if (hipHostMalloc(reinterpret_cast<void **>(&q), cap, hipHostMallocDefault) != hipSuccess) return SIZE_MAX;
+    if (pageable_) {
+      q = static_cast<unsigned char *>(std::malloc(cap));
+      if (!q) return SIZE_MAX;
+    } else if (hipHostMalloc(reinterpret_cast<void **>(&q), cap, hipHostMallocDefault) != hipSuccess) {
+      return SIZE_MAX;
+    }
     if (n_) std::memcpy(q, p_, n_);
-    if (p_) (void)hipHostFree(p_);
+    if (p_ && pageable_) std::free(p_);
+    else if (p_) (void)hipHostFree(p_);
     p_ = q;
     cap_ = cap;
   }
@@ -244,7 +259,21 @@ size_t Staging::put(const void *src, size_t bytes) {
 
 // -- Executor ------------------------------------------------------------------
 
-Executor::Executor(hipStream_t stream) : spec_combos_(kSpecCombos), long_seg_(kMinSeg) {
+Executor::Executor(hipStream_t stream, void *arena, size_t bytes)
+    : spec_combos_(kSpecCombos), long_seg_(kMinSeg), stream_(stream), max_table_bytes_(bytes / 4) {
+  if (!arena) return;  // the caller has checked the device (a gfx950 holding the arena)
+  pool_.set_arena(arena, bytes);
+  staging_.set_pageable();
+  // The arena keeps the last call's contents: the zero table is cleared here.
+  const size_t zb = size_t(2) * 4 * kBlock * sizeof(uint32_t);
+  size_t cls = 0;
+  zero_table_ = static_cast<uint32_t *>(pool_.get(zb, &cls));
+  if (!zero_table_ || hipMemsetAsync(zero_table_, 0, zb, stream_) != hipSuccess) return;
+  ok_ = grow_states(64) == QD_OK;
+}
+
+Executor::Executor(hipStream_t stream)
+    : spec_combos_(kSpecCombos), long_seg_(kMinSeg), max_table_bytes_(kMaxTableBytes) {
   int dev = 0, cnt = 0;
   hipDeviceProp_t prop;
   if (hipGetDeviceCount(&cnt) != hipSuccess || cnt <= 0 || hipGetDevice(&dev) != hipSuccess ||
@@ -264,9 +293,11 @@ Executor::Executor(hipStream_t stream) : spec_combos_(kSpecCombos), long_seg_(kM
 }
 
 Executor::~Executor() {
-  if (zero_table_) (void)hipFree(zero_table_);
-  if (states_) (void)hipFree(states_);
-  if (hstates_) (void)hipHostFree(hstates_);
+  if (!pool_.arena()) {
+    if (zero_table_) (void)hipFree(zero_table_);
+    if (states_) (void)hipFree(states_);
+    if (hstates_) (void)hipHostFree(hstates_);
+  }
   for (hipEvent_t e : events_) (void)hipEventDestroy(e);
   if (own_stream_) (void)hipStreamDestroy(stream_);
 }
@@ -291,6 +322,16 @@ int Executor::grow_states(int need) {
   if (nstates_ >= need) return QD_OK;
   const int cap = std::max(need, 2 * nstates_);
   DevState *d = nullptr, *h = nullptr;
+  if (pool_.arena()) {  // fixed at construction: one state array in the arena
+    size_t cls = 0;
+    if (states_ || !(d = static_cast<DevState *>(pool_.get(sizeof(DevState) * cap, &cls)))) return QD_ERR_NOMEM;
+    host_states_.assign(size_t(cap), DevState{});
+    for (int i = cap - 1; i >= 0; --i) free_slots_.push_back(i);
+    states_ = d;
+    hstates_ = host_states_.data();
+    nstates_ = cap;
+    return QD_OK;
+  }
   if (hipMalloc(reinterpret_cast<void **>(&d), sizeof(DevState) * cap) != hipSuccess) return QD_ERR_NOMEM;
   if (hipHostMalloc(reinterpret_cast<void **>(&h), sizeof(DevState) * cap, hipHostMallocDefault) != hipSuccess) {
     (void)hipFree(d);
@@ -811,10 +852,11 @@ int Executor::schedule(Job &job, int sharing) {
     // reaches it.
     f.L_before = job.single_round ? -1 : lower_bound(tsim, job.delta, job.halve);
     const int cap = job.opt.saved_depth < 0 ? 0 : job.opt.saved_depth ? job.opt.saved_depth : kDefaultSavedDepth;
-    f.u = saved_depth(g, job.D, t, cap);
+    f.u = saved_depth(g, job.D, t, cap, max_table_bytes_);
     f.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : choose_seg(planned, sharing, long_seg_);
     const int tm = job.opt.tops_mode;
-    f.use_tops = tm == 1 || (tm == 0 && g.suffix[t - f.u] <= kMaxTopEntries);
+    const unsigned long long max_tops = std::min(kMaxTopEntries, max_table_bytes_ / (kElemWords * 4));
+    f.use_tops = tm == 1 || (tm == 0 && g.suffix[t - f.u] <= max_tops);
     if (planned <= kTinyRound && job.opt.saved_depth == 0 && tm == 0) {
       f.u = 0;
       f.use_tops = false;
@@ -1017,11 +1059,15 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   const unsigned char *base = nullptr;
   size_t desc_off = 0;
   const double ts_desc = trace ? now_ms() : 0.0;
+  // The witness slots first: a step that cannot get them fails before it
+  // uploads or builds anything.
+  if (!launches.empty() && !alloc(slots_, size_t(max_tiles) * kElemWords * 4)) return QD_ERR_NOMEM;
   if (const int rc = flush(s, &base, &desc_off)) return rc;
   const double ts_flush = trace ? now_ms() : 0.0;
   if (!launches.empty()) {
-    if (!alloc(slots_, size_t(max_tiles) * kElemWords * 4)) return QD_ERR_NOMEM;
-    while (events_.size() < 2 * launches.size()) {
+    bool any_timed = false;  // events are created only for timed launches
+    for (const Launch &L : launches) any_timed = any_timed || L.timed;
+    while (any_timed && events_.size() < 2 * launches.size()) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return QD_ERR_DEVICE;
       events_.push_back(e);

@@ -32,8 +32,19 @@ class DevPool {
   size_t held() const { return held_; }
   int mallocs() const { return mallocs_; }
   double malloc_ms() const { return malloc_ms_; }
+  // Arena mode: blocks are carved in order from [base, base + cap), which
+  // the caller owns, and are never given back (put is a no-op); nothing is
+  // allocated from the driver.  get returns nullptr once the arena is full.
+  void set_arena(void *base, size_t cap) {
+    arena_ = static_cast<unsigned char *>(base);
+    arena_cap_ = cap;
+    arena_off_ = 0;
+  }
+  bool arena() const { return arena_ != nullptr; }
 
  private:
+  unsigned char *arena_ = nullptr;
+  size_t arena_cap_ = 0, arena_off_ = 0;
   int mallocs_ = 0;
   double malloc_ms_ = 0.0;
   std::map<size_t, std::vector<void *>> free_;
@@ -81,10 +92,13 @@ class Staging {
   size_t size() const { return n_; }
   const unsigned char *data() const { return p_; }
   void clear() { n_ = 0; }
+  // Ordinary (pageable) host memory instead of pinned memory.
+  void set_pageable() { pageable_ = true; }
 
  private:
   unsigned char *p_ = nullptr;
   size_t n_ = 0, cap_ = 0;
+  bool pageable_ = false;
 };
 
 // One scheduled (t, Gamma_j) round of a code and its tile plan.
@@ -158,7 +172,15 @@ struct Job {
 class Executor {
  public:
   explicit Executor(hipStream_t stream = nullptr);
+  // Arena executor: all device memory is carved from [arena, arena + bytes)
+  // (the caller's), uploads go through pageable host memory, no stream or
+  // event is created (stream may be the null stream) and nothing is
+  // allocated from the driver; a request that does not fit fails with
+  // QD_ERR_NOMEM from its step.  The caller checks the device: a gfx950
+  // that holds the arena.
+  Executor(hipStream_t stream, void *arena, size_t bytes);
   ~Executor();
+  bool arena() const { return pool_.arena(); }
   bool ok() const { return ok_; }
   hipStream_t stream() const { return stream_; }
   size_t device_bytes() const { return pool_.held(); }
@@ -202,9 +224,14 @@ class Executor {
   bool own_stream_ = false;
   hipStream_t stream_ = nullptr;
   DevPool pool_;
-  // per-code states (device) and their pinned host mirror
+  // per-code states (device) and their pinned host mirror (arena executor:
+  // ordinary host memory, host_states_)
   DevState *states_ = nullptr;
   DevState *hstates_ = nullptr;
+  std::vector<DevState> host_states_;
+  // Saved and tops tables of at most this many bytes (arena executor: a
+  // quarter of the arena)
+  unsigned long long max_table_bytes_;
   int nstates_ = 0;
   std::vector<int> free_slots_;
   std::vector<int> dirty_slots_;  // states to upload at the next flush
@@ -233,5 +260,14 @@ int default_executor(Executor **ex, std::unique_lock<std::mutex> *lock);
 
 // Runs a set of prepared jobs to completion on one executor.
 int run_jobs(Executor &ex, std::vector<Job *> &jobs, hipStream_t s);
+
+// One round over a caller-given package layout (rows: 2P rows of 2n bytes,
+// dims 1 or 2 per package): the body of qd_round_min, qd_round_census,
+// qd_round_walk and qd_round_min_noalloc.  Runs on `arena_ex` (an arena
+// executor; QD_ERR_TOO_LARGE when the round does not fit its arena) or, when
+// it is NULL, on the current device's default executor.
+int one_round(const uint8_t *rows, const int *dims, int P, int n, int t, int partial_words, int walk, int *wmin,
+              uint8_t *witness, unsigned long long *count, unsigned long long *weight_sum, int below,
+              unsigned long long *census, Executor *arena_ex);
 
 }  // namespace qd

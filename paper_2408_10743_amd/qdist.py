@@ -22,6 +22,7 @@ QD_OK, QD_INCOMPLETE = 0, 1
 QD_ERR_INVALID, QD_ERR_ZERO_CODE, QD_ERR_TOO_LARGE = -1, -2, -3
 QD_ERR_NOMEM, QD_ERR_DEVICE, QD_ERR_INTERNAL = -4, -5, -6
 QD_MAX_N, QD_MAX_GAMMA, QD_MAX_LOG = 128, 8, 96
+QD_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libqdist.so not found at {LIB_PATH}; build it with __graft_entry__.build()")
@@ -128,6 +129,8 @@ _lib.qd_round_min.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_in
 _lib.qd_round_census.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  _ip, _u8p, ctypes.POINTER(ctypes.c_ulonglong), ctypes.POINTER(ctypes.c_ulonglong),
                                  ctypes.POINTER(ctypes.c_ulonglong)]
+_lib.qd_round_min_noalloc.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _u8p,
+                                      ctypes.POINTER(ctypes.c_ulonglong), ctypes.c_int, ctypes.c_void_p]
 _lib.qd_round_walk.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _u8p,
                                ctypes.POINTER(ctypes.c_ulonglong), ctypes.POINTER(ctypes.c_ulonglong)]
 _lib.qd_device_check.argtypes = [ctypes.c_char_p, ctypes.c_int]
@@ -268,6 +271,21 @@ def qd_round_min(rows, dims, t, partial_words=0):
     return st, w.value, wit, cnt.value
 
 
+def qd_round_min_noalloc(rows, dims, t, partial_words=0, stream=None):
+    """qd_round_min on the library's fixed device array (no device
+    allocation): returns (status, wmin, witness, count)."""
+    rows = np.ascontiguousarray(rows, dtype=np.uint8)
+    dims = np.ascontiguousarray(dims, dtype=np.int32)
+    P = dims.shape[0]
+    n = rows.shape[1] // 2
+    w = ctypes.c_int(0)
+    cnt = ctypes.c_ulonglong(0)
+    wit = np.zeros(2 * n, dtype=np.uint8)
+    st = _lib.qd_round_min_noalloc(rows.ctypes.data_as(_u8p), dims.ctypes.data_as(_ip), P, n, t, ctypes.byref(w),
+                                   wit.ctypes.data_as(_u8p), ctypes.byref(cnt), partial_words, stream)
+    return st, w.value, wit, cnt.value
+
+
 def qd_round_census(rows, dims, t, below, partial_words=0):
     """One GPU enumeration round with a census: returns (status, wmin,
     witness, count, below_count, below_weight_sum)."""
@@ -356,5 +374,5 @@ def qd_engine_destroy(engine):
 def exported_symbols():
     """Names of the C ABI entry points declared in include/qdist.h."""
     return ["qd_distance", "qd_distance_ex", "qd_distance_batch", "qd_distance_batch_ex", "qd_plan",
-            "qd_round_min", "qd_round_census", "qd_round_walk", "qd_strerror", "qd_device_check", "qd_valu_peak", "qd_valu_mix", "qd_engine_create",
+            "qd_round_min", "qd_round_census", "qd_round_min_noalloc", "qd_round_walk", "qd_strerror", "qd_device_check", "qd_valu_peak", "qd_valu_mix", "qd_engine_create",
             "qd_engine_submit", "qd_engine_poll", "qd_engine_outstanding", "qd_engine_destroy"]

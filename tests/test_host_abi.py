@@ -109,6 +109,7 @@ def test_no_cpu_fallback_without_gpu(Q):
     st, w, _, _ = Q.qd_round_min(*W.random_packages(3, 8, 1), 1)
     assert st == Q.QD_ERR_DEVICE
     assert Q.qd_round_census(*W.random_packages(3, 8, 1), 1, 5)[0] == Q.QD_ERR_DEVICE
+    assert Q.qd_round_min_noalloc(*W.random_packages(3, 8, 1), 1)[0] == Q.QD_ERR_DEVICE
 
 
 def test_engine_needs_gpu(Q):
