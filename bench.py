@@ -47,7 +47,7 @@ PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # scaled by what it reads for a 1 GiB device copy in the same runs), valid
 # only for the kernel source with this fingerprint (sha256 prefixes of
 # round.hip and kernels.hpp, the enumeration kernel and its data layouts).
-TRAFFIC = {"fingerprint": None, "bytes_per_launch": None}
+TRAFFIC = {"fingerprint": "aae15a77db169ddda38cd37dcef04b3b", "bytes_per_launch": 1210947289}
 
 
 def kernel_fingerprint():
@@ -93,6 +93,9 @@ def parse():
                     help="only time the VALU instruction mixes of qd_valu_mix and print their rates")
     ap.add_argument("--default-only", action="store_true",
                     help="only run the default-path steps on the main code (partial weights), for a profiler")
+    ap.add_argument("--every-word-only", action="store_true",
+                    help="only run the timed steps on the main code (every word evaluated) and print their "
+                         "rate and roofline, for a profiler")
     ap.add_argument("--walk-only", action="store_true",
                     help="only run the plain per-round walk on the same code (--steps timed calls after "
                          "one warm-up call), for a profiler")
@@ -553,6 +556,25 @@ def main():
         wall, stats = run(a.steps)
         print(json.dumps({"default_path_ms_per_step": wall * 1e3 / a.steps}))
         return
+    def copy_calibration():
+        """Three device copies of 1 GiB: the reference for HBM byte counters."""
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        return src.numel() * 4
+
+    if a.every_word_only:
+        run(a.warmup, partial_weight=-1)
+        wall, stats = run(a.steps, partial_weight=-1)
+        roof = kernel_roofline([s for _, s in stats], sum(s.launches for _, s in stats))
+        out = {"ms_per_step": wall * 1e3 / a.steps,
+               "codewords_per_s": sum(s.combinations for _, s in stats) / wall, "roofline": roof}
+        if a.copy_calibration:
+            out["copy_calibration_bytes"] = copy_calibration()
+        print(json.dumps(out))
+        return
 
     # The step: every word of every codeword evaluated (partial_weight -1).
     run(a.warmup, partial_weight=-1)
@@ -609,12 +631,7 @@ def main():
         "device": name,
     }
     if a.copy_calibration:
-        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = src.numel() * 4
+        out["copy_calibration_bytes"] = copy_calibration()
     if not a.no_extra:
         out["plain_per_code"] = leg_walk(Q, G, field, stream.cuda_stream, ttd_ms, 3)
         out["plain_per_code"]["engine_every_word_speedup"] = out["plain_per_code"]["ms_per_step"] / out["ms_per_step"]
