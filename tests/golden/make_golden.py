@@ -1,5 +1,7 @@
 """Writes oracle_distances.json: distances of the stand-in workloads computed
-by the CPU oracle only (its Brouwer-Zimmermann over the F4 construction).
+by the CPU oracle only (its Brouwer-Zimmermann over the F4 construction),
+and for config 3 the oracle's round-by-round trace (the combinations its
+BZ enumerates to reach the exact distance).
 Run from the repository root:
     python tests/golden/make_golden.py [config2] [config3] [config4]
 With no argument every part is (re)computed; with arguments only those
@@ -39,11 +41,14 @@ def part_config2(out):
 
 def part_config3(out):
     out["config3"] = []
+    out["config3_oracle_rounds"] = []
     for i in range(5):
         t0 = time.time()
         G, f = W.config3(i)
         d, _, log = O.bz(O.expand(G, f), O.DIAG_F4, 2)
         out["config3"].append(d)
+        # the oracle's BZ trace: (t, j, L, U, combinations) after each round
+        out["config3_oracle_rounds"].append([list(r) for r in log])
         print("config3", i, d, f"{time.time() - t0:.1f}s", log[-1], flush=True)
 
 

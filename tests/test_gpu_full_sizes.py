@@ -112,6 +112,82 @@ def test_config5_engine_mix(Q):
         assert swt(w) == d and O.in_rowspace(O.expand(G, f), w)
 
 
+def test_config3_golden_seeds(Q):
+    """Config 3 seeds 0-4 against the oracle's BZ distances, on the default
+    path (partial weights, mixed packages allowed) and with every word
+    evaluated and two-row packages first (the paper's construction)."""
+    assert len(GOLD["config3"]) == 5
+    for i, d_ref in enumerate(GOLD["config3"]):
+        G, f = W.config3(i)
+        B = O.expand(G, f)
+        for opts in ({}, {"partial_weight": -1, "mixed_packages": -1}):
+            print(f"config3 seed {i} d={d_ref} {opts}", flush=True)
+            st, d, w, s = Q.qd_distance_ex(G, f, **opts)
+            assert st == 0 and d == d_ref, (i, opts, st, d)
+            assert swt(w) == d and O.in_rowspace(B, w)
+            words_per_codeword = s.words / max(s.enumerated, 1)
+            if opts:
+                assert words_per_codeword == s.D
+            else:
+                assert words_per_codeword < 1.1  # the partial-weight path decided the rounds
+
+
+def test_config4_oracle_sample(Q):
+    """A fixed sample of the bench's config-4 codes, spread over predicted
+    work (1e4..1e11 combinations, both fields, n 28..80), against the
+    oracle's BZ distances: the default path (partial weights on the codes
+    planned at >= 1e8 combinations, capped two-row packages where the
+    planner caps them) and every word evaluated with two-row packages
+    first."""
+    rows = GOLD["config4_sample"]
+    pool = W.config4(800)  # draw i is the i-th code of the bench's draw sequence
+    assert len(rows) >= 24
+    big = capped = 0
+    for r in rows:
+        G, f = pool[r["index"]]
+        assert bench.predicted_work(Q, G, f) <= 1e11  # a member of the bench's batch
+        B = O.expand(G, f)
+        for opts in ({}, {"partial_weight": -1, "mixed_packages": -1}):
+            print(f"config4 draw {r['index']} n={r['n']} field={f} d={r['d']} {opts}", flush=True)
+            st, d, w, s = Q.qd_distance_ex(G, f, **opts)
+            assert st == 0 and d == r["d"], (r, opts, st, d)
+            assert swt(w) == d and O.in_rowspace(B, w)
+            if not opts:
+                if s.words < s.D * s.enumerated:
+                    big += 1
+                if any(c >= 0 for c in list(s.two_row_cap)[:s.h]):
+                    capped += 1
+    print(f"config4 sample: {len(rows)} codes, {big} on partial weights, {capped} with capped packages", flush=True)
+    assert big >= 8 and capped >= 4
+
+
+def test_config4_first_draws_bounds(Q):
+    """Config 4 as drawn (the first 512 draws, n up to 96, no work filter)
+    in one batch with the bench's per-code budget: every code ends exact or
+    QD_INCOMPLETE; exact codes carry a valid witness, incomplete ones
+    certified bounds L < U with a witness of weight U; the golden sample's
+    codes among these draws give the oracle's distance."""
+    codes = W.config4(512)
+    st, ds, wits, sts, stats = Q.qd_distance_batch(codes, budget=int(4e11))
+    assert st == 0
+    gold = {r["index"]: r["d"] for r in GOLD["config4_sample"]}
+    n_inc = 0
+    for i, ((G, f), d, w, x, s) in enumerate(zip(codes, ds, wits, sts, stats)):
+        assert x in (0, Q.QD_INCOMPLETE), (i, x)
+        B = O.expand(G, f)
+        assert swt(w) == d == s.U and O.in_rowspace(B, w), i
+        if x == 0:
+            assert s.L >= s.U
+            if i in gold:
+                assert d == gold[i], i
+        else:
+            n_inc += 1
+            assert s.L < s.U, i
+    ns = [G.shape[1] // 2 if f == 2 else G.shape[1] for G, f in codes]
+    print(f"config4 first draws: {len(codes) - n_inc} exact, {n_inc} incomplete, n {min(ns)}..{max(ns)}", flush=True)
+    assert max(ns) == 96
+
+
 def test_config3_full_size_bench_call(Q):
     """Config 3 exactly as bench.py times it (stream, timing on): the oracle's
     golden distance, and every completed round visited its planned count."""
