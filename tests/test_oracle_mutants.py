@@ -32,8 +32,10 @@ MUTANTS = {
     "alpha_times_row_wrong": ("ag[n + q] = (uint8_t)(a ^ b);", "ag[n + q] = (uint8_t)a;"),
     "weight_xor_not_or": ("w += __builtin_popcountll(c[i] | c[W + i]);", "w += __builtin_popcountll(c[i] ^ c[W + i]);"),
     "one_row_clearing_skipped": ("if (sv == sr || sv == (sr ^ beta))", "if (0)"),
-    "round_skips_last_package": ("for (int i = start; i <= c->P - (c->t - depth); ++i)",
-                                 "for (int i = start; i < c->P - (c->t - depth); ++i)"),
+    "round_skips_last_package": ("  for (int i = start; i <= c->P - (c->t - depth); ++i)\n    for (int e = 0; e < c->ne[i]; ++e) {\n      const uint64_t *x = c->el + (size_t)(i * 3 + e) * W2;\n      for (int k = 0; k < W2; ++k) nxt[k] = cur[k] ^ x[k];\n      round_rec",
+                                 "  for (int i = start; i < c->P - (c->t - depth); ++i)\n    for (int e = 0; e < c->ne[i]; ++e) {\n      const uint64_t *x = c->el + (size_t)(i * 3 + e) * W2;\n      for (int k = 0; k < W2; ++k) nxt[k] = cur[k] ^ x[k];\n      round_rec"),
+    "hist_skips_last_package": ("  for (int i = start; i <= c->P - (c->t - depth); ++i)\n    for (int e = 0; e < c->ne[i]; ++e) {\n      const uint64_t *x = c->el + (size_t)(i * 3 + e) * W2;\n      for (int k = 0; k < W2; ++k) nxt[k] = cur[k] ^ x[k];\n      hist_rec",
+                                "  for (int i = start; i < c->P - (c->t - depth); ++i)\n    for (int e = 0; e < c->ne[i]; ++e) {\n      const uint64_t *x = c->el + (size_t)(i * 3 + e) * W2;\n      for (int k = 0; k < W2; ++k) nxt[k] = cur[k] ^ x[k];\n      hist_rec"),
     "third_element_missing": ("      ne[i] = 3;", "      ne[i] = 2;"),
     "stop_one_early": ("if (L >= U || t == P[j]) finished = 1;", "if (L + 1 >= U || t == P[j]) finished = 1;"),
     "two_dim_clears_with_wrong_row": ("        } else if (sv == ss) {\n          row_add(R + (size_t)v * len, R + (size_t)s * len, len);",
