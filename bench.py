@@ -103,6 +103,8 @@ def parse():
                     help="only run the config-4 batch leg (two batched calls and the per-code loop), for a profiler")
     ap.add_argument("--first-draws-only", action="store_true",
                     help="only run the unfiltered config-4 draws (first --batch-codes draws, per-code budget)")
+    ap.add_argument("--tune-out", default="",
+                    help="only run the launch-shape tuner (qd_tune_run, up to 300 s) and write its table to this file")
     ap.add_argument("--latency-only", action="store_true",
                     help="only run the time-to-exact-d leg on configs 1 and 2, for a profiler")
     ap.add_argument("--round-sweep", action="store_true",
@@ -293,6 +295,16 @@ def leg_batched(Q, W, a):
     t_fw, ds_fw, sts_fw, stats_fw = fw[1]
     comb_fw = sum(s.combinations for s in stats_fw)
     _, _, _, stats_bt = run_batch(Q, codes, budget, timing=1)
+    # The same batch under the fixed launch-shape rules (no tuning table).
+    st_t, tuned = Q.qd_tune_get()
+    n_tuned = len(json.loads(tuned)["entries"]) if st_t == 0 else 0
+    t_rules = None
+    if n_tuned:
+        Q.qd_tune_reset()
+        run_batch(Q, codes, budget)
+        rr = sorted(run_batch(Q, codes, budget)[0] for _ in range(3))
+        t_rules = rr[1]
+        Q.qd_tune_load(tuned)
     ns = [G.shape[1] // 2 if f == 2 else G.shape[1] for G, f in codes]
     return {
         "workload": f"config 4: first {len(codes)} of {drawn} drawn codes (n~U{{24..96}}, even additive m~U{{n-8..n+8}}, "
@@ -302,6 +314,7 @@ def leg_batched(Q, W, a):
         "same_d_as_per_code": ds == ds_p, "same_d_every_word": ds_fw == ds,
         "time_to_exact_d_s": t_batch, "batched_first_call_s": t_cold,
         "per_code_loop_s": t_plain, "speedup_vs_per_code_loop": t_plain / t_batch,
+        "tuned_buckets": n_tuned, "time_to_exact_d_s_fixed_rules": t_rules,
         "per_code_loop_kernel_s": kms_p * 1e-3,
         "batched_kernel_s": sum(s.kernel_ms for s in stats_bt) * 1e-3,
         "combinations_certified_per_s": comb_b / t_batch,
@@ -552,6 +565,16 @@ def main():
         return
     stream = torch.cuda.current_stream()
     G, field = W.config3(a.seed)
+    if a.tune_out:
+        t0 = time.perf_counter()
+        st, text = Q.qd_tune_run(300.0)
+        if st not in (0, Q.QD_INCOMPLETE):
+            raise RuntimeError(Q.qd_strerror(st))
+        with open(a.tune_out, "w") as fh:
+            fh.write(text)
+        print(json.dumps({"tune": {"status": st, "seconds": time.perf_counter() - t0,
+                                   "entries": len(json.loads(text)["entries"]), "file": a.tune_out}}))
+        return
     if a.cpu_exact:
         print(json.dumps({"cpu_exact": cpu_exact(G, field, a.seed)}))
         return

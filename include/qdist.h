@@ -270,6 +270,36 @@ int qd_round_census(const uint8_t *rows, const int *dims, int P, int n, int t, i
                     int below, int *wmin, uint8_t *witness, unsigned long long *count,
                     unsigned long long *below_count, unsigned long long *below_weight_sum);
 
+/* -- Measured tuning of the launch shape -------------------------------------
+ * The enumeration's launch shape per round is a segment length (saved-table
+ * entries per tile) and a saved-table depth cap (packages per saved entry,
+ * the "saving additions" of Sec. 2.1).  Without tuning the library picks
+ * them by fixed rules; qd_tune_run measures them on the current device and
+ * installs the fastest per bucket: word count D = 1..4, round size (nearest
+ * of 2^20, 2^24, ..., 2^36 combinations), codes sharing a step (1, 2-8,
+ * more) and word path (every word evaluated, or partial weights).  For
+ * each bucket it times synthetic rounds of random two-row packages under
+ * every segment length in {256, 512, 1024, 2048, 4096} and depth cap in
+ * {2, 3, 4} (best of two runs after a warm-up; builds, launches and
+ * readbacks included).  Installed shapes apply to every later call in the
+ * process on every device, except the serving engine's (latency first) and
+ * calls whose qd_options fix seg_len or saved_depth.  Results do not depend
+ * on the shape.  The first GPU call of a process installs the file named by
+ * $QD_TUNE_FILE, or tune_gfx950.json beside the library when that variable
+ * is unset (an empty value: none).
+ *
+ * qd_tune_run: the sweep, stopped after max_seconds (> 0; QD_INCOMPLETE when
+ * it stopped early, with the buckets measured so far installed).  json
+ * (json_len bytes, may be NULL) receives the installed table as text;
+ * QD_ERR_INVALID if it does not fit.  qd_tune_load installs such a text
+ * (QD_ERR_INVALID if it does not parse; nothing changes then);
+ * qd_tune_get writes the installed table; qd_tune_reset returns to the
+ * fixed rules. */
+int qd_tune_run(double max_seconds, char *json, size_t json_len);
+int qd_tune_load(const char *json);
+int qd_tune_get(char *json, size_t json_len);
+int qd_tune_reset(void);
+
 /* Device bytes of the fixed array qd_round_min_noalloc works in (per GPU). */
 #define QD_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
 

@@ -21,7 +21,7 @@ namespace {
 constexpr int kDefaultSavedDepth = 4;                     // packages per saved-table entry
 constexpr unsigned long long kMaxTableBytes = 1ull << 29;
 constexpr unsigned long long kMaxTopEntries = 1ull << 24;  // 512 MB of tops
-constexpr unsigned long long kTilesPerLaunch = 1ull << 21;
+constexpr unsigned long long kTilesPerLaunch = 1ull << 22;
 constexpr unsigned long long kTargetTiles = 1ull << 18;    // ~32 tiles per wave slot
 constexpr unsigned kMinSeg = 1024, kMaxSeg = 4096;
 // Rounds below kShortRound combinations of a step with few codes start from
@@ -851,9 +851,17 @@ int Executor::schedule(Job &job, int sharing) {
     // are in this step or earlier, so the round's waves may stop as soon as U
     // reaches it.
     f.L_before = job.single_round ? -1 : lower_bound(tsim, job.delta, job.halve);
-    const int cap = job.opt.saved_depth < 0 ? 0 : job.opt.saved_depth ? job.opt.saved_depth : kDefaultSavedDepth;
+    // A measured shape for this bucket, unless the caller fixed one.
+    unsigned tseg = 0;
+    int tdepth = 0;
+    const bool tuned = tuned_ && !job.opt.seg_len && !job.opt.saved_depth &&
+                       tune_lookup(job.D, planned, sharing, job.partial || job.force_words > 0 ? 1 : 0, &tseg, &tdepth);
+    const int cap = job.opt.saved_depth < 0 ? 0
+                    : job.opt.saved_depth   ? job.opt.saved_depth
+                    : tuned                 ? tdepth
+                                            : kDefaultSavedDepth;
     f.u = saved_depth(g, job.D, t, cap, max_table_bytes_);
-    f.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : choose_seg(planned, sharing, long_seg_);
+    f.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : tuned ? tseg : choose_seg(planned, sharing, long_seg_);
     const int tm = job.opt.tops_mode;
     const unsigned long long max_tops = std::min(kMaxTopEntries, max_table_bytes_ / (kElemWords * 4));
     f.use_tops = tm == 1 || (tm == 0 && g.suffix[t - f.u] <= max_tops);
@@ -1228,6 +1236,7 @@ int default_executor(Executor **ex, std::unique_lock<std::mutex> *lock) {
       locks.resize(dev + 1);
     }
     if (!per_dev[dev]) {
+      tune_autoload();
       per_dev[dev] = std::make_unique<Executor>();
       locks[dev] = std::make_unique<std::mutex>();
     }

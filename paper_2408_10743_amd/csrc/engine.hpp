@@ -190,6 +190,9 @@ class Executor {
   // Table entries per tile that large rounds start from (steps of fewer
   // than 9 codes): shorter tiles end steps sooner, e.g. for serving.
   void set_long_seg(unsigned seg) { long_seg_ = seg; }
+  // Whether rounds take the measured launch shapes (tune_lookup) where
+  // installed; the serving engine keeps its latency-minded model rules.
+  void set_tuned(bool on) { tuned_ = on; }
 
   // Host-side preparation of a job (input check, basis, diagonalizations,
   // plan).  Thread-safe; touches no device state.
@@ -219,6 +222,7 @@ class Executor {
   int grow_states(int need);
 
   bool ok_ = false;
+  bool tuned_ = true;
   unsigned long long spec_combos_;
   unsigned long_seg_;
   bool own_stream_ = false;
@@ -257,6 +261,14 @@ class Executor {
 
 // The executor of the current device for the synchronous entry points.
 int default_executor(Executor **ex, std::unique_lock<std::mutex> *lock);
+
+// Measured launch shapes (tune.cpp): the tuned segment length and saved-table
+// depth cap for a round of `planned` combinations of a code with D words per
+// half, in a step shared by `sharing` codes, on the partial-weight path
+// (partial_words > 0) or not; false when no tuning is installed for that
+// bucket.  tune_autoload installs the tuning file once per process.
+bool tune_lookup(int D, unsigned long long planned, int sharing, int partial_words, unsigned *seg, int *depth);
+void tune_autoload();
 
 // Runs a set of prepared jobs to completion on one executor.
 int run_jobs(Executor &ex, std::vector<Job *> &jobs, hipStream_t s);

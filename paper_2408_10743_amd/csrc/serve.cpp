@@ -116,6 +116,7 @@ qd_engine *qd_engine_create(size_t mem_budget, int max_active, void *stream) {
   // Tiles of 256 entries: a step ends with its last tile, and requests
   // that arrive meanwhile wait for it.
   e->ex->set_long_seg(256);
+  e->ex->set_tuned(false);  // latency first: short tiles, whatever a throughput tuning chose
   e->budget = mem_budget ? mem_budget : (size_t(8) << 30);
   e->max_active = max_active > 0 ? max_active : 512;
   qd_engine *raw = e.release();

@@ -1,0 +1,276 @@
+// tune.cpp -- measured tuning of the enumeration's launch shape.  For each
+// (word count D, round size, codes sharing a step, word path) the tuner times
+// synthetic rounds on the device under every candidate segment length (table
+// entries per tile) and saved-table depth cap, and keeps the fastest; the
+// scheduler then takes the tuned shape for rounds of that bucket instead of
+// its model rules (choose_seg, saved_depth).
+#include <dlfcn.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/qdist.h"
+#include "engine.hpp"
+#include "host.hpp"
+
+namespace qd {
+
+namespace {
+
+using Key = std::tuple<int, int, int, int>;  // D, size bucket (log2), sharing bucket, partial words
+
+struct Choice {
+  unsigned seg;
+  int depth;
+  double ms;
+};
+
+std::mutex g_mu;
+std::map<Key, Choice> g_table;
+
+double wall_ms() {
+  using C = std::chrono::steady_clock;
+  return std::chrono::duration<double, std::milli>(C::now().time_since_epoch()).count();
+}
+
+// Buckets: round size to the nearest of 2^20, 2^24, ..., 2^36 (log2 scale);
+// codes sharing the step: 1, 2..8, more.
+int size_bucket(unsigned long long planned) {
+  const double l = std::log2(double(std::max<unsigned long long>(planned, 1)));
+  const int b = int(std::lround(l / 4.0)) * 4;
+  return std::min(36, std::max(20, b));
+}
+int share_bucket(int sharing) { return sharing <= 1 ? 1 : sharing <= 8 ? 4 : 16; }
+
+// Deterministic synthetic packages (xorshift64*): tuning input, not part of
+// any result.
+struct Rng {
+  uint64_t s;
+  uint64_t next() {
+    s ^= s >> 12;
+    s ^= s << 25;
+    s ^= s >> 27;
+    return s * 0x2545F4914F6CDD1Dull;
+  }
+};
+
+// A job for one synthetic round: P two-row packages of random (x|z) rows on n
+// qubits, round t, the given shape and word path.
+bool synth_job(Job &job, int P, int n, int t, unsigned seg, int depth, int partial_words, uint64_t seed) {
+  job = Job{};
+  job.n = n;
+  job.single_round = true;
+  job.t = t;
+  job.opt.partial_weight = -1;
+  job.opt.seg_len = int(seg);
+  job.opt.saved_depth = depth;
+  job.opt.timing = 0;
+  job.force_words = partial_words;
+  Rng r{seed | 1};
+  Gamma g;
+  std::vector<uint8_t> rows(size_t(2) * 2 * n);
+  for (int i = 0; i < P; ++i) {
+    for (auto &b : rows) b = uint8_t(r.next() >> 63);
+    Package pk;
+    pk.dim = 2;
+    pk.pivot = -1;
+    std::vector<BRow> two;
+    if (load_rows(rows.data(), 2, n, QD_FIELD_F2, two)) return false;
+    pk.r = two[0];
+    pk.s = two[1];
+    g.pk.push_back(pk);
+  }
+  job.use.push_back(g);
+  Executor::prepare_gammas(job);
+  return true;
+}
+
+// Time of `share` copies of one synthetic round under one shape: best of two
+// runs after a warm-up run (host wall clock around the whole run: table
+// builds, launches and readbacks included).
+double time_shape(Executor &ex, int share, int P, int n, int t, unsigned seg, int depth, int pw) {
+  double best = 1e30;
+  for (int rep = 0; rep < 3; ++rep) {
+    std::vector<Job> jobs(static_cast<size_t>(share));
+    std::vector<Job *> v;
+    for (int i = 0; i < share; ++i) {
+      if (!synth_job(jobs[size_t(i)], P, n, t, seg, depth, pw, 0x9E3779B97F4A7C15ull * uint64_t(i + 1))) return -1;
+      v.push_back(&jobs[size_t(i)]);
+    }
+    const double t0 = wall_ms();
+    run_jobs(ex, v, ex.stream());
+    const double ms = wall_ms() - t0;
+    for (Job &j : jobs)
+      if (j.status < 0) return -1;
+    if (rep) best = std::min(best, ms);
+  }
+  return best;
+}
+
+std::string to_json_locked() {
+  std::string s = "{\"format\": \"qdist-tune-1\", \"entries\": [";
+  bool first = true;
+  for (const auto &kv : g_table) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf),
+                  "%s\n {\"D\": %d, \"size_log2\": %d, \"share\": %d, \"partial_words\": %d, \"seg\": %u, "
+                  "\"depth\": %d, \"ms\": %.4f}",
+                  first ? "" : ",", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                  std::get<3>(kv.first), kv.second.seg, kv.second.depth, kv.second.ms);
+    s += buf;
+    first = false;
+  }
+  s += "\n]}\n";
+  return s;
+}
+
+int write_out(const std::string &s, char *out, size_t len) {
+  if (!out) return QD_OK;
+  if (s.size() + 1 > len) return QD_ERR_INVALID;
+  std::memcpy(out, s.c_str(), s.size() + 1);
+  return QD_OK;
+}
+
+// The integer after "name": in an entry's text; false when absent.
+bool field(const std::string &e, const char *name, long *v) {
+  const std::string k = std::string("\"") + name + "\":";
+  const size_t p = e.find(k);
+  if (p == std::string::npos) return false;
+  char *end = nullptr;
+  *v = std::strtol(e.c_str() + p + k.size(), &end, 10);
+  return end != e.c_str() + p + k.size();
+}
+
+bool valid_seg(long seg) { return seg >= 8 && seg <= 65536 && seg % 8 == 0; }
+
+}  // namespace
+
+// Installs the tuning file once per process: $QD_TUNE_FILE, or (unset)
+// tune_gfx950.json beside the library; an empty $QD_TUNE_FILE, a missing file
+// or one that does not parse leaves the model rules.
+void tune_autoload() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    std::string path;
+    if (const char *e = std::getenv("QD_TUNE_FILE")) {
+      path = e;
+    } else {
+      Dl_info info;
+      if (dladdr(reinterpret_cast<void *>(&qd_tune_get), &info) && info.dli_fname) {
+        path = info.dli_fname;
+        const size_t slash = path.rfind('/');
+        path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) + "/tune_gfx950.json";
+      }
+    }
+    if (path.empty()) return;
+    std::ifstream f(path);
+    if (!f) return;
+    const std::string text((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+    (void)qd_tune_load(text.c_str());
+  });
+}
+
+bool tune_lookup(int D, unsigned long long planned, int sharing, int partial_words, unsigned *seg, int *depth) {
+  std::lock_guard<std::mutex> g(g_mu);
+  if (g_table.empty()) return false;
+  const auto it = g_table.find(Key{D, size_bucket(planned), share_bucket(sharing), partial_words > 0 ? 1 : 0});
+  if (it == g_table.end()) return false;
+  *seg = it->second.seg;
+  *depth = it->second.depth;
+  return true;
+}
+
+}  // namespace qd
+
+using namespace qd;
+
+int qd_tune_run(double max_seconds, char *json, size_t json_len) {
+  Executor *ex = nullptr;
+  std::unique_lock<std::mutex> lk;
+  int rc = default_executor(&ex, &lk);
+  if (rc) return rc;
+  if (!(max_seconds > 0)) return QD_ERR_INVALID;
+  // Round t over P two-row packages: e_t = C(P, t) 3^t close to 2^size.
+  struct Size { int log2, t, P; };
+  const Size sizes[] = {{20, 4, 25}, {24, 5, 26}, {28, 6, 28}, {32, 6, 43}, {36, 7, 43}};
+  const unsigned segs[] = {64, 128, 256, 512, 1024, 2048, 4096};
+  const int depths[] = {2, 3, 4};
+  const double t_end = wall_ms() + max_seconds * 1e3;
+  // QD_TUNE_VERBOSE=1: one line per bucket on stderr.
+  const bool verbose = std::getenv("QD_TUNE_VERBOSE") && std::getenv("QD_TUNE_VERBOSE")[0] == '1';
+  std::map<Key, Choice> table;
+  bool complete = true;
+  for (int D = 1; D <= 4 && complete; ++D) {
+    const int n = 32 * D - 3;
+    for (const Size &sz : sizes) {
+      for (int share : {1, 16}) {
+        if (share > 1 && sz.log2 > 32) continue;  // 16 such rounds: beyond a tuning run's time
+        for (int pw = 0; pw <= (D > 1 ? 1 : 0); ++pw) {
+          if (wall_ms() > t_end) { complete = false; break; }
+          Choice best{0, 0, 1e30};
+          for (unsigned seg : segs)
+            for (int depth : depths) {
+              if (depth > sz.t - 2) continue;  // the same tables as t - 2
+              const double ms = time_shape(*ex, share, sz.P, n, sz.t, seg, depth, pw);
+              if (ms < 0) return QD_ERR_DEVICE;
+              if (ms < best.ms) best = Choice{seg, depth, ms};
+            }
+          table[Key{D, sz.log2, share, pw}] = best;
+          if (verbose)
+            std::fprintf(stderr, "qd tune: D %d size 2^%d share %d partial %d: seg %u depth %d %.3f ms\n", D, sz.log2,
+                         share, pw, best.seg, best.depth, best.ms);
+        }
+      }
+    }
+  }
+  std::lock_guard<std::mutex> g(g_mu);
+  g_table = table;
+  rc = write_out(to_json_locked(), json, json_len);
+  return rc ? rc : (complete ? QD_OK : QD_INCOMPLETE);
+}
+
+int qd_tune_load(const char *json) {
+  if (!json) return QD_ERR_INVALID;
+  const std::string s(json);
+  if (s.find("\"qdist-tune-1\"") == std::string::npos) return QD_ERR_INVALID;
+  std::map<Key, Choice> table;
+  size_t p = s.find('[');
+  while (p != std::string::npos) {
+    const size_t a = s.find('{', p), b = a == std::string::npos ? a : s.find('}', a);
+    if (a == std::string::npos || b == std::string::npos) break;
+    const std::string e = s.substr(a, b - a + 1);
+    long D, sz, share, pw, seg, depth;
+    if (!field(e, "D", &D) || !field(e, "size_log2", &sz) || !field(e, "share", &share) ||
+        !field(e, "partial_words", &pw) || !field(e, "seg", &seg) || !field(e, "depth", &depth) || D < 1 ||
+        D > 4 || sz < 20 || sz > 36 || sz % 4 || (share != 1 && share != 4 && share != 16) || !valid_seg(seg) ||
+        depth < 0 || depth > 8 || (pw != 0 && pw != 1))
+      return QD_ERR_INVALID;
+    table[Key{int(D), int(sz), int(share), int(pw)}] = Choice{unsigned(seg), int(depth), 0.0};
+    p = b + 1;
+  }
+  std::lock_guard<std::mutex> g(g_mu);
+  g_table = table;
+  return QD_OK;
+}
+
+int qd_tune_get(char *json, size_t json_len) {
+  std::lock_guard<std::mutex> g(g_mu);
+  return write_out(to_json_locked(), json, json_len);
+}
+
+int qd_tune_reset(void) {
+  std::lock_guard<std::mutex> g(g_mu);
+  g_table.clear();
+  return QD_OK;
+}

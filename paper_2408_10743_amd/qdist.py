@@ -131,6 +131,9 @@ _lib.qd_round_census.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c
                                  ctypes.POINTER(ctypes.c_ulonglong)]
 _lib.qd_round_min_noalloc.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _u8p,
                                       ctypes.POINTER(ctypes.c_ulonglong), ctypes.c_int, ctypes.c_void_p]
+_lib.qd_tune_run.argtypes = [ctypes.c_double, ctypes.c_char_p, ctypes.c_size_t]
+_lib.qd_tune_load.argtypes = [ctypes.c_char_p]
+_lib.qd_tune_get.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
 _lib.qd_round_walk.argtypes = [_u8p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _u8p,
                                ctypes.POINTER(ctypes.c_ulonglong), ctypes.POINTER(ctypes.c_ulonglong)]
 _lib.qd_device_check.argtypes = [ctypes.c_char_p, ctypes.c_int]
@@ -271,6 +274,28 @@ def qd_round_min(rows, dims, t, partial_words=0):
     return st, w.value, wit, cnt.value
 
 
+def qd_tune_run(max_seconds=60.0):
+    """Measures the launch shapes on the device and installs them: returns
+    (status, table as JSON text)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    st = _lib.qd_tune_run(max_seconds, buf, len(buf))
+    return st, buf.value.decode()
+
+
+def qd_tune_load(text):
+    return _lib.qd_tune_load(text.encode())
+
+
+def qd_tune_get():
+    buf = ctypes.create_string_buffer(1 << 16)
+    st = _lib.qd_tune_get(buf, len(buf))
+    return st, buf.value.decode()
+
+
+def qd_tune_reset():
+    return _lib.qd_tune_reset()
+
+
 def qd_round_min_noalloc(rows, dims, t, partial_words=0, stream=None):
     """qd_round_min on the library's fixed device array (no device
     allocation): returns (status, wmin, witness, count)."""
@@ -374,5 +399,6 @@ def qd_engine_destroy(engine):
 def exported_symbols():
     """Names of the C ABI entry points declared in include/qdist.h."""
     return ["qd_distance", "qd_distance_ex", "qd_distance_batch", "qd_distance_batch_ex", "qd_plan",
-            "qd_round_min", "qd_round_census", "qd_round_min_noalloc", "qd_round_walk", "qd_strerror", "qd_device_check", "qd_valu_peak", "qd_valu_mix", "qd_engine_create",
+            "qd_round_min", "qd_round_census", "qd_round_min_noalloc", "qd_round_walk",
+            "qd_tune_run", "qd_tune_load", "qd_tune_get", "qd_tune_reset", "qd_strerror", "qd_device_check", "qd_valu_peak", "qd_valu_mix", "qd_engine_create",
             "qd_engine_submit", "qd_engine_poll", "qd_engine_outstanding", "qd_engine_destroy"]

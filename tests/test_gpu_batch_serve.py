@@ -142,3 +142,24 @@ def test_engine_destroy_with_work_outstanding(Q):
     t0 = time.time()
     Q.qd_engine_destroy(e)
     assert time.time() - t0 < 30
+
+
+def test_batch_of_every_word_count_in_one_launch(Q):
+    """Codes of D = 1, 2, 3 and 4 words per half in one batch (each step
+    launches the round kernel of every D).  Every code gives the oracle's
+    distance and its result alone, on the default path, with every word
+    evaluated, and with 64-entry tiles."""
+    codes = []
+    for i, n in enumerate((20, 30, 40, 60, 72, 90, 100, 120)):
+        rng = W.SplitMix64(W.config_seed(93, i))
+        codes.append((W.additive(n, rng.uniform_int(18, 24), rng.next()), 2))
+    codes.append((W.f4_linear(70, 11, W.config_seed(93, 50)), 4))
+    refs = [O.distance(G, f)[0] for G, f in codes]
+    for opts in ({}, {"partial_weight": -1}, {"seg_len": 64}):
+        st, ds, wits, sts, stats = Q.qd_distance_batch(codes, **opts)
+        assert st == 0 and all(s == 0 for s in sts), (opts, sts)
+        assert sorted({s.D for s in stats}) == [1, 2, 3, 4]
+        for (G, f), d, w, r in zip(codes, ds, wits, refs):
+            assert d == r, opts
+            assert swt(w) == d and O.in_rowspace(O.expand(G, f), w)
+            assert Q.qd_distance_ex(G, f, **opts)[1] == d
