@@ -10,7 +10,7 @@
 
 namespace qd {
 
-hipError_t launch_round(int D, const LaunchParams &lp, bool census, hipStream_t s);
+hipError_t launch_round(int D, const LaunchParams &lp, bool census, bool every_word, hipStream_t s);
 hipError_t launch_walk(int D, const LaunchParams &lp, bool sum, hipStream_t s);
 hipError_t launch_build(int D, const BuildParams &bp, hipStream_t s);
 hipError_t launch_commit(const LaunchParams &lp, hipStream_t s);
@@ -952,6 +952,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   struct Launch {
     int D;
     bool walk, sum;  // plain walk kernel; with the weight sum
+    bool every_word; // no piece uses partial weights (entry-major kernel)
     size_t d0, d1;
     unsigned long long tiles;
     unsigned lds;
@@ -971,7 +972,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   for (int kind = 0; kind < 8; ++kind) {
     const int D = kind % 4 + 1;
     const bool walk = kind >= 4;
-    Launch L{D, walk, false, descs_.size(), 0, 0, 0, false};
+    Launch L{D, walk, false, true, descs_.size(), 0, 0, 0, false};
     for (Job *jp : jobs) {
       Job &job = *jp;
       if (job.done || job.D != D || job.status || (job.opt.walk > 0) != walk) continue;
@@ -1051,6 +1052,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         if (lds > kStageMaxBytes) { d.stage = 0; lds = 0; }
         L.lds = std::max(L.lds, lds);
         L.timed = L.timed || job.opt.timing;
+        L.every_word = L.every_word && !job.partial && !job.force_words;
         L.tiles += (take + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
         f.sent += take;
         ++f.launches;
@@ -1089,7 +1091,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
       lp.tiles = L.tiles;
       lp.slots = static_cast<uint32_t *>(slots_.p);
       if (L.timed && hipEventRecord(events_[2 * i], s) != hipSuccess) return QD_ERR_DEVICE;
-      if ((L.walk ? launch_walk(L.D, lp, L.sum, s) : launch_round(L.D, lp, L.sum, s)) != hipSuccess) return QD_ERR_DEVICE;
+      if ((L.walk ? launch_walk(L.D, lp, L.sum, s) : launch_round(L.D, lp, L.sum, L.every_word, s)) != hipSuccess) return QD_ERR_DEVICE;
       if (L.timed && hipEventRecord(events_[2 * i + 1], s) != hipSuccess) return QD_ERR_DEVICE;
       if (launch_commit(lp, s) != hipSuccess) return QD_ERR_DEVICE;
     }

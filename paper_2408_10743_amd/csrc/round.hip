@@ -167,6 +167,80 @@ __device__ __forceinline__ uint32_t blocks_min_partial(const uint32_t (&ax)[D], 
   return best;
 }
 
+// Entry-major blocks (every word evaluated): a block is kWave * K consecutive
+// table entries, lane l holding entries e0 + l + 64 i (i < K) in VGPRs, and
+// the wave's tops broadcast one at a time from the lane holding them
+// (ds_bpermute).  Every operand of the XOR, the XOR-OR and the popcount is
+// then a VGPR, which lets the VALU pair the bitwise operations; the
+// streaming loop (block_min) reads its entries through SGPRs, and an
+// operation with an SGPR operand never pairs.
+template <int D>
+struct EmK {
+  static constexpr int K = D <= 2 ? 16 : D == 3 ? 8 : 4;  // entries per lane (VGPRs: 2D K)
+};
+
+__device__ __forceinline__ uint32_t bcast(uint32_t v, int src_lane) {
+  return static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(src_lane << 2, static_cast<int>(v)));
+}
+
+// One entry-major block: entries [e0, e0 + 64 K) against the tops of lanes
+// 0..ntop-1; returns the lane's minimum over its entries and those tops.
+template <int D, bool kCensus>
+__device__ __forceinline__ uint32_t em_block(const uint32_t *__restrict__ table, unsigned long long e0, uint32_t lane,
+                                             const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop,
+                                             uint32_t best, Census &cs) {
+  constexpr int K = EmK<D>::K;
+  uint32_t ex[K][D], ez[K][D];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const unsigned long long k = e0 + static_cast<unsigned long long>(i) * kWave + lane;
+    const uint32_t *b = table + (k / kBlock) * (2 * D * kBlock) + (k % kBlock);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      ex[i][d] = b[d * kBlock];
+      ez[i][d] = b[(D + d) * kBlock];
+    }
+  }
+  uint32_t tx[D], tz[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    tx[d] = bcast(ax[d], 0);
+    tz[d] = bcast(az[d], 0);
+  }
+  for (int j = 0; j < ntop; ++j) {
+    uint32_t nx[D], nz[D];  // the next top, fetched while this one is evaluated
+    const int jn = j + 1 < ntop ? j + 1 : j;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      nx[d] = bcast(ax[d], jn);
+      nz[d] = bcast(az[d], jn);
+    }
+    uint32_t w[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      uint32_t acc = 0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const uint32_t o = (ex[i][d] ^ tx[d]) | (ez[i][d] ^ tz[d]);
+        acc = d == 0 ? __builtin_popcount(o) : bcnt_acc(o, acc);
+      }
+      w[i] = acc;
+    }
+    if constexpr (kCensus) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) cs.add(w[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < K; i += 2) best = min3(best, w[i], w[i + 1]);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      tx[d] = nx[d];
+      tz[d] = nz[d];
+    }
+  }
+  return best;
+}
+
 // The full blocks of a tile with partial weights, kPartialBlocks blocks per
 // wait for their scalar loads.
 constexpr int kPartialBlocks = 2;
@@ -246,7 +320,11 @@ constexpr uint32_t kXcdChunk = 16;
 // lanes stay full; a lane stops at its own group's prefix length.  A launch
 // holds pieces of the current rounds of several codes (RoundDesc).  With
 // kCensus every piece also takes the census of its codewords below p.below.
-template <int D, bool kCensus>
+// kEntryMajor: the launch's pieces evaluate every word (no partial weights),
+// and their full blocks go through entry-major blocks first; the kernel then
+// holds more registers, so launches with partial weights keep the streaming
+// loop alone.
+template <int D, bool kCensus, bool kEntryMajor>
 __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   extern __shared__ unsigned long long smem[];
   // Consecutive workgroups land on different XCDs (round robin).  Deal them
@@ -357,8 +435,23 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   for (int w = D - 1; w >= 1; --w)
     if (U0 <= p.cap[w - 1]) W = w;
   uint32_t rec = 0;  // full blocks evaluated in full
+  // Every word: entry-major blocks over the wave's active tops (lanes
+  // 0..nact-1: items grow with the lane), then the streaming loop for the
+  // rest of the full blocks.  best_em and cs_em hold codewords of every
+  // active top, whatever the lane's own top.
+  uint32_t best_em = 0xFFFFFFFFu;
+  Census cs_em;
+  if constexpr (kCensus) cs_em.below = static_cast<uint32_t>(p.below);
+  const int ntop = static_cast<int>(__popcll(__ballot(active)));
   if (W == D) {
-    for (uint32_t i = 0; i < nfull; ++i, blk += 2 * D * kBlock) best = block_min<D, kCensus>(ax, az, blk, best, cs);
+    constexpr uint32_t kEm = kWave * EmK<D>::K;
+    const uint32_t nem = kEntryMajor && ntop > 1 ? sfull / kEm : 0u;
+    for (uint32_t bk = 0; bk < nem; ++bk)
+      best_em = em_block<D, kCensus>(p.table, k0 + static_cast<unsigned long long>(bk) * kEm, lane, ax, az, ntop,
+                                     best_em, cs_em);
+    blk += (nem * kEm / kBlock) * (2 * D * kBlock);
+    for (uint32_t i = nem * kEm / kBlock; i < nfull; ++i, blk += 2 * D * kBlock)
+      best = block_min<D, kCensus>(ax, az, blk, best, cs);
   } else {
     const int c = p.credit[W - 1];
     const uint32_t thr = U0 > c ? static_cast<uint32_t>(U0 - c) : 0u;
@@ -380,13 +473,13 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
     }
   }
   if (!active) best = 0xFFFFFFFFu;
-  const uint32_t wmin = wave_min(best);
+  const uint32_t wmin = wave_min(min(best, best_em));
   const uint32_t visited = wave_sum(active ? span : 0u);
-  const unsigned long long nact = __popcll(__ballot(active));  // outside the lane-0 branch
+  const unsigned long long nact = static_cast<unsigned long long>(ntop);
   if constexpr (kCensus) {
-    // Per lane at most seg entries of weight <= 128: the wave sums fit 32 bits.
-    const uint32_t ccnt = wave_sum(active ? cs.cnt : 0u);
-    const uint32_t csum = wave_sum(active ? cs.sum : 0u);
+    // Per lane at most 64 seg codewords of weight <= 128: the wave sums fit 32 bits.
+    const uint32_t ccnt = wave_sum((active ? cs.cnt : 0u) + cs_em.cnt);
+    const uint32_t csum = wave_sum((active ? cs.sum : 0u) + cs_em.sum);
     if (lane == 0 && p.census) {
       atomicAdd(p.census, static_cast<unsigned long long>(ccnt));
       atomicAdd(p.census + 1, static_cast<unsigned long long>(csum));
@@ -453,7 +546,7 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
       const uint32_t w = weight_at<D>(p.table, k0 + i, ax, az);
       if (i < span && w == wmin && kf == 0xFFFFFFFFu) kf = i;
     }
-    const unsigned long long mask = __ballot(active && best == wmin);
+    const unsigned long long mask = __ballot(active && kf != 0xFFFFFFFFu);
     const int winner = __ffsll(static_cast<long long>(mask)) - 1;
     if (static_cast<int>(lane) == winner) {
       const uint32_t slot = static_cast<uint32_t>(p.slot0 + local);  // launch-wide slot
@@ -473,19 +566,23 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
 
 // -- launch (host) -------------------------------------------------------------
 
-hipError_t launch_round(int D, const LaunchParams &lp, bool census, hipStream_t s) {
+template <int D>
+void launch_round_d(const LaunchParams &lp, bool census, bool em, dim3 grid, dim3 block, hipStream_t s) {
+  if (census && em) hipLaunchKernelGGL((qd_round_kernel<D, true, true>), grid, block, lp.lds, s, lp);
+  else if (census) hipLaunchKernelGGL((qd_round_kernel<D, true, false>), grid, block, lp.lds, s, lp);
+  else if (em) hipLaunchKernelGGL((qd_round_kernel<D, false, true>), grid, block, lp.lds, s, lp);
+  else hipLaunchKernelGGL((qd_round_kernel<D, false, false>), grid, block, lp.lds, s, lp);
+}
+
+hipError_t launch_round(int D, const LaunchParams &lp, bool census, bool every_word, hipStream_t s) {
   unsigned long long wgs = lp.tiles / kWavesPerGroup;
   wgs = (wgs + 8 * kXcdChunk - 1) / (8 * kXcdChunk) * (8 * kXcdChunk);  // the XCD dealing is a bijection
   dim3 grid(static_cast<uint32_t>(wgs)), block(kWave * kWavesPerGroup);
-  switch (D * 2 + (census ? 1 : 0)) {
-    case 2: hipLaunchKernelGGL((qd_round_kernel<1, false>), grid, block, lp.lds, s, lp); break;
-    case 3: hipLaunchKernelGGL((qd_round_kernel<1, true>), grid, block, lp.lds, s, lp); break;
-    case 4: hipLaunchKernelGGL((qd_round_kernel<2, false>), grid, block, lp.lds, s, lp); break;
-    case 5: hipLaunchKernelGGL((qd_round_kernel<2, true>), grid, block, lp.lds, s, lp); break;
-    case 6: hipLaunchKernelGGL((qd_round_kernel<3, false>), grid, block, lp.lds, s, lp); break;
-    case 7: hipLaunchKernelGGL((qd_round_kernel<3, true>), grid, block, lp.lds, s, lp); break;
-    case 8: hipLaunchKernelGGL((qd_round_kernel<4, false>), grid, block, lp.lds, s, lp); break;
-    case 9: hipLaunchKernelGGL((qd_round_kernel<4, true>), grid, block, lp.lds, s, lp); break;
+  switch (D) {
+    case 1: launch_round_d<1>(lp, census, every_word, grid, block, s); break;
+    case 2: launch_round_d<2>(lp, census, every_word, grid, block, s); break;
+    case 3: launch_round_d<3>(lp, census, every_word, grid, block, s); break;
+    case 4: launch_round_d<4>(lp, census, every_word, grid, block, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
