@@ -167,6 +167,9 @@ __device__ __forceinline__ uint32_t blocks_min_partial(const uint32_t (&ax)[D], 
   return best;
 }
 
+// Kernel variants by the entry-major blocks they use (qd_round_kernel).
+constexpr int kEmEveryWord = 1, kEmPartial = 2;
+
 // Entry-major blocks (every word evaluated): a block is kWave * K consecutive
 // table entries, lane l holding entries e0 + l + 64 i (i < K) in VGPRs, and
 // the wave's tops broadcast one at a time from the lane holding them
@@ -237,6 +240,66 @@ __device__ __forceinline__ uint32_t em_block(const uint32_t *__restrict__ table,
       tx[d] = nx[d];
       tz[d] = nz[d];
     }
+  }
+  return best;
+}
+
+// Entry-major blocks with partial weights on the first word: lane l holds
+// word 0 (x and z) of entries e0 + l + 64 i, i < kEmPartialK.  For each top
+// the K first-word weights are formed from VGPR operands; when some lane's
+// bound falls below U (thr = U - credit) the 64 K codewords of that top are
+// completed, their remaining words read from the table, and their full
+// weights enter `best` and the census.  `done` counts the completed tops.
+constexpr int kEmPartialK = 16;
+
+template <int D, bool kCensus>
+__device__ __forceinline__ uint32_t em_block_partial(const uint32_t *__restrict__ table, unsigned long long e0,
+                                                     uint32_t lane, const uint32_t (&ax)[D], const uint32_t (&az)[D],
+                                                     int ntop, uint32_t best, uint32_t thr, Census &cs,
+                                                     uint32_t &done) {
+  constexpr int K = kEmPartialK;
+  uint32_t ex[K], ez[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const unsigned long long k = e0 + static_cast<unsigned long long>(i) * kWave + lane;
+    const uint32_t *b = table + (k / kBlock) * (2 * D * kBlock) + (k % kBlock);
+    ex[i] = b[0];
+    ez[i] = b[D * kBlock];
+  }
+  uint32_t tx = bcast(ax[0], 0), tz = bcast(az[0], 0);
+  for (int j = 0; j < ntop; ++j) {
+    const int jn = j + 1 < ntop ? j + 1 : j;
+    const uint32_t nx = bcast(ax[0], jn), nz = bcast(az[0], jn);  // the next top's first word
+    uint32_t w[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) w[i] = __builtin_popcount((ex[i] ^ tx) | (ez[i] ^ tz));
+    uint32_t pm = min3(w[0], w[1], w[2]);
+#pragma unroll
+    for (int i = 3; i + 1 < K; i += 2) pm = min3(pm, w[i], w[i + 1]);
+    pm = min(pm, w[K - 1]);
+    if (__ballot(pm < thr)) {  // rare once U is small: this top's codewords in full
+      uint32_t rx[D], rz[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        rx[d] = bcast(ax[d], j);
+        rz[d] = bcast(az[d], j);
+      }
+      // One entry at a time, re-read from the table: few registers for a
+      // rare path.
+#pragma unroll 1
+      for (int i = 0; i < K; ++i) {
+        const unsigned long long k = e0 + static_cast<unsigned long long>(i) * kWave + lane;
+        const uint32_t *b = table + (k / kBlock) * (2 * D * kBlock) + (k % kBlock);
+        uint32_t full = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) full = bcnt_acc((b[d * kBlock] ^ rx[d]) | (b[(D + d) * kBlock] ^ rz[d]), full);
+        if constexpr (kCensus) cs.add(full);
+        best = min(best, full);
+      }
+      ++done;
+    }
+    tx = nx;
+    tz = nz;
   }
   return best;
 }
@@ -320,11 +383,12 @@ constexpr uint32_t kXcdChunk = 16;
 // lanes stay full; a lane stops at its own group's prefix length.  A launch
 // holds pieces of the current rounds of several codes (RoundDesc).  With
 // kCensus every piece also takes the census of its codewords below p.below.
-// kEntryMajor: the launch's pieces evaluate every word (no partial weights),
-// and their full blocks go through entry-major blocks first; the kernel then
-// holds more registers, so launches with partial weights keep the streaming
-// loop alone.
-template <int D, bool kCensus, bool kEntryMajor>
+// kMode: kEmEveryWord for launches whose pieces evaluate every word (their
+// full blocks go through entry-major blocks first), kEmPartial for the
+// others (entry-major blocks on the first word where partial weights decide
+// on it).  The two hold different register sets, so each launch takes the
+// one its pieces need.
+template <int D, bool kCensus, int kMode>
 __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   extern __shared__ unsigned long long smem[];
   // Consecutive workgroups land on different XCDs (round robin).  Deal them
@@ -443,9 +507,10 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   Census cs_em;
   if constexpr (kCensus) cs_em.below = static_cast<uint32_t>(p.below);
   const int ntop = static_cast<int>(__popcll(__ballot(active)));
+  uint32_t em_partial = 0, em_done = 0;  // entry-major blocks with partial weights; tops completed in them
   if (W == D) {
     constexpr uint32_t kEm = kWave * EmK<D>::K;
-    const uint32_t nem = kEntryMajor && ntop > 1 ? sfull / kEm : 0u;
+    const uint32_t nem = kMode == kEmEveryWord && ntop > 1 ? sfull / kEm : 0u;
     for (uint32_t bk = 0; bk < nem; ++bk)
       best_em = em_block<D, kCensus>(p.table, k0 + static_cast<unsigned long long>(bk) * kEm, lane, ax, az, ntop,
                                      best_em, cs_em);
@@ -455,7 +520,19 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   } else {
     const int c = p.credit[W - 1];
     const uint32_t thr = U0 > c ? static_cast<uint32_t>(U0 - c) : 0u;
-    if constexpr (D >= 2) {
+    if constexpr (D >= 2 && kMode == kEmPartial) {
+      if (W == 1) {  // entry-major blocks on the first word, then the streaming loop
+        constexpr uint32_t kEm = kWave * kEmPartialK;
+        em_partial = ntop > 1 ? sfull / kEm : 0u;
+        for (uint32_t bk = 0; bk < em_partial; ++bk)
+          best_em = em_block_partial<D, kCensus>(p.table, k0 + static_cast<unsigned long long>(bk) * kEm, lane, ax,
+                                                 az, ntop, best_em, thr, cs_em, em_done);
+        const uint32_t skip = em_partial * kEm / kBlock;
+        best = partial_blocks<D, 1, kCensus>(ax, az, blk + skip * (2 * D * kBlock), nfull - skip, best, thr, rec,
+                                             cs);
+        rec += skip;  // the blocks the entry-major part covered are counted by em_done
+      }
+    } else if constexpr (D >= 2) {
       if (W == 1) best = partial_blocks<D, 1, kCensus>(ax, az, blk, nfull, best, thr, rec, cs);
     }
     if constexpr (D >= 3) {
@@ -488,7 +565,11 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   if (lane == 0) {
     // Words: D per visited codeword, less D - W for those of the full
     // blocks that the partial weights decided.
-    const unsigned long long skipped = static_cast<unsigned long long>(nfull - rec) * kBlock * (D - W) * nact;
+    // Entry-major blocks with partial weights: 64 K codewords per top,
+    // every top not completed skipped D - 1 words for each.
+    const unsigned long long skipped =
+        static_cast<unsigned long long>(nfull - rec) * kBlock * (D - W) * nact +
+        (static_cast<unsigned long long>(em_partial) * nact - em_done) * (kWave * kEmPartialK) * (D - 1);
     unsigned long long *c = p.counters + static_cast<size_t>(wg % kCountersPerCode) * kCounterStride;
     atomicAdd(c, static_cast<unsigned long long>(visited));
     atomicAdd(c + 1, static_cast<unsigned long long>(visited) * D - skipped);
@@ -567,11 +648,11 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
 // -- launch (host) -------------------------------------------------------------
 
 template <int D>
-void launch_round_d(const LaunchParams &lp, bool census, bool em, dim3 grid, dim3 block, hipStream_t s) {
-  if (census && em) hipLaunchKernelGGL((qd_round_kernel<D, true, true>), grid, block, lp.lds, s, lp);
-  else if (census) hipLaunchKernelGGL((qd_round_kernel<D, true, false>), grid, block, lp.lds, s, lp);
-  else if (em) hipLaunchKernelGGL((qd_round_kernel<D, false, true>), grid, block, lp.lds, s, lp);
-  else hipLaunchKernelGGL((qd_round_kernel<D, false, false>), grid, block, lp.lds, s, lp);
+void launch_round_d(const LaunchParams &lp, bool census, bool every_word, dim3 grid, dim3 block, hipStream_t s) {
+  if (census && every_word) hipLaunchKernelGGL((qd_round_kernel<D, true, kEmEveryWord>), grid, block, lp.lds, s, lp);
+  else if (census) hipLaunchKernelGGL((qd_round_kernel<D, true, kEmPartial>), grid, block, lp.lds, s, lp);
+  else if (every_word) hipLaunchKernelGGL((qd_round_kernel<D, false, kEmEveryWord>), grid, block, lp.lds, s, lp);
+  else hipLaunchKernelGGL((qd_round_kernel<D, false, kEmPartial>), grid, block, lp.lds, s, lp);
 }
 
 hipError_t launch_round(int D, const LaunchParams &lp, bool census, bool every_word, hipStream_t s) {
