@@ -592,7 +592,8 @@ def main():
         return
 
     def run(steps, **opts):
-        """`steps` calls on the main code, bracketed by device syncs."""
+        """`steps` calls on the main code, bracketed by device syncs (each call
+        returns after its device work, so s.wall_ms times one call)."""
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = []
@@ -603,6 +604,10 @@ def main():
             out.append((d, s))
         torch.cuda.synchronize()
         return time.perf_counter() - t0, out
+
+    def median_ms(stats):
+        w = sorted(s.wall_ms for _, s in stats)
+        return w[len(w) // 2]
 
     if a.default_only:
         run(a.warmup)
@@ -669,8 +674,10 @@ def main():
                    "packages": list(s0.P)[:s0.h], "delta": list(s0.delta)[:s0.h],
                    "rounds": s0.nlog, "codewords_per_step": combos // a.steps},
         "kernel_codewords_per_s": combos / (kernel_ms * 1e-3),
+        "median_ms_per_step": median_ms(stats),
         "host_ms_per_step": sum(s.host_ms for _, s in stats) / a.steps,
         "time_to_exact_d_ms": ttd_ms,
+        "time_to_exact_d_ms_median": median_ms(stats_d),
         "default_path": {
             "kind": "the library's default path: partial weights decide a codeword from its first words "
                     "plus a pivot credit, completing only blocks that may hold a weight below U",

@@ -276,12 +276,15 @@ int qd_round_census(const uint8_t *rows, const int *dims, int P, int n, int t, i
  * the "saving additions" of Sec. 2.1).  Without tuning the library picks
  * them by fixed rules; qd_tune_run measures them on the current device and
  * installs the fastest per bucket: word count D = 1..4, round size (nearest
- * of 2^20, 2^24, ..., 2^36 combinations), codes sharing a step (1, 2-8,
- * more) and word path (every word evaluated, or partial weights).  For
- * each bucket it times synthetic rounds of random two-row packages under
- * every segment length in {256, 512, 1024, 2048, 4096} and depth cap in
- * {2, 3, 4} (best of two runs after a warm-up; builds, launches and
- * readbacks included).  Installed shapes apply to every later call in the
+ * of 2^20, 2^24, ..., 2^36 combinations) and codes sharing a step (1, 2-8,
+ * more), for rounds that evaluate every word (rounds on partial weights
+ * keep the fixed rules: a synthetic round has no pivot credit, so it does
+ * not measure them faithfully).  For each bucket it times synthetic rounds
+ * of random two-row packages under
+ * every segment length in {64, 128, ..., 4096} and depth cap in {2, 3, 4}
+ * (best of three runs after a warm-up; builds, launches and readbacks
+ * included), and keeps the fixed rules' shape unless a candidate is faster
+ * by more than 3%.  Installed shapes apply to every later call in the
  * process on every device, except the serving engine's (latency first) and
  * calls whose qd_options fix seg_len or saved_depth.  Results do not depend
  * on the shape.  The first GPU call of a process installs the file named by

@@ -171,6 +171,9 @@ unsigned long long plan_round(const GammaDev &g, int t, int u, unsigned seg, boo
 
 }  // namespace
 
+unsigned rule_seg(unsigned long long planned, int sharing) { return choose_seg(planned, sharing, kMinSeg); }
+int rule_depth_cap() { return kDefaultSavedDepth; }
+
 // -- DevPool -------------------------------------------------------------------
 
 DevPool::~DevPool() {

@@ -269,6 +269,9 @@ int default_executor(Executor **ex, std::unique_lock<std::mutex> *lock);
 // bucket.  tune_autoload installs the tuning file once per process.
 bool tune_lookup(int D, unsigned long long planned, int sharing, int partial_words, unsigned *seg, int *depth);
 void tune_autoload();
+// The fixed rules' shape for such a round (no tuning installed).
+unsigned rule_seg(unsigned long long planned, int sharing);
+int rule_depth_cap();
 
 // Runs a set of prepared jobs to completion on one executor.
 int run_jobs(Executor &ex, std::vector<Job *> &jobs, hipStream_t s);
