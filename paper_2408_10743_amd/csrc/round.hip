@@ -250,7 +250,7 @@ __device__ __forceinline__ uint32_t em_block(const uint32_t *__restrict__ table,
 // bound falls below U (thr = U - credit) the 64 K codewords of that top are
 // completed, their remaining words read from the table, and their full
 // weights enter `best` and the census.  `done` counts the completed tops.
-constexpr int kEmPartialK = 16;
+constexpr int kEmPartialK = 8;
 
 template <int D, bool kCensus>
 __device__ __forceinline__ uint32_t em_block_partial(const uint32_t *__restrict__ table, unsigned long long e0,
