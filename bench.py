@@ -47,7 +47,7 @@ PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # scaled by what it reads for a 1 GiB device copy in the same runs), valid
 # only for the kernel source with this fingerprint (sha256 prefixes of
 # round.hip and kernels.hpp, the enumeration kernel and its data layouts).
-TRAFFIC = {"fingerprint": "aae15a77db169ddda38cd37dcef04b3b", "bytes_per_launch": 1210947289}
+TRAFFIC = {"fingerprint": "43ad9ab4c67d65c0a38cd37dcef04b3b", "bytes_per_launch": 763021494}
 
 
 def kernel_fingerprint():
@@ -645,7 +645,7 @@ def main():
     D = stats[0][1].D
     s0 = stats[0][1]
     roof = kernel_roofline([s for _, s in stats], launches)
-    roof["kernel"] = f"qd_round_kernel<{D}, false>"
+    roof["kernel"] = f"qd_round_kernel<{D}, false, every word>"
     roof["traffic"] = TRAFFIC["bytes_per_launch"] if kernel_fingerprint() == TRAFFIC["fingerprint"] else None
     # The library's default path on the same code: time to exact d.
     run(a.warmup)
