@@ -179,7 +179,7 @@ constexpr int kEmEveryWord = 1, kEmPartial = 2;
 // operation with an SGPR operand never pairs.
 template <int D>
 struct EmK {
-  static constexpr int K = D <= 2 ? 16 : D == 3 ? 8 : 4;  // entries per lane (VGPRs: 2D K)
+  static constexpr int K = D == 1 ? 16 : D <= 3 ? 8 : 4;  // entries per lane (VGPRs: 2D K)
 };
 
 __device__ __forceinline__ uint32_t bcast(uint32_t v, int src_lane) {
