@@ -141,6 +141,14 @@ typedef struct qd_options {
                                  Read during the call only.  A code whose matrices do not
                                  match resume->structure, or an invalid point or witness:
                                  QD_ERR_INVALID */
+  int matrix_cores;           /* 0: rounds with a saved table run on the matrix cores
+                                 (fp4 MFMA over +-1 sign vectors, exact: the weight of
+                                 a XOR of two codewords is an affine function of the dot
+                                 product of their signs over x, z and x ^ z), with an
+                                 expanded copy of the table (64 bytes per entry and
+                                 K-step, K-steps = words per half, one less when the last
+                                 word has at most 10 qubits; 1 with partial weights);
+                                 -1: vector ALU only.  Same d and witness rules either way */
 } qd_options;
 
 /* One (t, Gamma_j) round of the enumeration. */
@@ -187,6 +195,7 @@ typedef struct qd_stats {
   unsigned long long structure; /* hash of the generator matrices enumerated (qd_resume) */
   int nlog;                   /* rounds run (entries in log, capped at QD_MAX_LOG) */
   qd_round_log log[QD_MAX_LOG];
+  int matrix_core_launches;   /* of `launches`, those on the matrix cores (qd_options.matrix_cores) */
 } qd_stats;
 
 /* Structure chosen by the host planner (no GPU needed). */

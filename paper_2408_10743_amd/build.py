@@ -8,8 +8,10 @@ LIB = os.path.join(HERE, "libqdist.so")
 SOURCES = ["host.cpp", "engine.cpp", "serve.cpp", "api.cpp", "round.hip", "walk.hip", "support.hip",
            "noalloc.hip", "tune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# -amdgpu-mfma-vgpr-form: MFMA results in VGPRs, which the round kernel's
+# minimum reads next (no copies out of AGPRs).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def build(verbose=False):

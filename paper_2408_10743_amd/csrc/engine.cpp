@@ -10,7 +10,8 @@
 
 namespace qd {
 
-hipError_t launch_round(int D, const LaunchParams &lp, bool census, bool every_word, hipStream_t s);
+hipError_t launch_round(int D, const LaunchParams &lp, bool census, bool every_word, bool mfma, hipStream_t s);
+hipError_t launch_expand(const ExpandParams &ep, hipStream_t s);
 hipError_t launch_walk(int D, const LaunchParams &lp, bool sum, hipStream_t s);
 hipError_t launch_build(int D, const BuildParams &bp, hipStream_t s);
 hipError_t launch_commit(const LaunchParams &lp, hipStream_t s);
@@ -202,6 +203,7 @@ void *DevPool::get(size_t bytes, size_t *cls) {
     const hipError_t me = hipMalloc(&p, slab);
     malloc_ms_ += now_ms() - tm;
     if (me != hipSuccess) {
+      (void)hipGetLastError();  // the failed allocation must not fail a later launch check
       // Give cached blocks of the large classes back to the driver and try
       // once more (slab blocks stay: their slab may be partly in use).
       for (auto &kv : free_) {
@@ -213,7 +215,10 @@ void *DevPool::get(size_t bytes, size_t *cls) {
         }
         kv.second.clear();
       }
-      if (hipMalloc(&p, slab) != hipSuccess) return nullptr;
+      if (hipMalloc(&p, slab) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
     }
     all_.push_back(p);
     held_ += slab;
@@ -292,6 +297,7 @@ Executor::Executor(hipStream_t stream)
   const size_t zb = size_t(2) * 4 * kBlock * sizeof(uint32_t);
   if (hipMalloc(reinterpret_cast<void **>(&zero_table_), zb) != hipSuccess) return;
   if (hipMemset(zero_table_, 0, zb) != hipSuccess) return;
+  mtable_budget_ = prop.totalGlobalMem / 4;
   ok_ = grow_states(64) == QD_OK;
 }
 
@@ -378,7 +384,7 @@ void Executor::prepare(Job &job) {
       o.tops_mode > 2 || (o.filter != QD_FILTER_NONE && o.filter != QD_FILTER_STABILIZER) ||
       (o.scalar_classes != 0 && o.scalar_classes != -1) || (o.partial_weight < -1 || o.partial_weight > 1) ||
       (o.mixed_packages < -1 || o.mixed_packages > 1) || o.walk < 0 || o.walk > kWalkMaxOption ||
-      (o.walk > 0 && o.filter != QD_FILTER_NONE)) {
+      (o.walk > 0 && o.filter != QD_FILTER_NONE) || (o.matrix_cores != 0 && o.matrix_cores != -1)) {
     job.status = QD_ERR_INVALID;
     return;
   }
@@ -463,6 +469,10 @@ void Executor::prepare_gammas(Job &job) {
   // stays.
   job.partial = job.D >= 2 && (job.opt.partial_weight == 1 ||
                                (job.opt.partial_weight == 0 && job.pc.predicted >= kPartialMinWork));
+  // Matrix cores: the last word goes into a spare group when it is short.
+  job.mfma = job.opt.matrix_cores == 0 && job.opt.walk == 0;
+  job.mpack = job.D >= 3 && n - 32 * (job.D - 1) <= kMaxPackedQubits ? 1 : 0;
+  job.mks = job.D - job.mpack;
   for (int j = 0; j < h; ++j) {
     GammaDev &g = job.gd[j];
     const Gamma &gm = job.use[j];
@@ -668,6 +678,49 @@ int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops) {
   return QD_OK;
 }
 
+void Executor::release_mtable(GammaDev &g, int u) {
+  if (g.mtable[u].p) mtable_held_ -= std::min(mtable_held_, g.mtable[u].cls);
+  release(g.mtable[u]);
+  g.mtable_ks[u] = 0;
+}
+
+// Device tables of a job (none in flight).
+void Executor::release_tables(Job &job) {
+  for (GammaDev &g : job.gd)
+    for (int u = 0; u <= kTMax; ++u) {
+      release(g.table[u]);
+      release(g.tops[u]);
+      release_mtable(g, u);
+    }
+}
+
+// Queues the matrix-core form of saved table u (built or queued) with mks
+// K-steps per chunk for the next flush, after the table builds.
+// Without room (the executor's budget for these copies, or device memory)
+// the table keeps no such form and its rounds stay on the vector ALU.
+int Executor::ensure_mtable(Job &job, GammaDev &g, int u, int mks) {
+  if (g.mtable[u].p && g.mtable_ks[u] >= mks) return QD_OK;
+  const unsigned long long nent = g.prefix[size_t(g.P) * g.R + u];
+  const unsigned long long chunks = (nent + kChunk - 1) / kChunk;
+  const size_t bytes = size_t(chunks) * mks * kWave * sizeof(uint4);
+  release_mtable(g, u);
+  if (mtable_held_ + bytes > mtable_budget_ || !alloc(g.mtable[u], bytes)) {
+    release_mtable(g, u);
+    return QD_OK;
+  }
+  mtable_held_ += g.mtable[u].cls;
+  g.mtable_ks[u] = mks;
+  ExpandParams ep;
+  ep.table = static_cast<const uint32_t *>(g.table[u].p);
+  ep.mtable = static_cast<uint4 *>(g.mtable[u].p);
+  ep.nent = nent;
+  ep.D = job.D;
+  ep.mks = mks;
+  ep.pack = job.mpack;
+  expands_.push_back(ep);
+  return QD_OK;
+}
+
 // Sends everything staged since the last step to the device in one copy:
 // state resets and job data (applied by one scatter launch), each piece's
 // groups and runs, the round descriptors (read in place; *desc_off is
@@ -707,7 +760,7 @@ int Executor::flush(hipStream_t s, const unsigned char **base, size_t *desc_off)
   for (int D = 1; D <= 4; ++D) builds_[D].clear();
   for (int *m : level_marks_) *m = -1;
   level_marks_.clear();
-  if (staging_.size() == 0 && descs_.empty() && bl.empty() && recs_.empty()) return QD_OK;
+  if (staging_.size() == 0 && descs_.empty() && bl.empty() && recs_.empty() && expands_.empty()) return QD_OK;
   const size_t need = staging_.size() + align16(descs_.size() * sizeof(RoundDesc)) +
                       align16(bl.size() * sizeof(SavedParams)) + align16(recs_.size() * sizeof(CopyRec));
   if (!alloc(stage_dev_, need)) return QD_ERR_NOMEM;
@@ -746,6 +799,9 @@ int Executor::flush(hipStream_t s, const unsigned char **base, size_t *desc_off)
     bp.lds = lds <= kStageMaxBytes ? lds : 0u;
     if (launch_build(r.D, bp, s) != hipSuccess) return QD_ERR_DEVICE;
   }
+  for (const ExpandParams &ep : expands_)
+    if (launch_expand(ep, s) != hipSuccess) return QD_ERR_DEVICE;
+  expands_.clear();
   *base = dev;
   *desc_off = doff;
   return QD_OK;
@@ -874,6 +930,8 @@ int Executor::schedule(Job &job, int sharing) {
     }
     int rc = f.u > 0 ? ensure_table(job, g, f.u, false) : QD_OK;
     if (!rc && f.use_tops) rc = ensure_table(job, g, t - f.u, true);
+    if (!rc && f.u > 0 && job.mfma && !job.partial && !arena() && !job.force_words && job.census_below == 0)
+      rc = ensure_mtable(job, g, f.u, job.mks);
     if (rc) return rc;
     f.tiles = plan_round(g, t, f.u, f.seg, job.scalar, f.hg, f.hr);
     f.planned = planned;
@@ -956,6 +1014,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
     int D;
     bool walk, sum;  // plain walk kernel; with the weight sum
     bool every_word; // no piece uses partial weights (entry-major kernel)
+    bool mfma;       // every code of the launch may use the matrix cores
     size_t d0, d1;
     unsigned long long tiles;
     unsigned lds;
@@ -975,7 +1034,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   for (int kind = 0; kind < 8; ++kind) {
     const int D = kind % 4 + 1;
     const bool walk = kind >= 4;
-    Launch L{D, walk, false, true, descs_.size(), 0, 0, 0, false};
+    Launch L{D, walk, false, true, !arena(), descs_.size(), 0, 0, 0, false};
     for (Job *jp : jobs) {
       Job &job = *jp;
       if (job.done || job.D != D || job.status || (job.opt.walk > 0) != walk) continue;
@@ -993,6 +1052,12 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         d.elems = g.elems;
         d.table = f.u == 0 ? zero_table_ : static_cast<const uint32_t *>(g.table[f.u].p);
         d.tops = f.use_tops ? static_cast<const uint32_t *>(g.tops[f.t - f.u].p) : nullptr;
+        // The matrix-core form, when it holds the K-steps the piece needs.
+        const int need_ks = job.partial ? 1 : job.mks;
+        d.mtable = f.u > 0 && g.mtable_ks[f.u] >= need_ks ? static_cast<const uint4 *>(g.mtable[f.u].p) : nullptr;
+        d.mks = g.mtable_ks[f.u];
+        d.mpack = job.mpack;
+        if (f.u > 0 && !d.mtable) L.mfma = false;  // that piece needs the vector-ALU kernel
         // groups and runs travel with this step's upload (set by flush)
         const size_t go = staging_.put(f.hg.data(), f.hg.size() * sizeof(DevGroup));
         const size_t ro = staging_.put(f.hr.data(), f.hr.size() * sizeof(DevRun));
@@ -1056,6 +1121,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         L.lds = std::max(L.lds, lds);
         L.timed = L.timed || job.opt.timing;
         L.every_word = L.every_word && !job.partial && !job.force_words;
+        L.mfma = L.mfma && job.mfma && !job.partial && !job.force_words && job.census_below == 0;
         L.tiles += (take + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
         f.sent += take;
         ++f.launches;
@@ -1093,8 +1159,11 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
       lp.lds = L.lds;
       lp.tiles = L.tiles;
       lp.slots = static_cast<uint32_t *>(slots_.p);
+      if (L.mfma && !L.walk)
+        for (size_t d = L.d0; d < L.d1; ++d)
+          if (descs_[d].commit) ++members[d].job->S.matrix_core_launches;
       if (L.timed && hipEventRecord(events_[2 * i], s) != hipSuccess) return QD_ERR_DEVICE;
-      if ((L.walk ? launch_walk(L.D, lp, L.sum, s) : launch_round(L.D, lp, L.sum, L.every_word, s)) != hipSuccess) return QD_ERR_DEVICE;
+      if ((L.walk ? launch_walk(L.D, lp, L.sum, s) : launch_round(L.D, lp, L.sum, L.every_word, L.mfma, s)) != hipSuccess) return QD_ERR_DEVICE;
       if (L.timed && hipEventRecord(events_[2 * i + 1], s) != hipSuccess) return QD_ERR_DEVICE;
       if (launch_commit(lp, s) != hipSuccess) return QD_ERR_DEVICE;
     }
@@ -1136,7 +1205,10 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
       ++k;
     }
     job.fl.erase(job.fl.begin(), job.fl.begin() + long(k));
-    if (job.done) drop_flights(job);
+    if (job.done) {
+      drop_flights(job);
+      release_tables(job);  // other codes of the batch may use the memory
+    }
   }
   return QD_OK;
 }
@@ -1190,8 +1262,8 @@ void Executor::retire(Job &job) {
   for (GammaDev &g : job.gd) {
     g.elems = nullptr; g.csize = nullptr; g.dprefix = g.dsuffix = nullptr;
     g.inv = nullptr; g.logicals = nullptr;
-    for (int u = 0; u <= kTMax; ++u) { release(g.table[u]); release(g.tops[u]); }
   }
+  release_tables(job);
   release(job.data);
   drop_flights(job);
   if (job.state_slot >= 0) free_slots_.push_back(job.state_slot);

@@ -74,11 +74,15 @@ struct GammaDev {
   const uint32_t *logicals = nullptr;    // Modified BZ operators in the stored order
   const unsigned long long *dprefix = nullptr, *dsuffix = nullptr;
   PoolBuf table[kTMax + 1], tops[kTMax + 1];
+  // Matrix-core form of table[u] (RoundDesc::mtable) and its K-steps per chunk.
+  PoolBuf mtable[kTMax + 1];
+  int mtable_ks[kTMax + 1];
   // Launch wave of a table build queued for the next flush (-1: none).
   int table_level[kTMax + 1], tops_level[kTMax + 1];
   GammaDev() {
     for (int &l : table_level) l = -1;
     for (int &l : tops_level) l = -1;
+    for (int &k : mtable_ks) k = 0;
   }
 };
 
@@ -143,6 +147,10 @@ struct Job {
   bool partial = false; // partial weights (matrices stored in their qubit order)
   std::vector<int> caps; // mixed packages: two-row caps of the F4 matrices (empty: none)
   int force_words = 0;   // > 0: every tile evaluates this many words first (no credit)
+  // Matrix cores for the saved-table rounds; mks K-steps per chunk with every
+  // word (the last word packed into a spare group when mpack).
+  bool mfma = false;
+  int mks = 0, mpack = 0;
   // Resume point (copied from qd_options.resume by prepare)
   bool has_resume = false;
   int r_t = 0, r_j = 0, r_U = 0;
@@ -215,6 +223,9 @@ class Executor {
   void end_round(Job &job, Flight &f);
   void drop_flights(Job &job);
   int ensure_table(Job &job, GammaDev &g, int u, bool tops);
+  int ensure_mtable(Job &job, GammaDev &g, int u, int mks);
+  void release_mtable(GammaDev &g, int u);
+  void release_tables(Job &job);
   int flush(hipStream_t s, const unsigned char **base, size_t *desc_off);
   int settle();
   bool alloc(PoolBuf &b, size_t bytes);
@@ -253,6 +264,8 @@ class Executor {
   uint32_t *zero_table_ = nullptr;  // the saved table of depth 0: one zero entry
   std::vector<SavedParams> builds_[5];  // queued table builds per word count
   std::vector<int *> level_marks_;      // table_level entries to clear after the flush
+  std::vector<ExpandParams> expands_;   // queued matrix-core forms (after the builds)
+  size_t mtable_budget_ = 0, mtable_held_ = 0;  // bytes of matrix-core forms: limit, held
   std::vector<RoundDesc> descs_;
   std::vector<size_t> desc_groups_;  // staged offsets of each piece's groups, runs, binomials,
                                      // package map and walk parts (kStagedPerDesc each)

@@ -106,6 +106,22 @@ struct RoundDesc {
   int stage;                           // 1: copy the groups to LDS; 2: also suffix
                                        //    columns and elements (unranking path)
   int commit;                          // 1 for the first piece of its code in the launch
+  // Matrix-core form of the saved table (NULL: the vector-ALU loops only).
+  // Every codeword half-word is read as three groups of 32 signs per word,
+  // x, z and x ^ z (bit 0 -> +1, bit 1 -> -1): two codewords differ in a
+  // group's popcount(a ^ b) positions, so the sign dot product of a group
+  // is 32 - 2 popcount(a ^ b), and over x, z and x ^ z each qubit where
+  // the sum is not identity contributes exactly 2 to the popcounts.  With
+  // G groups, dot = 32 G - 4 wt.  K-step s (128 signs, one MFMA) holds the
+  // groups x_s, z_s, x_s ^ z_s and a fourth group that is empty, or, with
+  // mpack, for s = D - 2 the last word packed as x | z << 10 | (x ^ z) << 20
+  // (at most 10 qubits in it).  mtable: chunk c of 16 entries, K-step s:
+  // 64 lanes x 16 bytes at (c * mks + s) * 64 + lane, lane = 16 g + r for
+  // group g of entry 16 c + r, dword i holding the e2m1 codes of bits
+  // 8i..8i+7 (nibble j: bit 8i + j).  mks: K-steps stored per chunk (1: the
+  // first word only, for partial weights).
+  const uint4 *mtable;
+  int mks, mpack;
   // Census (round kernel, qd_round_census): codewords of weight below
   // `below` are counted in census[0] and their weights summed in census[1]
   // (NULL: not taken).  Partial-weight tiles then complete every block that
@@ -141,6 +157,27 @@ inline unsigned int round_lds_bytes(int P, int t, int u, int ngroups, int stage)
 // LDS bytes a walk kernel launch needs to stage binomials and elements.
 inline unsigned int walk_lds_bytes(int P, int t) {
   return static_cast<unsigned int>((P + 1) * (t + 1) * 8 + P * 3 * kElemWords * 4);
+}
+
+// Matrix-core layout of table entries and tops (RoundDesc::mtable).
+constexpr int kChunk = 16;             // table entries per chunk (MFMA rows)
+constexpr int kMaxPackedQubits = 10;   // last word packed into a spare group
+
+// e2m1 codes of 8 sign bits: nibble j is -1.0 (0xA) for bit j set, +1.0
+// (0x2) otherwise.  Spreads bit j to bit 4j, then to the nibble's sign.
+__device__ __forceinline__ uint32_t sign_nibbles(uint32_t b) {
+  uint32_t x = b & 0xFFu;
+  x = (x | (x << 12)) & 0x000F000Fu;
+  x = (x | (x << 6)) & 0x03030303u;
+  x = (x | (x << 3)) & 0x11111111u;
+  return (x << 3) | 0x22222222u;
+}
+
+// Group g of K-step s of a codeword: x_s, z_s, x_s ^ z_s, or (g = 3) the
+// packed last word (xl, zl) when `packed` (else an empty group).
+__device__ __forceinline__ uint32_t group_word(int g, bool packed, uint32_t x, uint32_t z, uint32_t xl,
+                                               uint32_t zl) {
+  return g == 0 ? x : g == 1 ? z : g == 2 ? x ^ z : packed ? xl | (zl << 10) | ((xl ^ zl) << 20) : 0u;
 }
 
 // XOR of element e of package pkg into a codeword of D words per half.

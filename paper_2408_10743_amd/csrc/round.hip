@@ -319,6 +319,152 @@ __device__ __forceinline__ uint32_t partial_blocks(const uint32_t (&ax)[D], cons
   return best;
 }
 
+// -- matrix cores -------------------------------------------------------------
+// A chunk of kChunk table entries against the wave's 64 tops is four 16x16
+// output blocks; K-step s of each is one fp4 MFMA over 128 signs (layout in
+// kernels.hpp).  Entries are the A rows (lane 16 g + r: row r, group g),
+// tops the B columns (lane 16 g + r: top 16 nb + r of block nb), and lane
+// 16 q + r receives rows 4q..4q+3 of column r.  The tops' signs are
+// negated, so the accumulator starts at C and ends at C - dot: with
+// C = 32 G it is 4 wt, an exact non-negative float whose bits order like
+// the weights.
+constexpr int kMfmaEveryWord = 3, kMfmaPartial = 4;
+typedef int v8i_t __attribute__((ext_vector_type(8)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f_t mfma_fp4(v8i_t a, v8i_t b, v4f_t c) {
+  // e2m1 operands (format 4) on both sides, unit scales (E8M0 127).
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 4, 4, 0, 127, 0, 127);
+}
+
+__device__ __forceinline__ v8i_t mfma_operand(uint4 a) {
+  return (v8i_t){static_cast<int>(a.x), static_cast<int>(a.y), static_cast<int>(a.z), static_cast<int>(a.w), 0, 0, 0,
+                 0};
+}
+
+// B operands of K-steps 0..KU-1 from the wave's tops (lane l holds top l);
+// tops at or past ntop give zero operands.
+template <int D, int KU>
+__device__ __forceinline__ void mfma_tops(const uint32_t (&ax)[D], const uint32_t (&az)[D], uint32_t lane, int ntop,
+                                          bool pack, v8i_t (&B)[KU][4]) {
+  const int g = static_cast<int>(lane >> 4);
+#pragma unroll
+  for (int s = 0; s < KU; ++s)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      const int src = nb * kChunk + static_cast<int>(lane & 15);
+      const bool packed = pack && s == D - 2;
+      const uint32_t x = bcast(ax[s], src), z = bcast(az[s], src);
+      const uint32_t xl = D >= 3 ? bcast(ax[D - 1], src) : 0u, zl = D >= 3 ? bcast(az[D - 1], src) : 0u;
+      const uint32_t w = group_word(g, packed, x, z, xl, zl);
+      const bool on = src < ntop && (g < 3 || packed);
+      const uint32_t neg = 0x88888888u;  // sign bit of every nibble
+      B[s][nb] = (v8i_t){static_cast<int>(on ? sign_nibbles(w) ^ neg : 0u),
+                         static_cast<int>(on ? sign_nibbles(w >> 8) ^ neg : 0u),
+                         static_cast<int>(on ? sign_nibbles(w >> 16) ^ neg : 0u),
+                         static_cast<int>(on ? sign_nibbles(w >> 24) ^ neg : 0u), 0, 0, 0, 0};
+    }
+}
+
+// One chunk, every word: bd[nb] keeps the least 4 wt (as float bits) of
+// the lane's column of block nb.
+template <int KS>
+__device__ __forceinline__ void mfma_chunk_every(const uint4 *__restrict__ mb, const v8i_t (&B)[KS][4], v4f_t c0,
+                                                 uint32_t (&bd)[4]) {
+  v8i_t A[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) A[s] = mfma_operand(mb[s * kWave]);
+  v4f_t acc[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_fp4(A[0], B[0][nb], c0);
+#pragma unroll
+  for (int s = 1; s < KS; ++s)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_fp4(A[s], B[s][nb], acc[nb]);
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    bd[nb] = min(min(bd[nb], __float_as_uint(acc[nb][0])), __float_as_uint(acc[nb][1]));
+    bd[nb] = min(min(bd[nb], __float_as_uint(acc[nb][2])), __float_as_uint(acc[nb][3]));
+  }
+}
+
+// Every word of chunks [cb, ce) of the table against the wave's tops; the
+// least weight over the lane's share of every valid top.
+constexpr int kMfmaUnroll = 2;  // chunks per group of loads
+template <int D, int KS>
+__device__ uint32_t mfma_every(const uint4 *__restrict__ mtab, uint32_t cb, uint32_t ce, uint32_t lane,
+                               const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop, bool pack) {
+  v8i_t B[KS][4];
+  mfma_tops<D, KS>(ax, az, lane, ntop, pack, B);
+  constexpr int G = 3 * KS + (KS < D ? 1 : 0);  // sign groups (packed last word: one)
+  const float cf = static_cast<float>(32 * G);
+  const v4f_t c0 = {cf, cf, cf, cf};
+  uint32_t bd[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+  const uint4 *mb = mtab + static_cast<size_t>(cb) * KS * kWave + lane;
+  uint32_t c = cb;
+  for (; c + kMfmaUnroll <= ce; c += kMfmaUnroll, mb += kMfmaUnroll * KS * kWave) {
+#pragma unroll
+    for (int u = 0; u < kMfmaUnroll; ++u) mfma_chunk_every<KS>(mb + u * KS * kWave, B, c0, bd);
+  }
+  for (; c < ce; ++c, mb += KS * kWave) mfma_chunk_every<KS>(mb, B, c0, bd);
+  uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb)
+    if (nb * kChunk + static_cast<int>(lane & 15) < ntop && bd[nb] != 0xFFFFFFFFu)
+      best = min(best, static_cast<uint32_t>(__uint_as_float(bd[nb])) >> 2);
+  return best;
+}
+
+// Partial weights on the first word, chunks [cb, ce): K-step 0 alone gives
+// 4 w0 (C = 96: the three groups of word 0); a chunk where some lane sees
+// w0 below thr is completed on the vector ALU (the lane's own top against
+// the chunk's two blocks, every word) and counted in `done`.
+template <int D, bool kCensus>
+__device__ uint32_t mfma_partial(const uint32_t *__restrict__ table, const uint4 *__restrict__ mtab, int mks,
+                                 uint32_t cb, uint32_t ce, uint32_t lane, const uint32_t (&ax)[D],
+                                 const uint32_t (&az)[D], int ntop, bool pack, uint32_t thr, uint32_t best,
+                                 uint32_t &done, Census &cs) {
+  v8i_t B[1][4];
+  mfma_tops<D, 1>(ax, az, lane, ntop, pack, B);
+  const v4f_t c0 = {96.0f, 96.0f, 96.0f, 96.0f};
+  const uint32_t T = __float_as_uint(static_cast<float>(4 * thr));
+  const size_t stride = static_cast<size_t>(mks) * kWave;
+  const uint4 *mb = mtab + static_cast<size_t>(cb) * stride + lane;
+  for (uint32_t c = cb; c < ce; c += kMfmaUnroll, mb += kMfmaUnroll * stride) {
+    const int nu = min(kMfmaUnroll, static_cast<int>(ce - c));
+    uint32_t pm[kMfmaUnroll];
+#pragma unroll
+    for (int u = 0; u < kMfmaUnroll; ++u) {
+      pm[u] = 0xFFFFFFFFu;
+      if (u < nu) {
+        const v8i_t A = mfma_operand(mb[u * stride]);
+        v4f_t acc[4];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_fp4(A, B[0][nb], c0);
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          pm[u] = min(min(pm[u], __float_as_uint(acc[nb][0])), __float_as_uint(acc[nb][1]));
+          pm[u] = min(min(pm[u], __float_as_uint(acc[nb][2])), __float_as_uint(acc[nb][3]));
+        }
+      }
+    }
+    uint32_t any = pm[0];
+#pragma unroll
+    for (int u = 1; u < kMfmaUnroll; ++u) any = min(any, pm[u]);
+    if (__ballot(any < T)) {  // rare once U is small
+#pragma unroll 1
+      for (int u = 0; u < nu; ++u) {
+        if (!__ballot(pm[u] < T)) continue;
+        const uint32_t *blk = table + static_cast<size_t>(c + u) * (kChunk / kBlock) * (2 * D * kBlock);
+        best = block_min<D, kCensus>(ax, az, blk, best, cs);
+        best = block_min<D, kCensus>(ax, az, blk + 2 * D * kBlock, best, cs);
+        ++done;
+      }
+    }
+  }
+  return best;
+}
+
 // A tile's witness slot: the codeword in the matrix's stored qubit order
 // (the commit kernel maps it back to qubit order).
 template <int D>
@@ -508,7 +654,42 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   if constexpr (kCensus) cs_em.below = static_cast<uint32_t>(p.below);
   const int ntop = static_cast<int>(__popcll(__ballot(active)));
   uint32_t em_partial = 0, em_done = 0;  // entry-major blocks with partial weights; tops completed in them
-  if (W == D) {
+  // Matrix cores: chunks [ca, cz) of kChunk entries inside the full blocks;
+  // the full blocks before and after them (at most one each) stay on the
+  // vector ALU.
+  constexpr bool kMfma = kMode == kMfmaEveryWord || kMode == kMfmaPartial;
+  uint32_t ca = 0, cz = 0, mf_done = 0;
+  if (kMfma && p.mtable) {
+    const uint32_t c_lo = static_cast<uint32_t>((k0 + kChunk - 1) / kChunk);
+    const uint32_t c_hi = static_cast<uint32_t>((k0 + nfull * kBlock) / kChunk);
+    if (c_hi > c_lo && (kMode == kMfmaEveryWord ? W == D : W == 1)) {
+      ca = __builtin_amdgcn_readfirstlane(c_lo);
+      cz = __builtin_amdgcn_readfirstlane(c_hi);
+    }
+  }
+  const uint32_t head = static_cast<uint32_t>((static_cast<unsigned long long>(ca) * kChunk - k0) / kBlock);
+  const uint32_t mid = (cz - ca) * (kChunk / kBlock);  // full blocks on the matrix cores
+  if (kMfma && mid > 0) {
+    if constexpr (kMode == kMfmaEveryWord) {
+      if (D >= 3 && p.mpack)
+        best_em = mfma_every<D, (D >= 3 ? D - 1 : D)>(p.mtable, ca, cz, lane, ax, az, ntop, true);
+      else
+        best_em = mfma_every<D, D>(p.mtable, ca, cz, lane, ax, az, ntop, false);
+      for (uint32_t i = 0; i < head; ++i, blk += 2 * D * kBlock) best = block_min<D, kCensus>(ax, az, blk, best, cs);
+      blk += mid * (2 * D * kBlock);
+      for (uint32_t i = head + mid; i < nfull; ++i, blk += 2 * D * kBlock)
+        best = block_min<D, kCensus>(ax, az, blk, best, cs);
+    } else if constexpr (D >= 2) {
+      const int c = p.credit[0];
+      const uint32_t thr = U0 > c ? static_cast<uint32_t>(U0 - c) : 0u;
+      best = mfma_partial<D, kCensus>(p.table, p.mtable, p.mks, ca, cz, lane, ax, az, ntop, p.mpack != 0, thr, best,
+                                      mf_done, cs);
+      best = partial_blocks<D, 1, kCensus>(ax, az, blk, head, best, thr, rec, cs);
+      best = partial_blocks<D, 1, kCensus>(ax, az, blk + (head + mid) * (2 * D * kBlock), nfull - head - mid, best,
+                                           thr, rec, cs);
+      rec += mid;  // the matrix-core blocks are counted by mf_done
+    }
+  } else if (W == D) {
     constexpr uint32_t kEm = kWave * EmK<D>::K;
     const uint32_t nem = kMode == kEmEveryWord && ntop > 1 ? sfull / kEm : 0u;
     for (uint32_t bk = 0; bk < nem; ++bk)
@@ -569,7 +750,8 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
     // every top not completed skipped D - 1 words for each.
     const unsigned long long skipped =
         static_cast<unsigned long long>(nfull - rec) * kBlock * (D - W) * nact +
-        (static_cast<unsigned long long>(em_partial) * nact - em_done) * (kWave * kEmPartialK) * (D - 1);
+        (static_cast<unsigned long long>(em_partial) * nact - em_done) * (kWave * kEmPartialK) * (D - 1) +
+        (kMode == kMfmaPartial ? static_cast<unsigned long long>(cz - ca - mf_done) * kChunk * nact * (D - 1) : 0ull);
     unsigned long long *c = p.counters + static_cast<size_t>(wg % kCountersPerCode) * kCounterStride;
     atomicAdd(c, static_cast<unsigned long long>(visited));
     atomicAdd(c + 1, static_cast<unsigned long long>(visited) * D - skipped);
@@ -648,22 +830,27 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
 // -- launch (host) -------------------------------------------------------------
 
 template <int D>
-void launch_round_d(const LaunchParams &lp, bool census, bool every_word, dim3 grid, dim3 block, hipStream_t s) {
-  if (census && every_word) hipLaunchKernelGGL((qd_round_kernel<D, true, kEmEveryWord>), grid, block, lp.lds, s, lp);
+void launch_round_d(const LaunchParams &lp, bool census, bool every_word, bool mfma, dim3 grid, dim3 block,
+                    hipStream_t s) {
+  if (mfma && !census && every_word)
+    hipLaunchKernelGGL((qd_round_kernel<D, false, kMfmaEveryWord>), grid, block, lp.lds, s, lp);
+  else if (mfma && !census && D >= 2)
+    hipLaunchKernelGGL((qd_round_kernel<D, false, kMfmaPartial>), grid, block, lp.lds, s, lp);
+  else if (census && every_word) hipLaunchKernelGGL((qd_round_kernel<D, true, kEmEveryWord>), grid, block, lp.lds, s, lp);
   else if (census) hipLaunchKernelGGL((qd_round_kernel<D, true, kEmPartial>), grid, block, lp.lds, s, lp);
   else if (every_word) hipLaunchKernelGGL((qd_round_kernel<D, false, kEmEveryWord>), grid, block, lp.lds, s, lp);
   else hipLaunchKernelGGL((qd_round_kernel<D, false, kEmPartial>), grid, block, lp.lds, s, lp);
 }
 
-hipError_t launch_round(int D, const LaunchParams &lp, bool census, bool every_word, hipStream_t s) {
+hipError_t launch_round(int D, const LaunchParams &lp, bool census, bool every_word, bool mfma, hipStream_t s) {
   unsigned long long wgs = lp.tiles / kWavesPerGroup;
   wgs = (wgs + 8 * kXcdChunk - 1) / (8 * kXcdChunk) * (8 * kXcdChunk);  // the XCD dealing is a bijection
   dim3 grid(static_cast<uint32_t>(wgs)), block(kWave * kWavesPerGroup);
   switch (D) {
-    case 1: launch_round_d<1>(lp, census, every_word, grid, block, s); break;
-    case 2: launch_round_d<2>(lp, census, every_word, grid, block, s); break;
-    case 3: launch_round_d<3>(lp, census, every_word, grid, block, s); break;
-    case 4: launch_round_d<4>(lp, census, every_word, grid, block, s); break;
+    case 1: launch_round_d<1>(lp, census, every_word, mfma, grid, block, s); break;
+    case 2: launch_round_d<2>(lp, census, every_word, mfma, grid, block, s); break;
+    case 3: launch_round_d<3>(lp, census, every_word, mfma, grid, block, s); break;
+    case 4: launch_round_d<4>(lp, census, every_word, mfma, grid, block, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -116,6 +116,31 @@ __global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
 // codeword of the winning slot into the code's state, in qubit order, and
 // folds the code's spread counters into its visited and evaluated-word
 // counts.
+// Matrix-core form of a saved table (ExpandParams): thread t writes the 16
+// bytes of lane t % 64 of (chunk, K-step) t / 64, so a wave writes one
+// contiguous kilobyte.
+__global__ __launch_bounds__(256) void qd_expand_kernel(ExpandParams ep) {
+  const unsigned long long t = static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const unsigned long long nchunk = (ep.nent + kChunk - 1) / kChunk;
+  if (t >= nchunk * ep.mks * kWave) return;
+  const int lane = static_cast<int>(t % kWave), g = lane / kChunk;
+  const int s = static_cast<int>((t / kWave) % ep.mks);
+  const unsigned long long e = (t / (static_cast<unsigned long long>(kWave) * ep.mks)) * kChunk + lane % kChunk;
+  const bool packed = ep.pack && s == ep.D - 2;
+  uint4 o = {0u, 0u, 0u, 0u};
+  if (e < ep.nent && (g < 3 || packed)) {
+    const int D = ep.D;
+    const uint32_t *b = ep.table + (e / kBlock) * (2 * D * kBlock) + e % kBlock;
+    const uint32_t w = group_word(g, packed, b[s * kBlock], b[(D + s) * kBlock], b[(D - 1) * kBlock],
+                                  b[(2 * D - 1) * kBlock]);
+    o.x = sign_nibbles(w);
+    o.y = sign_nibbles(w >> 8);
+    o.z = sign_nibbles(w >> 16);
+    o.w = sign_nibbles(w >> 24);
+  }
+  ep.mtable[t] = o;
+}
+
 __global__ __launch_bounds__(256) void qd_commit_kernel(LaunchParams lp) {
   __shared__ unsigned long long part[2][256];
   const RoundDesc &p = lp.desc[blockIdx.x];
@@ -313,6 +338,13 @@ hipError_t launch_build(int D, const BuildParams &bp, hipStream_t s) {
 
 hipError_t launch_commit(const LaunchParams &lp, hipStream_t s) {
   hipLaunchKernelGGL(qd_commit_kernel, dim3(lp.ndesc), dim3(256), 0, s, lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const ExpandParams &ep, hipStream_t s) {
+  const unsigned long long threads = (ep.nent + kChunk - 1) / kChunk * ep.mks * kWave;
+  if (threads == 0) return hipSuccess;
+  hipLaunchKernelGGL(qd_expand_kernel, dim3(static_cast<uint32_t>((threads + 255) / 256)), dim3(256), 0, s, ep);
   return hipGetLastError();
 }
 

@@ -61,6 +61,15 @@ constexpr unsigned long long kEsymTables = ~0ull - 1;
 constexpr unsigned long long kEsymSat = 1ull << 62;
 constexpr int kMaxEsymPackages = 256;  // packages per e_r table record; R <= kWave
 
+// Matrix-core form of one saved table (RoundDesc::mtable): chunks of
+// kChunk entries, `mks` K-steps each; entries at or past nent read as zero.
+struct ExpandParams {
+  const uint32_t *table;               // saved table, blocks of kBlock entries
+  uint4 *mtable;                       // ceil(nent / kChunk) * mks * 64 uint4
+  unsigned long long nent;
+  int D, mks, pack;
+};
+
 __host__ __device__ inline unsigned int build_lds_bytes(int P, int u) { return static_cast<unsigned int>((P + 1) * (u + 1) * 8); }
 
 }  // namespace qd

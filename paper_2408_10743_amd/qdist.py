@@ -56,7 +56,7 @@ class qd_options(ctypes.Structure):
                 ("saved_depth", ctypes.c_int), ("timing", ctypes.c_int), ("tops_mode", ctypes.c_int),
                 ("filter", ctypes.c_int), ("scalar_classes", ctypes.c_int),
                 ("partial_weight", ctypes.c_int), ("mixed_packages", ctypes.c_int), ("walk", ctypes.c_int),
-                ("resume", ctypes.POINTER(qd_resume))]
+                ("resume", ctypes.POINTER(qd_resume)), ("matrix_cores", ctypes.c_int)]
 
 
 class qd_round_log(ctypes.Structure):
@@ -79,7 +79,7 @@ class qd_stats(ctypes.Structure):
                 ("scalar_classes", ctypes.c_int), ("two_row_cap", ctypes.c_int * QD_MAX_GAMMA),
                 ("next_t", ctypes.c_int), ("next_j", ctypes.c_int), ("structure", ctypes.c_ulonglong),
                 ("nlog", ctypes.c_int),
-                ("log", qd_round_log * QD_MAX_LOG)]
+                ("log", qd_round_log * QD_MAX_LOG), ("matrix_core_launches", ctypes.c_int)]
 
     def rounds(self):
         out = []
@@ -208,7 +208,7 @@ def qd_distance_ex(G, field=QD_FIELD_F2, **opts):
     """Returns (status, d, witness, qd_stats).  Options: diag, max_gamma,
     budget, cancel (ctypes.c_int), stream (hipStream_t as int), seg_len,
     saved_depth, timing, tops_mode, filter, scalar_classes, partial_weight,
-    mixed_packages, walk, resume (a resume_point tuple)."""
+    mixed_packages, walk, resume (a resume_point tuple), matrix_cores."""
     G, m, n = _matrix(G, field)
     o, _keep = _options(opts)
     d = ctypes.c_int(-1)

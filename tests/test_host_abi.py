@@ -175,6 +175,15 @@ def test_partial_weight_option_validation(Q):
         assert st == Q.QD_ERR_INVALID and d == -1, v
 
 
+def test_matrix_cores_option_validation(Q):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    for v in (1, -2, 7):
+        st, d, _, _ = Q.qd_distance_ex(*W.config2(0), matrix_cores=v)
+        assert st == Q.QD_ERR_INVALID and d == -1, v
+
+
 def test_alpha_closed_binary_input_uses_scalar_classes(Q):
     # a binary input whose span is closed under alpha is F4-linear: the F4
     # prediction counts one codeword per scalar class, as for F4 input
