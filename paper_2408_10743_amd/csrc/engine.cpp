@@ -930,8 +930,8 @@ int Executor::schedule(Job &job, int sharing) {
     }
     int rc = f.u > 0 ? ensure_table(job, g, f.u, false) : QD_OK;
     if (!rc && f.use_tops) rc = ensure_table(job, g, t - f.u, true);
-    if (!rc && f.u > 0 && job.mfma && !job.partial && !arena() && !job.force_words && job.census_below == 0)
-      rc = ensure_mtable(job, g, f.u, job.mks);
+    if (!rc && f.u > 0 && job.mfma && !arena() && !job.force_words && job.census_below == 0)
+      rc = ensure_mtable(job, g, f.u, job.partial ? 1 : job.mks);
     if (rc) return rc;
     f.tiles = plan_round(g, t, f.u, f.seg, job.scalar, f.hg, f.hr);
     f.planned = planned;
@@ -1121,7 +1121,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         L.lds = std::max(L.lds, lds);
         L.timed = L.timed || job.opt.timing;
         L.every_word = L.every_word && !job.partial && !job.force_words;
-        L.mfma = L.mfma && job.mfma && !job.partial && !job.force_words && job.census_below == 0;
+        L.mfma = L.mfma && job.mfma && !job.force_words && job.census_below == 0;
         L.tiles += (take + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
         f.sent += take;
         ++f.launches;

@@ -366,14 +366,11 @@ __device__ __forceinline__ void mfma_tops(const uint32_t (&ax)[D], const uint32_
     }
 }
 
-// One chunk, every word: bd[nb] keeps the least 4 wt (as float bits) of
-// the lane's column of block nb.
+// One chunk, every word, from its A operands: bd[nb] keeps the least 4 wt
+// (as float bits) of the lane's column of block nb.
 template <int KS>
-__device__ __forceinline__ void mfma_chunk_every(const uint4 *__restrict__ mb, const v8i_t (&B)[KS][4], v4f_t c0,
+__device__ __forceinline__ void mfma_every_chunk(const v8i_t (&A)[KS], const v8i_t (&B)[KS][4], v4f_t c0,
                                                  uint32_t (&bd)[4]) {
-  v8i_t A[KS];
-#pragma unroll
-  for (int s = 0; s < KS; ++s) A[s] = mfma_operand(mb[s * kWave]);
   v4f_t acc[4];
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_fp4(A[0], B[0][nb], c0);
@@ -388,25 +385,100 @@ __device__ __forceinline__ void mfma_chunk_every(const uint4 *__restrict__ mb, c
   }
 }
 
-// Every word of chunks [cb, ce) of the table against the wave's tops; the
-// least weight over the lane's share of every valid top.
-constexpr int kMfmaUnroll = 2;  // chunks per group of loads
+// One chunk on K-step 0: the least 4 w0 over the chunk's 16 x 64 outputs.
+__device__ __forceinline__ uint32_t mfma_first_chunk(v8i_t A, const v8i_t (&B)[1][4], v4f_t c0) {
+  v4f_t acc[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_fp4(A, B[0][nb], c0);
+  uint32_t pm = 0xFFFFFFFFu;
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    pm = min(min(pm, __float_as_uint(acc[nb][0])), __float_as_uint(acc[nb][1]));
+    pm = min(min(pm, __float_as_uint(acc[nb][2])), __float_as_uint(acc[nb][3]));
+  }
+  return pm;
+}
+
+// Chunks shared by the four waves of a workgroup (same table segment):
+// they stream through LDS in groups of kCoopChunks, double-buffered, each
+// thread moving 16 bytes per K-step, so a chunk is read from memory once
+// for the workgroup's 256 tops instead of once per wave.  Group g + 1 is
+// loaded while group g is evaluated; one barrier per group.
+constexpr int kCoopChunks = 4;  // kCoopChunks * kWave = threads of a workgroup
+
+template <int KU>
+struct CoopStream {
+  static constexpr int kPer = kCoopChunks * KU * kWave;  // uint4 per buffer
+  uint4 r[KU];
+  __device__ __forceinline__ void load(const uint4 *__restrict__ mtab, int mks, uint32_t c0, uint32_t nu) {
+    const int t = static_cast<int>(threadIdx.x);
+#pragma unroll
+    for (int q = 0; q < KU; ++q) {
+      const int idx = q * kWavesPerGroup * kWave + t;
+      const uint32_t u = static_cast<uint32_t>(idx / (KU * kWave));
+      const int s = (idx / kWave) % KU;
+      r[q] = u < nu ? mtab[(static_cast<size_t>(c0 + u) * mks + s) * kWave + (idx % kWave)] : uint4{0u, 0u, 0u, 0u};
+    }
+  }
+  __device__ __forceinline__ void store(uint4 *buf) const {
+#pragma unroll
+    for (int q = 0; q < KU; ++q) buf[q * kWavesPerGroup * kWave + threadIdx.x] = r[q];
+  }
+};
+
+// Every word of chunks [ca, cz) against the wave's tops, chunks [ca, cs)
+// shared with the workgroup (coop; sbuf: 2 x kCoopChunks x KS x 64 uint4);
+// the least weight over the lane's share of every valid top.
+constexpr int kMfmaUnroll = 2;  // chunks per group of loads (a wave alone)
 template <int D, int KS>
-__device__ uint32_t mfma_every(const uint4 *__restrict__ mtab, uint32_t cb, uint32_t ce, uint32_t lane,
-                               const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop, bool pack) {
+__device__ uint32_t mfma_every(const uint4 *__restrict__ mtab, uint32_t ca, uint32_t cs, uint32_t cz, bool coop,
+                               uint4 *sbuf, uint32_t lane, const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop,
+                               bool pack) {
   v8i_t B[KS][4];
   mfma_tops<D, KS>(ax, az, lane, ntop, pack, B);
   constexpr int G = 3 * KS + (KS < D ? 1 : 0);  // sign groups (packed last word: one)
   const float cf = static_cast<float>(32 * G);
   const v4f_t c0 = {cf, cf, cf, cf};
   uint32_t bd[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-  const uint4 *mb = mtab + static_cast<size_t>(cb) * KS * kWave + lane;
-  uint32_t c = cb;
-  for (; c + kMfmaUnroll <= ce; c += kMfmaUnroll, mb += kMfmaUnroll * KS * kWave) {
+  uint32_t c = ca;
+  if (coop) {
+    CoopStream<KS> st;
+    constexpr int kPer = CoopStream<KS>::kPer;
+    st.load(mtab, KS, c, min(kCoopChunks, static_cast<int>(cs - c)));
+    st.store(sbuf);
+    __syncthreads();
+    for (int g = 0; c < cs; ++g, c += kCoopChunks) {
+      const uint32_t nu = min(kCoopChunks, static_cast<int>(cs - c));
+      const bool more = c + kCoopChunks < cs;
+      if (more) st.load(mtab, KS, c + kCoopChunks, min(kCoopChunks, static_cast<int>(cs - c - kCoopChunks)));
+      const uint4 *cur = sbuf + (g & 1) * kPer;
+      for (uint32_t u = 0; u < nu; ++u) {
+        v8i_t A[KS];
 #pragma unroll
-    for (int u = 0; u < kMfmaUnroll; ++u) mfma_chunk_every<KS>(mb + u * KS * kWave, B, c0, bd);
+        for (int s = 0; s < KS; ++s) A[s] = mfma_operand(cur[(u * KS + s) * kWave + lane]);
+        mfma_every_chunk<KS>(A, B, c0, bd);
+      }
+      if (more) st.store(sbuf + ((g + 1) & 1) * kPer);
+      __syncthreads();
+    }
+    c = cs;  // the last group may be short
   }
-  for (; c < ce; ++c, mb += KS * kWave) mfma_chunk_every<KS>(mb, B, c0, bd);
+  const uint4 *mb = mtab + static_cast<size_t>(c) * KS * kWave + lane;
+  for (; c + kMfmaUnroll <= cz; c += kMfmaUnroll, mb += kMfmaUnroll * KS * kWave) {
+#pragma unroll
+    for (int u = 0; u < kMfmaUnroll; ++u) {
+      v8i_t A[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) A[s] = mfma_operand(mb[(u * KS + s) * kWave]);
+      mfma_every_chunk<KS>(A, B, c0, bd);
+    }
+  }
+  for (; c < cz; ++c, mb += KS * kWave) {
+    v8i_t A[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) A[s] = mfma_operand(mb[s * kWave]);
+    mfma_every_chunk<KS>(A, B, c0, bd);
+  }
   uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb)
@@ -415,52 +487,70 @@ __device__ uint32_t mfma_every(const uint4 *__restrict__ mtab, uint32_t cb, uint
   return best;
 }
 
-// Partial weights on the first word, chunks [cb, ce): K-step 0 alone gives
+// Partial weights on the first word, chunks [ca, cz) ([ca, cs) shared with
+// the workgroup, sbuf: 2 x kCoopChunks x 64 uint4): K-step 0 alone gives
 // 4 w0 (C = 96: the three groups of word 0); a chunk where some lane sees
 // w0 below thr is completed on the vector ALU (the lane's own top against
 // the chunk's two blocks, every word) and counted in `done`.
 template <int D, bool kCensus>
+__device__ __forceinline__ uint32_t complete_chunks(const uint32_t *__restrict__ table, uint32_t c, int nu,
+                                                    const uint32_t *pm, uint32_t T, const uint32_t (&ax)[D],
+                                                    const uint32_t (&az)[D], uint32_t best, uint32_t &done,
+                                                    Census &cs) {
+#pragma unroll 1
+  for (int u = 0; u < nu; ++u) {
+    if (!__ballot(pm[u] < T)) continue;
+    const uint32_t *blk = table + static_cast<size_t>(c + u) * (kChunk / kBlock) * (2 * D * kBlock);
+    best = block_min<D, kCensus>(ax, az, blk, best, cs);
+    best = block_min<D, kCensus>(ax, az, blk + 2 * D * kBlock, best, cs);
+    ++done;
+  }
+  return best;
+}
+
+template <int D, bool kCensus>
 __device__ uint32_t mfma_partial(const uint32_t *__restrict__ table, const uint4 *__restrict__ mtab, int mks,
-                                 uint32_t cb, uint32_t ce, uint32_t lane, const uint32_t (&ax)[D],
-                                 const uint32_t (&az)[D], int ntop, bool pack, uint32_t thr, uint32_t best,
-                                 uint32_t &done, Census &cs) {
+                                 uint32_t ca, uint32_t cs_end, uint32_t cz, bool coop, uint4 *sbuf, uint32_t lane,
+                                 const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop, bool pack, uint32_t thr,
+                                 uint32_t best, uint32_t &done, Census &cs) {
   v8i_t B[1][4];
   mfma_tops<D, 1>(ax, az, lane, ntop, pack, B);
   const v4f_t c0 = {96.0f, 96.0f, 96.0f, 96.0f};
   const uint32_t T = __float_as_uint(static_cast<float>(4 * thr));
+  uint32_t c = ca;
+  if (coop) {
+    CoopStream<1> st;
+    constexpr int kPer = CoopStream<1>::kPer;
+    st.load(mtab, mks, c, min(kCoopChunks, static_cast<int>(cs_end - c)));
+    st.store(sbuf);
+    __syncthreads();
+    for (int g = 0; c < cs_end; ++g, c += kCoopChunks) {
+      const int nu = min(kCoopChunks, static_cast<int>(cs_end - c));
+      const bool more = c + kCoopChunks < cs_end;
+      if (more) st.load(mtab, mks, c + kCoopChunks, min(kCoopChunks, static_cast<int>(cs_end - c - kCoopChunks)));
+      const uint4 *cur = sbuf + (g & 1) * kPer;
+      uint32_t pm[kCoopChunks];
+#pragma unroll
+      for (int u = 0; u < kCoopChunks; ++u)
+        pm[u] = u < nu ? mfma_first_chunk(mfma_operand(cur[u * kWave + lane]), B, c0) : 0xFFFFFFFFu;
+      const uint32_t any = min(min(pm[0], pm[1]), min(pm[2], pm[3]));
+      if (__ballot(any < T)) best = complete_chunks<D, kCensus>(table, c, nu, pm, T, ax, az, best, done, cs);
+      if (more) st.store(sbuf + ((g + 1) & 1) * kPer);
+      __syncthreads();
+    }
+    c = cs_end;  // the last group may be short
+  }
   const size_t stride = static_cast<size_t>(mks) * kWave;
-  const uint4 *mb = mtab + static_cast<size_t>(cb) * stride + lane;
-  for (uint32_t c = cb; c < ce; c += kMfmaUnroll, mb += kMfmaUnroll * stride) {
-    const int nu = min(kMfmaUnroll, static_cast<int>(ce - c));
+  const uint4 *mb = mtab + static_cast<size_t>(c) * stride + lane;
+  for (; c < cz; c += kMfmaUnroll, mb += kMfmaUnroll * stride) {
+    const int nu = min(kMfmaUnroll, static_cast<int>(cz - c));
     uint32_t pm[kMfmaUnroll];
 #pragma unroll
-    for (int u = 0; u < kMfmaUnroll; ++u) {
-      pm[u] = 0xFFFFFFFFu;
-      if (u < nu) {
-        const v8i_t A = mfma_operand(mb[u * stride]);
-        v4f_t acc[4];
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_fp4(A, B[0][nb], c0);
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-          pm[u] = min(min(pm[u], __float_as_uint(acc[nb][0])), __float_as_uint(acc[nb][1]));
-          pm[u] = min(min(pm[u], __float_as_uint(acc[nb][2])), __float_as_uint(acc[nb][3]));
-        }
-      }
-    }
+    for (int u = 0; u < kMfmaUnroll; ++u) pm[u] = u < nu ? mfma_first_chunk(mfma_operand(mb[u * stride]), B, c0) : 0xFFFFFFFFu;
     uint32_t any = pm[0];
 #pragma unroll
     for (int u = 1; u < kMfmaUnroll; ++u) any = min(any, pm[u]);
-    if (__ballot(any < T)) {  // rare once U is small
-#pragma unroll 1
-      for (int u = 0; u < nu; ++u) {
-        if (!__ballot(pm[u] < T)) continue;
-        const uint32_t *blk = table + static_cast<size_t>(c + u) * (kChunk / kBlock) * (2 * D * kBlock);
-        best = block_min<D, kCensus>(ax, az, blk, best, cs);
-        best = block_min<D, kCensus>(ax, az, blk + 2 * D * kBlock, best, cs);
-        ++done;
-      }
-    }
+    if (__ballot(any < T)) best = complete_chunks<D, kCensus>(table, c, nu, pm, T, ax, az, best, done, cs);
   }
   return best;
 }
@@ -548,6 +638,13 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   if (wtile >= lp.tiles) return;  // whole workgroup: launch padding
   const RoundDesc *const descs = lp.desc;
   const RoundDesc &p = descs[wave_last_le(lp.ndesc, wtile, [descs](int i) { return descs[i].tile_begin; })];
+  // Matrix cores: each wave's shared-chunk range (first chunk << 32 | end),
+  // ~0 for a wave that takes no part; chunk buffers of the workgroup.
+  constexpr bool kMfma = kMode == kMfmaEveryWord || kMode == kMfmaPartial;
+  constexpr int kCoopLds = kMfma ? 2 * kCoopChunks * (kMode == kMfmaPartial ? 1 : D) * kWave : 1;
+  __shared__ unsigned long long coop_slot[kWavesPerGroup];
+  __shared__ uint4 coop_buf[kCoopLds];
+  if (kMfma && (threadIdx.x & (kWave - 1)) == 0) coop_slot[threadIdx.x / kWave] = ~0ull;
 
   // Unranking reads suffix columns, the group table and the elements with
   // data-dependent addresses: stage them in LDS once per workgroup.
@@ -569,8 +666,9 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
       E = sE;
       ld = C;
     }
-    __syncthreads();
+    if constexpr (!kMfma) __syncthreads();
   }
+  if constexpr (kMfma) __syncthreads();  // staged tables; every wave's coop_slot cleared
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const unsigned long long local = wtile + wave - p.tile_begin;  // tile within the piece
@@ -657,7 +755,6 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   // Matrix cores: chunks [ca, cz) of kChunk entries inside the full blocks;
   // the full blocks before and after them (at most one each) stay on the
   // vector ALU.
-  constexpr bool kMfma = kMode == kMfmaEveryWord || kMode == kMfmaPartial;
   uint32_t ca = 0, cz = 0, mf_done = 0;
   if (kMfma && p.mtable) {
     const uint32_t c_lo = static_cast<uint32_t>((k0 + kChunk - 1) / kChunk);
@@ -667,14 +764,33 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
       cz = __builtin_amdgcn_readfirstlane(c_hi);
     }
   }
+  // The workgroup's four waves share chunks [ca, cs) when all of them take
+  // part from the same first chunk (the same table segment).
+  uint32_t cs_end = ca;
+  bool coop = false;
+  if constexpr (kMfma) {
+    if (lane == 0 && cz > ca) coop_slot[wave] = (static_cast<unsigned long long>(ca) << 32) | cz;
+    __syncthreads();  // the waves that returned early left ~0
+    coop = cz > ca;
+    cs_end = cz;
+#pragma unroll
+    for (int w = 0; w < kWavesPerGroup; ++w) {
+      const unsigned long long v = coop_slot[w];
+      coop = coop && v != ~0ull && static_cast<uint32_t>(v >> 32) == ca;
+      cs_end = min(cs_end, static_cast<uint32_t>(v));
+    }
+    coop = __builtin_amdgcn_readfirstlane(coop ? 1u : 0u) != 0u;
+    cs_end = coop ? __builtin_amdgcn_readfirstlane(cs_end) : ca;
+  }
   const uint32_t head = static_cast<uint32_t>((static_cast<unsigned long long>(ca) * kChunk - k0) / kBlock);
   const uint32_t mid = (cz - ca) * (kChunk / kBlock);  // full blocks on the matrix cores
   if (kMfma && mid > 0) {
     if constexpr (kMode == kMfmaEveryWord) {
       if (D >= 3 && p.mpack)
-        best_em = mfma_every<D, (D >= 3 ? D - 1 : D)>(p.mtable, ca, cz, lane, ax, az, ntop, true);
+        best_em = mfma_every<D, (D >= 3 ? D - 1 : D)>(p.mtable, ca, cs_end, cz, coop, coop_buf, lane, ax, az, ntop,
+                                                      true);
       else
-        best_em = mfma_every<D, D>(p.mtable, ca, cz, lane, ax, az, ntop, false);
+        best_em = mfma_every<D, D>(p.mtable, ca, cs_end, cz, coop, coop_buf, lane, ax, az, ntop, false);
       for (uint32_t i = 0; i < head; ++i, blk += 2 * D * kBlock) best = block_min<D, kCensus>(ax, az, blk, best, cs);
       blk += mid * (2 * D * kBlock);
       for (uint32_t i = head + mid; i < nfull; ++i, blk += 2 * D * kBlock)
@@ -682,8 +798,8 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
     } else if constexpr (D >= 2) {
       const int c = p.credit[0];
       const uint32_t thr = U0 > c ? static_cast<uint32_t>(U0 - c) : 0u;
-      best = mfma_partial<D, kCensus>(p.table, p.mtable, p.mks, ca, cz, lane, ax, az, ntop, p.mpack != 0, thr, best,
-                                      mf_done, cs);
+      best = mfma_partial<D, kCensus>(p.table, p.mtable, p.mks, ca, cs_end, cz, coop, coop_buf, lane, ax, az, ntop,
+                                      p.mpack != 0, thr, best, mf_done, cs);
       best = partial_blocks<D, 1, kCensus>(ax, az, blk, head, best, thr, rec, cs);
       best = partial_blocks<D, 1, kCensus>(ax, az, blk + (head + mid) * (2 * D * kBlock), nfull - head - mid, best,
                                            thr, rec, cs);

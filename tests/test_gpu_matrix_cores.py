@@ -92,3 +92,20 @@ def test_batch_mixed_layouts(Q):
         if any(rd["t"] >= 3 for rd in s.rounds()):
             assert s.matrix_core_launches > 0
         assert swt(w) == d and O.in_rowspace(O.expand(G, f), w)
+
+
+@pytest.mark.parametrize("seg", [64, 128, 192])
+def test_shared_chunks_ragged_ends(Q, seg):
+    """Short tiles over a depth-2 saved table: the four waves of a workgroup
+    share a segment's chunks up to the shortest wave's end, and each wave
+    finishes its own remaining chunks (ends that are not a multiple of the
+    shared group).  Config-4 draws of two and three words per half against
+    the vector ALU."""
+    pool = [c for c in W.config4(120) if 50 <= c[0].shape[1] // 2 <= 74 and c[1] == 2][:6]
+    assert len(pool) >= 3
+    for i, (G, f) in enumerate(pool):
+        opts = dict(saved_depth=2, seg_len=seg, budget=int(2e10))
+        print(f"code {i} n={G.shape[1] // 2} seg={seg}", flush=True)
+        (st0, d0, w0, s0), (st1, d1, w1, s1) = [Q.qd_distance_ex(G, f, matrix_cores=mc, **opts) for mc in (0, -1)]
+        assert (st0, d0, s0.L, s0.U, s0.combinations) == (st1, d1, s1.L, s1.U, s1.combinations)
+        assert swt(w0) == d0 and O.in_rowspace(O.expand(G, f), w0)
