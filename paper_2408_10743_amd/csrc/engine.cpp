@@ -10,7 +10,7 @@
 
 namespace qd {
 
-hipError_t launch_round(int D, const LaunchParams &lp, bool census, bool every_word, bool mfma, hipStream_t s);
+hipError_t launch_round(int D, const LaunchParams &lp, bool census, bool every_word, int mfma, hipStream_t s);
 hipError_t launch_expand(const ExpandParams &ep, hipStream_t s);
 hipError_t launch_walk(int D, const LaunchParams &lp, bool sum, hipStream_t s);
 hipError_t launch_build(int D, const BuildParams &bp, hipStream_t s);
@@ -1015,6 +1015,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
     bool walk, sum;  // plain walk kernel; with the weight sum
     bool every_word; // no piece uses partial weights (entry-major kernel)
     bool mfma;       // every code of the launch may use the matrix cores
+    bool packed, plain;  // some piece with the packed / plain K-step layout
     size_t d0, d1;
     unsigned long long tiles;
     unsigned lds;
@@ -1034,7 +1035,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   for (int kind = 0; kind < 8; ++kind) {
     const int D = kind % 4 + 1;
     const bool walk = kind >= 4;
-    Launch L{D, walk, false, true, !arena(), descs_.size(), 0, 0, 0, false};
+    Launch L{D, walk, false, true, !arena(), false, false, descs_.size(), 0, 0, 0, false};
     for (Job *jp : jobs) {
       Job &job = *jp;
       if (job.done || job.D != D || job.status || (job.opt.walk > 0) != walk) continue;
@@ -1058,6 +1059,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         d.mks = g.mtable_ks[f.u];
         d.mpack = job.mpack;
         if (f.u > 0 && !d.mtable) L.mfma = false;  // that piece needs the vector-ALU kernel
+        (job.mpack ? L.packed : L.plain) = true;
         // groups and runs travel with this step's upload (set by flush)
         const size_t go = staging_.put(f.hg.data(), f.hg.size() * sizeof(DevGroup));
         const size_t ro = staging_.put(f.hr.data(), f.hr.size() * sizeof(DevRun));
@@ -1163,7 +1165,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         for (size_t d = L.d0; d < L.d1; ++d)
           if (descs_[d].commit) ++members[d].job->S.matrix_core_launches;
       if (L.timed && hipEventRecord(events_[2 * i], s) != hipSuccess) return QD_ERR_DEVICE;
-      if ((L.walk ? launch_walk(L.D, lp, L.sum, s) : launch_round(L.D, lp, L.sum, L.every_word, L.mfma, s)) != hipSuccess) return QD_ERR_DEVICE;
+      if ((L.walk ? launch_walk(L.D, lp, L.sum, s) : launch_round(L.D, lp, L.sum, L.every_word, !L.mfma ? 0 : L.packed && L.plain ? 1 : L.packed ? 2 : 3, s)) != hipSuccess) return QD_ERR_DEVICE;
       if (L.timed && hipEventRecord(events_[2 * i + 1], s) != hipSuccess) return QD_ERR_DEVICE;
       if (launch_commit(lp, s) != hipSuccess) return QD_ERR_DEVICE;
     }

@@ -328,7 +328,12 @@ __device__ __forceinline__ uint32_t partial_blocks(const uint32_t (&ax)[D], cons
 // negated, so the accumulator starts at C and ends at C - dot: with
 // C = 32 G it is 4 wt, an exact non-negative float whose bits order like
 // the weights.
-constexpr int kMfmaEveryWord = 3, kMfmaPartial = 4;
+// Every word on the matrix cores: kMfmaEveryWord picks the K-step layout per
+// piece; kMfmaEveryPacked / kMfmaEveryPlain serve launches whose pieces all
+// have the packed (K-steps D - 1) / plain (K-steps D) layout, with the
+// registers of that layout only.
+constexpr int kMfmaEveryWord = 3, kMfmaPartial = 4, kMfmaEveryPacked = 5, kMfmaEveryPlain = 6;
+constexpr bool mfma_every_mode(int m) { return m == kMfmaEveryWord || m == kMfmaEveryPacked || m == kMfmaEveryPlain; }
 typedef int v8i_t __attribute__((ext_vector_type(8)));
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 
@@ -426,14 +431,13 @@ struct CoopStream {
   }
 };
 
-// Every word of chunks [ca, cz) against the wave's tops, chunks [ca, cs)
-// shared with the workgroup (coop; sbuf: 2 x kCoopChunks x KS x 64 uint4);
-// the least weight over the lane's share of every valid top.
+// Every word of chunks [ca, cz) against the wave's tops; the least weight
+// over the lane's share of every valid top.  (Shared chunks do not pay
+// here: eight MFMAs per chunk hide a wave's own loads.)
 constexpr int kMfmaUnroll = 2;  // chunks per group of loads (a wave alone)
 template <int D, int KS>
-__device__ uint32_t mfma_every(const uint4 *__restrict__ mtab, uint32_t ca, uint32_t cs, uint32_t cz, bool coop,
-                               uint4 *sbuf, uint32_t lane, const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop,
-                               bool pack) {
+__device__ uint32_t mfma_every(const uint4 *__restrict__ mtab, uint32_t ca, uint32_t cz, uint32_t lane,
+                               const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop, bool pack) {
   v8i_t B[KS][4];
   mfma_tops<D, KS>(ax, az, lane, ntop, pack, B);
   constexpr int G = 3 * KS + (KS < D ? 1 : 0);  // sign groups (packed last word: one)
@@ -441,28 +445,6 @@ __device__ uint32_t mfma_every(const uint4 *__restrict__ mtab, uint32_t ca, uint
   const v4f_t c0 = {cf, cf, cf, cf};
   uint32_t bd[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
   uint32_t c = ca;
-  if (coop) {
-    CoopStream<KS> st;
-    constexpr int kPer = CoopStream<KS>::kPer;
-    st.load(mtab, KS, c, min(kCoopChunks, static_cast<int>(cs - c)));
-    st.store(sbuf);
-    __syncthreads();
-    for (int g = 0; c < cs; ++g, c += kCoopChunks) {
-      const uint32_t nu = min(kCoopChunks, static_cast<int>(cs - c));
-      const bool more = c + kCoopChunks < cs;
-      if (more) st.load(mtab, KS, c + kCoopChunks, min(kCoopChunks, static_cast<int>(cs - c - kCoopChunks)));
-      const uint4 *cur = sbuf + (g & 1) * kPer;
-      for (uint32_t u = 0; u < nu; ++u) {
-        v8i_t A[KS];
-#pragma unroll
-        for (int s = 0; s < KS; ++s) A[s] = mfma_operand(cur[(u * KS + s) * kWave + lane]);
-        mfma_every_chunk<KS>(A, B, c0, bd);
-      }
-      if (more) st.store(sbuf + ((g + 1) & 1) * kPer);
-      __syncthreads();
-    }
-    c = cs;  // the last group may be short
-  }
   const uint4 *mb = mtab + static_cast<size_t>(c) * KS * kWave + lane;
   for (; c + kMfmaUnroll <= cz; c += kMfmaUnroll, mb += kMfmaUnroll * KS * kWave) {
 #pragma unroll
@@ -530,9 +512,14 @@ __device__ uint32_t mfma_partial(const uint32_t *__restrict__ table, const uint4
       if (more) st.load(mtab, mks, c + kCoopChunks, min(kCoopChunks, static_cast<int>(cs_end - c - kCoopChunks)));
       const uint4 *cur = sbuf + (g & 1) * kPer;
       uint32_t pm[kCoopChunks];
+      if (nu == kCoopChunks) {  // a full group: one straight block the compiler can interleave
 #pragma unroll
-      for (int u = 0; u < kCoopChunks; ++u)
-        pm[u] = u < nu ? mfma_first_chunk(mfma_operand(cur[u * kWave + lane]), B, c0) : 0xFFFFFFFFu;
+        for (int u = 0; u < kCoopChunks; ++u) pm[u] = mfma_first_chunk(mfma_operand(cur[u * kWave + lane]), B, c0);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kCoopChunks; ++u)
+          pm[u] = u < nu ? mfma_first_chunk(mfma_operand(cur[u * kWave + lane]), B, c0) : 0xFFFFFFFFu;
+      }
       const uint32_t any = min(min(pm[0], pm[1]), min(pm[2], pm[3]));
       if (__ballot(any < T)) best = complete_chunks<D, kCensus>(table, c, nu, pm, T, ax, az, best, done, cs);
       if (more) st.store(sbuf + ((g + 1) & 1) * kPer);
@@ -640,11 +627,12 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   const RoundDesc &p = descs[wave_last_le(lp.ndesc, wtile, [descs](int i) { return descs[i].tile_begin; })];
   // Matrix cores: each wave's shared-chunk range (first chunk << 32 | end),
   // ~0 for a wave that takes no part; chunk buffers of the workgroup.
-  constexpr bool kMfma = kMode == kMfmaEveryWord || kMode == kMfmaPartial;
-  constexpr int kCoopLds = kMfma ? 2 * kCoopChunks * (kMode == kMfmaPartial ? 1 : D) * kWave : 1;
+  constexpr bool kMfmaEvery = mfma_every_mode(kMode);
+  constexpr bool kMfma = kMfmaEvery || kMode == kMfmaPartial;
+  constexpr bool kCoop = kMode == kMfmaPartial;
   __shared__ unsigned long long coop_slot[kWavesPerGroup];
-  __shared__ uint4 coop_buf[kCoopLds];
-  if (kMfma && (threadIdx.x & (kWave - 1)) == 0) coop_slot[threadIdx.x / kWave] = ~0ull;
+  __shared__ uint4 coop_buf[kCoop ? 2 * kCoopChunks * kWave : 1];
+  if (kCoop && (threadIdx.x & (kWave - 1)) == 0) coop_slot[threadIdx.x / kWave] = ~0ull;
 
   // Unranking reads suffix columns, the group table and the elements with
   // data-dependent addresses: stage them in LDS once per workgroup.
@@ -666,9 +654,9 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
       E = sE;
       ld = C;
     }
-    if constexpr (!kMfma) __syncthreads();
+    if constexpr (!kCoop) __syncthreads();
   }
-  if constexpr (kMfma) __syncthreads();  // staged tables; every wave's coop_slot cleared
+  if constexpr (kCoop) __syncthreads();  // staged tables; every wave's coop_slot cleared
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const unsigned long long local = wtile + wave - p.tile_begin;  // tile within the piece
@@ -759,7 +747,7 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   if (kMfma && p.mtable) {
     const uint32_t c_lo = static_cast<uint32_t>((k0 + kChunk - 1) / kChunk);
     const uint32_t c_hi = static_cast<uint32_t>((k0 + nfull * kBlock) / kChunk);
-    if (c_hi > c_lo && (kMode == kMfmaEveryWord ? W == D : W == 1)) {
+    if (c_hi > c_lo && (kMfmaEvery ? W == D : W == 1)) {
       ca = __builtin_amdgcn_readfirstlane(c_lo);
       cz = __builtin_amdgcn_readfirstlane(c_hi);
     }
@@ -768,7 +756,7 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   // part from the same first chunk (the same table segment).
   uint32_t cs_end = ca;
   bool coop = false;
-  if constexpr (kMfma) {
+  if constexpr (kCoop) {
     if (lane == 0 && cz > ca) coop_slot[wave] = (static_cast<unsigned long long>(ca) << 32) | cz;
     __syncthreads();  // the waves that returned early left ~0
     coop = cz > ca;
@@ -785,12 +773,16 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   const uint32_t head = static_cast<uint32_t>((static_cast<unsigned long long>(ca) * kChunk - k0) / kBlock);
   const uint32_t mid = (cz - ca) * (kChunk / kBlock);  // full blocks on the matrix cores
   if (kMfma && mid > 0) {
-    if constexpr (kMode == kMfmaEveryWord) {
-      if (D >= 3 && p.mpack)
-        best_em = mfma_every<D, (D >= 3 ? D - 1 : D)>(p.mtable, ca, cs_end, cz, coop, coop_buf, lane, ax, az, ntop,
-                                                      true);
+    if constexpr (kMfmaEvery) {
+      constexpr int kPackedKs = D >= 3 ? D - 1 : D;
+      if constexpr (kMode == kMfmaEveryPacked)
+        best_em = mfma_every<D, kPackedKs>(p.mtable, ca, cz, lane, ax, az, ntop, true);
+      else if constexpr (kMode == kMfmaEveryPlain)
+        best_em = mfma_every<D, D>(p.mtable, ca, cz, lane, ax, az, ntop, false);
+      else if (D >= 3 && p.mpack)
+        best_em = mfma_every<D, kPackedKs>(p.mtable, ca, cz, lane, ax, az, ntop, true);
       else
-        best_em = mfma_every<D, D>(p.mtable, ca, cs_end, cz, coop, coop_buf, lane, ax, az, ntop, false);
+        best_em = mfma_every<D, D>(p.mtable, ca, cz, lane, ax, az, ntop, false);
       for (uint32_t i = 0; i < head; ++i, blk += 2 * D * kBlock) best = block_min<D, kCensus>(ax, az, blk, best, cs);
       blk += mid * (2 * D * kBlock);
       for (uint32_t i = head + mid; i < nfull; ++i, blk += 2 * D * kBlock)
@@ -946,19 +938,38 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
 // -- launch (host) -------------------------------------------------------------
 
 template <int D>
-void launch_round_d(const LaunchParams &lp, bool census, bool every_word, bool mfma, dim3 grid, dim3 block,
+void launch_round_d(const LaunchParams &lp, bool census, bool every_word, int mfma, dim3 grid, dim3 block,
                     hipStream_t s) {
-  if (mfma && !census && every_word)
-    hipLaunchKernelGGL((qd_round_kernel<D, false, kMfmaEveryWord>), grid, block, lp.lds, s, lp);
-  else if (mfma && !census && D >= 2)
-    hipLaunchKernelGGL((qd_round_kernel<D, false, kMfmaPartial>), grid, block, lp.lds, s, lp);
-  else if (census && every_word) hipLaunchKernelGGL((qd_round_kernel<D, true, kEmEveryWord>), grid, block, lp.lds, s, lp);
-  else if (census) hipLaunchKernelGGL((qd_round_kernel<D, true, kEmPartial>), grid, block, lp.lds, s, lp);
-  else if (every_word) hipLaunchKernelGGL((qd_round_kernel<D, false, kEmEveryWord>), grid, block, lp.lds, s, lp);
-  else hipLaunchKernelGGL((qd_round_kernel<D, false, kEmPartial>), grid, block, lp.lds, s, lp);
+#define QD_LAUNCH(C, M) hipLaunchKernelGGL((qd_round_kernel<D, C, M>), grid, block, lp.lds, s, lp)
+  if (mfma && !census && every_word) {
+    if constexpr (D >= 3) {  // a packed last word needs three words per half
+      if (mfma == 2)
+        QD_LAUNCH(false, kMfmaEveryPacked);
+      else if (mfma == 1)
+        QD_LAUNCH(false, kMfmaEveryWord);
+      else
+        QD_LAUNCH(false, kMfmaEveryPlain);
+    } else {
+      QD_LAUNCH(false, kMfmaEveryPlain);
+    }
+  } else if (mfma && !census && D >= 2) {
+    QD_LAUNCH(false, kMfmaPartial);
+  } else if (census) {
+    if (every_word)
+      QD_LAUNCH(true, kEmEveryWord);
+    else
+      QD_LAUNCH(true, kEmPartial);
+  } else if (every_word) {
+    QD_LAUNCH(false, kEmEveryWord);
+  } else {
+    QD_LAUNCH(false, kEmPartial);
+  }
+#undef QD_LAUNCH
 }
 
-hipError_t launch_round(int D, const LaunchParams &lp, bool census, bool every_word, bool mfma, hipStream_t s) {
+// mfma: 0 vector ALU; matrix cores with 1 layouts mixed, 2 every piece packed,
+// 3 every piece plain.
+hipError_t launch_round(int D, const LaunchParams &lp, bool census, bool every_word, int mfma, hipStream_t s) {
   unsigned long long wgs = lp.tiles / kWavesPerGroup;
   wgs = (wgs + 8 * kXcdChunk - 1) / (8 * kXcdChunk) * (8 * kXcdChunk);  // the XCD dealing is a bijection
   dim3 grid(static_cast<uint32_t>(wgs)), block(kWave * kWavesPerGroup);
