@@ -40,6 +40,8 @@ sys.path.insert(0, ROOT)
 # issue capacity behind the chip's 157.3 TFLOP/s fp32 vector figure: 4 SIMDs
 # x 16 lanes x 2 VALU issues per cycle; single issue is half of it).
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
+# MI355X dense fp4 (e2m1) MFMA peak, the published figure (no sparsity).
+PEAK_FP4_FLOPS = 10.1e15
 
 
 # HBM bytes per launch of the round kernel in the every-word run of this
@@ -70,6 +72,22 @@ def issued_ops_per_codeword(D):
     return 3 * D + 1
 
 
+def flops_per_codeword(n):
+    """Matrix-core path: a codeword's weight is an affine function of the
+    dot product of two sign vectors of length 3n (the x, z and x ^ z signs
+    of every qubit), 3n multiply-adds."""
+    return 2 * 3 * n
+
+
+def mfma_flops_per_codeword(n):
+    """What the MFMAs execute per codeword: K-steps of 128 signs, one per
+    word (the last word packed into a spare group when it holds at most 10
+    qubits)."""
+    D = (n + 31) // 32
+    ks = D - 1 if D >= 3 and n - 32 * (D - 1) <= 10 else D
+    return 2 * 128 * ks
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1, help="GPUs (only 1 is supported)")
@@ -93,6 +111,8 @@ def parse():
                     help="only time the VALU instruction mixes of qd_valu_mix and print their rates")
     ap.add_argument("--default-only", action="store_true",
                     help="only run the default-path steps on the main code (partial weights), for a profiler")
+    ap.add_argument("--vector-alu", action="store_true",
+                    help="with --every-word-only or --default-only: the vector-ALU kernels (matrix_cores -1)")
     ap.add_argument("--every-word-only", action="store_true",
                     help="only run the timed steps on the main code (every word evaluated) and print their "
                          "rate and roofline, for a profiler")
@@ -235,19 +255,33 @@ def config4_codes(Q, W, count, max_work):
 def kernel_roofline(stats, launches=None):
     """Roofline of the enumeration kernel over runs with every word
     evaluated: codewords the kernel enumerated (rounds run ahead included)
-    x (4D+1) lane-ops, over the kernel time spent on them (HIP events on
-    the launch stream, shared among a launch's codes by their tiles)."""
-    ops = sum(s.enumerated * ops_per_codeword(s.D) for s in stats)
-    issued = sum(s.enumerated * issued_ops_per_codeword(s.D) for s in stats)
+    x the work per codeword, over the kernel time spent on them (HIP events
+    on the launch stream, shared among a launch's codes by their tiles).
+    On the matrix cores the work is 6n flops (3n sign multiply-adds)
+    against the fp4 MFMA peak; on the vector ALU (4D+1) lane-ops against
+    the lane-op peak."""
     ms = sum(s.enumerated_kernel_ms for s in stats)
     assert all(s.words == s.D * s.enumerated for s in stats), "not an every-word run"
-    achieved = ops / (ms * 1e-3)
-    out = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
-           "frac": achieved / PEAK_LANE_OPS,
-           "ops_basis": "4D+1 lane-ops per codeword (2D XOR, D OR, D popcount, 1 min)",
-           "codewords_enumerated": sum(s.enumerated for s in stats),
-           "kernel_ms_total": ms,
-           "frac_issued_3D1": issued / (ms * 1e-3) / PEAK_LANE_OPS}
+    enumerated = sum(s.enumerated for s in stats)
+    if all(s.matrix_core_launches == s.launches and s.launches > 0 for s in stats):
+        flops = sum(s.enumerated * flops_per_codeword(s.n) for s in stats)
+        hw = sum(s.enumerated * mfma_flops_per_codeword(s.n) for s in stats)
+        achieved = flops / (ms * 1e-3)
+        out = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP4_FLOPS / 1e12, "unit": "TFLOP/s",
+               "frac": achieved / PEAK_FP4_FLOPS,
+               "ops_basis": "6n flops per codeword: the 3n-sign dot product (x, z, x^z signs per qubit), "
+                            "fp4 e2m1 operands, fp32 sums, exact",
+               "codewords_enumerated": enumerated, "kernel_ms_total": ms,
+               "frac_executed": hw / (ms * 1e-3) / PEAK_FP4_FLOPS}
+    else:
+        ops = sum(s.enumerated * ops_per_codeword(s.D) for s in stats)
+        issued = sum(s.enumerated * issued_ops_per_codeword(s.D) for s in stats)
+        achieved = ops / (ms * 1e-3)
+        out = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
+               "frac": achieved / PEAK_LANE_OPS,
+               "ops_basis": "4D+1 lane-ops per codeword (2D XOR, D OR, D popcount, 1 min)",
+               "codewords_enumerated": enumerated, "kernel_ms_total": ms,
+               "frac_issued_3D1": issued / (ms * 1e-3) / PEAK_LANE_OPS}
     if launches:
         out["launches"] = launches
         out["avg_launch_ms"] = ms / launches
@@ -609,9 +643,10 @@ def main():
         w = sorted(s.wall_ms for _, s in stats)
         return w[len(w) // 2]
 
+    kopt = {"matrix_cores": -1} if a.vector_alu else {}
     if a.default_only:
-        run(a.warmup)
-        wall, stats = run(a.steps)
+        run(a.warmup, **kopt)
+        wall, stats = run(a.steps, **kopt)
         print(json.dumps({"default_path_ms_per_step": wall * 1e3 / a.steps}))
         return
     def copy_calibration():
@@ -624,8 +659,8 @@ def main():
         return src.numel() * 4
 
     if a.every_word_only:
-        run(a.warmup, partial_weight=-1)
-        wall, stats = run(a.steps, partial_weight=-1)
+        run(a.warmup, partial_weight=-1, **kopt)
+        wall, stats = run(a.steps, partial_weight=-1, **kopt)
         roof = kernel_roofline([s for _, s in stats], sum(s.launches for _, s in stats))
         out = {"ms_per_step": wall * 1e3 / a.steps,
                "codewords_per_s": sum(s.combinations for _, s in stats) / wall, "roofline": roof}
@@ -645,7 +680,8 @@ def main():
     D = stats[0][1].D
     s0 = stats[0][1]
     roof = kernel_roofline([s for _, s in stats], launches)
-    roof["kernel"] = f"qd_round_kernel<{D}, false, every word>"
+    roof["kernel"] = (f"qd_round_kernel<{D}, false, every word on the matrix cores>" if roof["bound"] == "mfma"
+                      else f"qd_round_kernel<{D}, false, every word>")
     roof["traffic"] = TRAFFIC["bytes_per_launch"] if kernel_fingerprint() == TRAFFIC["fingerprint"] else None
     # The library's default path on the same code: time to exact d.
     run(a.warmup)
@@ -655,6 +691,20 @@ def main():
     words_d = sum(s.words for _, s in stats_d)
     enum_d = sum(s.enumerated for _, s in stats_d)
     ttd_ms = wall_d * 1e3 / a.steps
+    # The same two legs on the vector-ALU kernels (qd_options.matrix_cores -1).
+    vsteps = max(1, min(a.steps, 5))
+    run(1, partial_weight=-1, matrix_cores=-1)
+    wall_v, stats_v = run(vsteps, partial_weight=-1, matrix_cores=-1)
+    run(1, matrix_cores=-1)
+    wall_vd, stats_vd = run(vsteps, matrix_cores=-1)
+    assert all(x[0] == d for x in stats_v + stats_vd)
+    vector_alu = {
+        "kind": "the same code on the vector-ALU kernels (matrix_cores -1)",
+        "ms_per_step": wall_v * 1e3 / vsteps,
+        "codewords_per_s": sum(s.combinations for _, s in stats_v) / wall_v,
+        "time_to_exact_d_ms": wall_vd * 1e3 / vsteps,
+        "roofline": kernel_roofline([s for _, s in stats_v], sum(s.launches for _, s in stats_v)),
+    }
     out = {
         "metric": "codewords/s (XOR+symplectic wt) & time-to-exact-d: batched vs plain per-code",
         "value": combos / wall,
@@ -666,7 +716,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "fp4" if roof["bound"] == "mfma" else "u32",
         "data": "synthetic",
         "config": {"workload": f"single additive code n=72 m=72 Bernoulli(1/2), seed {a.seed} (config 3), "
                                f"exact d with every word of every codeword evaluated",
@@ -688,6 +738,7 @@ def main():
             "speedup_vs_every_word": (wall * 1e3 / a.steps) / ttd_ms,
         },
         "roofline": roof,
+        "vector_alu": vector_alu,
         "device": name,
     }
     if a.copy_calibration:

@@ -11,7 +11,7 @@
 namespace qd {
 
 hipError_t launch_round(int D, const LaunchParams &lp, bool census, bool every_word, int mfma, hipStream_t s);
-hipError_t launch_expand(const ExpandParams &ep, hipStream_t s);
+hipError_t launch_expand(const ExpandBatch &eb, hipStream_t s);
 hipError_t launch_walk(int D, const LaunchParams &lp, bool sum, hipStream_t s);
 hipError_t launch_build(int D, const BuildParams &bp, hipStream_t s);
 hipError_t launch_commit(const LaunchParams &lp, hipStream_t s);
@@ -30,6 +30,9 @@ constexpr unsigned kMinSeg = 1024, kMaxSeg = 4096;
 // dependent table loads, so shorter tiles finish sooner.
 constexpr unsigned long long kShortRound = 1ull << 24;
 constexpr unsigned kShortSeg = 64;
+// Rounds of at least this many combinations get the matrix-core form of
+// their saved table (smaller ones stay on the vector ALU).
+constexpr unsigned long long kMfmaMinRound = 1ull << 20;
 // Partial weights for codes whose planned work reaches this many combinations.
 constexpr double kPartialMinWork = 1e8;
 constexpr unsigned kStageMaxBytes = 32768;
@@ -761,8 +764,14 @@ int Executor::flush(hipStream_t s, const unsigned char **base, size_t *desc_off)
   for (int *m : level_marks_) *m = -1;
   level_marks_.clear();
   if (staging_.size() == 0 && descs_.empty() && bl.empty() && recs_.empty() && expands_.empty()) return QD_OK;
+  unsigned long long ex_threads = 0;
+  for (ExpandParams &ep : expands_) {
+    ep.first = ex_threads;
+    ex_threads += expand_threads(ep.nent, ep.mks);
+  }
   const size_t need = staging_.size() + align16(descs_.size() * sizeof(RoundDesc)) +
-                      align16(bl.size() * sizeof(SavedParams)) + align16(recs_.size() * sizeof(CopyRec));
+                      align16(bl.size() * sizeof(SavedParams)) + align16(recs_.size() * sizeof(CopyRec)) +
+                      align16(expands_.size() * sizeof(ExpandParams));
   if (!alloc(stage_dev_, need)) return QD_ERR_NOMEM;
   const unsigned char *dev = static_cast<const unsigned char *>(stage_dev_.p);
   for (size_t i = 0; i < descs_.size(); ++i) {
@@ -776,7 +785,8 @@ int Executor::flush(hipStream_t s, const unsigned char **base, size_t *desc_off)
   const size_t doff = staging_.put(descs_.data(), descs_.size() * sizeof(RoundDesc));
   const size_t boff = staging_.put(bl.data(), bl.size() * sizeof(SavedParams));
   const size_t roff = staging_.put(recs_.data(), recs_.size() * sizeof(CopyRec));
-  if (doff == SIZE_MAX || boff == SIZE_MAX || roff == SIZE_MAX) return QD_ERR_NOMEM;
+  const size_t eoff = staging_.put(expands_.data(), expands_.size() * sizeof(ExpandParams));
+  if (doff == SIZE_MAX || boff == SIZE_MAX || roff == SIZE_MAX || eoff == SIZE_MAX) return QD_ERR_NOMEM;
   if (staging_.size() != need) return QD_ERR_INTERNAL;
   if (hipMemcpyAsync(stage_dev_.p, staging_.data(), need, hipMemcpyHostToDevice, s) != hipSuccess)
     return QD_ERR_DEVICE;
@@ -799,8 +809,14 @@ int Executor::flush(hipStream_t s, const unsigned char **base, size_t *desc_off)
     bp.lds = lds <= kStageMaxBytes ? lds : 0u;
     if (launch_build(r.D, bp, s) != hipSuccess) return QD_ERR_DEVICE;
   }
-  for (const ExpandParams &ep : expands_)
-    if (launch_expand(ep, s) != hipSuccess) return QD_ERR_DEVICE;
+  if (!expands_.empty()) {
+    ExpandBatch eb;
+    eb.req = reinterpret_cast<const ExpandParams *>(dev + eoff);
+    eb.nreq = int(expands_.size());
+    eb.threads = ex_threads;
+    eb.base = 0;
+    if (launch_expand(eb, s) != hipSuccess) return QD_ERR_DEVICE;
+  }
   expands_.clear();
   *base = dev;
   *desc_off = doff;
@@ -930,7 +946,8 @@ int Executor::schedule(Job &job, int sharing) {
     }
     int rc = f.u > 0 ? ensure_table(job, g, f.u, false) : QD_OK;
     if (!rc && f.use_tops) rc = ensure_table(job, g, t - f.u, true);
-    if (!rc && f.u > 0 && job.mfma && !arena() && !job.force_words && job.census_below == 0)
+    if (!rc && f.u > 0 && planned >= kMfmaMinRound && job.mfma && !arena() && !job.force_words &&
+        job.census_below == 0)
       rc = ensure_mtable(job, g, f.u, job.partial ? 1 : job.mks);
     if (rc) return rc;
     f.tiles = plan_round(g, t, f.u, f.seg, job.scalar, f.hg, f.hr);
@@ -1016,6 +1033,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
     bool every_word; // no piece uses partial weights (entry-major kernel)
     bool mfma;       // every code of the launch may use the matrix cores
     bool packed, plain;  // some piece with the packed / plain K-step layout
+    bool any_mtable;     // some piece with the matrix-core form
     size_t d0, d1;
     unsigned long long tiles;
     unsigned lds;
@@ -1035,7 +1053,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   for (int kind = 0; kind < 8; ++kind) {
     const int D = kind % 4 + 1;
     const bool walk = kind >= 4;
-    Launch L{D, walk, false, true, !arena(), false, false, descs_.size(), 0, 0, 0, false};
+    Launch L{D, walk, false, true, !arena(), false, false, false, descs_.size(), 0, 0, 0, false};
     for (Job *jp : jobs) {
       Job &job = *jp;
       if (job.done || job.D != D || job.status || (job.opt.walk > 0) != walk) continue;
@@ -1058,8 +1076,11 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         d.mtable = f.u > 0 && g.mtable_ks[f.u] >= need_ks ? static_cast<const uint4 *>(g.mtable[f.u].p) : nullptr;
         d.mks = g.mtable_ks[f.u];
         d.mpack = job.mpack;
-        if (f.u > 0 && !d.mtable) L.mfma = false;  // that piece needs the vector-ALU kernel
-        (job.mpack ? L.packed : L.plain) = true;
+        // A large round without the matrix-core form (no room for it) needs
+        // the vector-ALU kernel; small rounds run its streaming loop anywhere.
+        if (f.u > 0 && !d.mtable && f.planned >= kMfmaMinRound) L.mfma = false;
+        if (d.mtable) L.any_mtable = true;
+        if (d.mtable) (job.mpack ? L.packed : L.plain) = true;
         // groups and runs travel with this step's upload (set by flush)
         const size_t go = staging_.put(f.hg.data(), f.hg.size() * sizeof(DevGroup));
         const size_t ro = staging_.put(f.hr.data(), f.hr.size() * sizeof(DevRun));
@@ -1132,6 +1153,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
       }
     }
     L.d1 = descs_.size();
+    L.mfma = L.mfma && L.any_mtable;  // only small rounds: the vector-ALU kernel
     if (L.d1 > L.d0) {
       launches.push_back(L);
       max_tiles = std::max(max_tiles, L.tiles);

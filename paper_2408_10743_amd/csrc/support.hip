@@ -2,6 +2,8 @@
 // per-launch commit, the upload scatter and the VALU rate probe.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "support.hpp"
 
@@ -17,7 +19,7 @@ namespace qd {
 template <int D>
 __global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
   extern __shared__ unsigned long long ecnt[];
-  const unsigned long long wfirst = static_cast<unsigned long long>(blockIdx.x) * kBuildGroup;
+  const unsigned long long wfirst = bp.base + static_cast<unsigned long long>(blockIdx.x) * kBuildGroup;
   if (wfirst >= bp.threads) return;
   int lo = 0, hi = bp.nreq;
   while (hi - lo > 1) {
@@ -116,11 +118,20 @@ __global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
 // codeword of the winning slot into the code's state, in qubit order, and
 // folds the code's spread counters into its visited and evaluated-word
 // counts.
-// Matrix-core form of a saved table (ExpandParams): thread t writes the 16
-// bytes of lane t % 64 of (chunk, K-step) t / 64, so a wave writes one
-// contiguous kilobyte.
-__global__ __launch_bounds__(256) void qd_expand_kernel(ExpandParams ep) {
-  const unsigned long long t = static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+// Matrix-core forms of a step's saved tables (ExpandBatch): thread t of a
+// table writes the 16 bytes of lane t % 64 of (chunk, K-step) t / 64, so a
+// wave writes one contiguous kilobyte.
+__global__ __launch_bounds__(256) void qd_expand_kernel(ExpandBatch eb) {
+  const unsigned long long wfirst = eb.base + static_cast<unsigned long long>(blockIdx.x) * blockDim.x;
+  if (wfirst >= eb.threads) return;
+  int lo = 0, hi = eb.nreq;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (eb.req[mid].first <= wfirst) lo = mid;
+    else hi = mid;
+  }
+  const ExpandParams &ep = eb.req[lo];
+  const unsigned long long t = wfirst - ep.first + threadIdx.x;
   const unsigned long long nchunk = (ep.nent + kChunk - 1) / kChunk;
   if (t >= nchunk * ep.mks * kWave) return;
   const int lane = static_cast<int>(t % kWave), g = lane / kChunk;
@@ -324,16 +335,22 @@ __global__ __launch_bounds__(256) void qd_mix_kernel(uint32_t seed, uint32_t ite
 
 // -- launch helpers (host) ---------------------------------------------------
 
-hipError_t launch_build(int D, const BuildParams &bp, hipStream_t s) {
-  dim3 grid(static_cast<uint32_t>(bp.threads / kBuildGroup)), block(kBuildGroup);
-  switch (D) {
-    case 1: hipLaunchKernelGGL(qd_build_kernel<1>, grid, block, bp.lds, s, bp); break;
-    case 2: hipLaunchKernelGGL(qd_build_kernel<2>, grid, block, bp.lds, s, bp); break;
-    case 3: hipLaunchKernelGGL(qd_build_kernel<3>, grid, block, bp.lds, s, bp); break;
-    case 4: hipLaunchKernelGGL(qd_build_kernel<4>, grid, block, bp.lds, s, bp); break;
-    default: return hipErrorInvalidValue;
+hipError_t launch_build(int D, const BuildParams &bp_all, hipStream_t s) {
+  for (unsigned long long base = 0; base < bp_all.threads; base += kMaxLaunchThreads) {
+    BuildParams bp = bp_all;
+    bp.base = base;
+    const unsigned long long n = std::min(bp_all.threads - base, kMaxLaunchThreads);
+    dim3 grid(static_cast<uint32_t>(n / kBuildGroup)), block(kBuildGroup);
+    switch (D) {
+      case 1: hipLaunchKernelGGL(qd_build_kernel<1>, grid, block, bp.lds, s, bp); break;
+      case 2: hipLaunchKernelGGL(qd_build_kernel<2>, grid, block, bp.lds, s, bp); break;
+      case 3: hipLaunchKernelGGL(qd_build_kernel<3>, grid, block, bp.lds, s, bp); break;
+      case 4: hipLaunchKernelGGL(qd_build_kernel<4>, grid, block, bp.lds, s, bp); break;
+      default: return hipErrorInvalidValue;
+    }
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_commit(const LaunchParams &lp, hipStream_t s) {
@@ -341,11 +358,15 @@ hipError_t launch_commit(const LaunchParams &lp, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_expand(const ExpandParams &ep, hipStream_t s) {
-  const unsigned long long threads = (ep.nent + kChunk - 1) / kChunk * ep.mks * kWave;
-  if (threads == 0) return hipSuccess;
-  hipLaunchKernelGGL(qd_expand_kernel, dim3(static_cast<uint32_t>((threads + 255) / 256)), dim3(256), 0, s, ep);
-  return hipGetLastError();
+hipError_t launch_expand(const ExpandBatch &eb_all, hipStream_t s) {
+  for (unsigned long long base = 0; base < eb_all.threads; base += kMaxLaunchThreads) {
+    ExpandBatch eb = eb_all;
+    eb.base = base;
+    const unsigned long long n = std::min(eb_all.threads - base, kMaxLaunchThreads);
+    hipLaunchKernelGGL(qd_expand_kernel, dim3(static_cast<uint32_t>(n / 256)), dim3(256), 0, s, eb);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_scatter(const CopyRec *rec, int n, const unsigned char *base, hipStream_t s) {

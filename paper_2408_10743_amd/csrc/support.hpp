@@ -40,7 +40,12 @@ struct BuildParams {
   int nreq;
   unsigned int lds;                    // dynamic LDS bytes (0: read counts from memory)
   unsigned long long threads;
+  unsigned long long base;             // first thread of this launch (a slice of `threads`)
 };
+
+// Threads per launch at most: a dispatch packet counts its grid in 32-bit
+// work-items, so larger builds go out in slices of this many threads.
+constexpr unsigned long long kMaxLaunchThreads = 1ull << 31;
 
 // One block move of a step's upload: `bytes` (a multiple of 16) from the
 // step's device staging buffer at byte offset `src`, or zeros when src is
@@ -67,8 +72,23 @@ struct ExpandParams {
   const uint32_t *table;               // saved table, blocks of kBlock entries
   uint4 *mtable;                       // ceil(nent / kChunk) * mks * 64 uint4
   unsigned long long nent;
+  unsigned long long first;            // first thread of this table in the launch
   int D, mks, pack;
 };
+
+// One launch expands every table queued for a step.
+struct ExpandBatch {
+  const ExpandParams *req;             // sorted by first; each starts a workgroup
+  int nreq;
+  unsigned long long threads;
+  unsigned long long base;             // first thread of this launch (a slice of `threads`)
+};
+
+// Threads of a table's expansion, rounded up to whole workgroups.
+__host__ __device__ inline unsigned long long expand_threads(unsigned long long nent, int mks) {
+  const unsigned long long t = (nent + kChunk - 1) / kChunk * mks * kWave;
+  return (t + 255) / 256 * 256;
+}
 
 __host__ __device__ inline unsigned int build_lds_bytes(int P, int u) { return static_cast<unsigned int>((P + 1) * (u + 1) * 8); }
 
