@@ -125,6 +125,8 @@ def parse():
                     help="only run the unfiltered config-4 draws (first --batch-codes draws, per-code budget)")
     ap.add_argument("--tune-out", default="",
                     help="only run the launch-shape tuner (qd_tune_run, up to 300 s) and write its table to this file")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only run the two serving legs (default path and every word) and print them")
     ap.add_argument("--latency-only", action="store_true",
                     help="only run the time-to-exact-d leg on configs 1 and 2, for a profiler")
     ap.add_argument("--round-sweep", action="store_true",
@@ -526,12 +528,22 @@ def leg_serving(Q, W, a, **opts):
     exceeds 1e10 are redrawn (stated in the output).  opts apply to every
     request (partial_weight=-1: every word evaluated)."""
     reqs, drawn = serving_requests(Q, W, a)
-    # service capacity: the same requests run back to back as one batch
-    # (timed on a second call, after device memory and tables are warm)
-    Q.qd_distance_batch(reqs, **opts)
-    t0 = time.perf_counter()
-    Q.qd_distance_batch(reqs, **opts)
-    t_all = time.perf_counter() - t0
+
+    def back_to_back():
+        """Service capacity: the serving engine given every request at once."""
+        e = Q.qd_engine_create()
+        t0 = time.perf_counter()
+        for i, (G, f) in enumerate(reqs):
+            Q.qd_engine_submit(e, G, f, i, **opts)
+        done = 0
+        while done < len(reqs):
+            done += len(Q.qd_engine_poll(e, 64, 100))
+        t = time.perf_counter() - t0
+        Q.qd_engine_destroy(e)
+        return t
+
+    back_to_back()  # device memory and tables warm
+    t_all = back_to_back()
     rate = a.serve_rate or 0.6 * len(reqs) / t_all
     gaps = [t for t, _, _ in W.config5(len(reqs), rate, index=1)]
     e = Q.qd_engine_create()
@@ -551,7 +563,7 @@ def leg_serving(Q, W, a, **opts):
     lat.sort()
     key = "codewords_per_s" if opts.get("partial_weight") == -1 else "combinations_certified_per_s"
     return {"workload": f"config 5: {len(reqs)} requests of {drawn} drawn (predicted work <= 1e10), "
-                        f"Poisson rate {rate:.1f}/s (60% of back-to-back capacity)",
+                        f"Poisson rate {rate:.1f}/s (60% of the engine's back-to-back capacity)",
             "rate_per_s": rate, "requests": len(reqs), "exact": sum(1 for x in statuses if x == 0),
             "p50_ms": lat[len(lat) // 2], "p99_ms": lat[min(len(lat) - 1, int(0.99 * len(lat)))],
             key: comb / t_total, "window_s": t_total}
@@ -620,6 +632,10 @@ def main():
         return
     if a.latency_only:
         print(json.dumps({"latency": leg_latency(Q, W)}))
+        return
+    if a.serving_only:
+        print(json.dumps({"serving": leg_serving(Q, W, a),
+                          "serving_every_word": leg_serving(Q, W, a, partial_weight=-1)}))
         return
     if a.walk_only:
         print(json.dumps({"walk_per_round": leg_walk(Q, G, field, stream.cuda_stream, float("nan"), a.steps)}))

@@ -271,7 +271,8 @@ size_t Staging::put(const void *src, size_t bytes) {
 // -- Executor ------------------------------------------------------------------
 
 Executor::Executor(hipStream_t stream, void *arena, size_t bytes)
-    : spec_combos_(kSpecCombos), long_seg_(kMinSeg), stream_(stream), max_table_bytes_(bytes / 4) {
+    : mfma_min_round_(kMfmaMinRound), spec_combos_(kSpecCombos), long_seg_(kMinSeg), stream_(stream),
+      max_table_bytes_(bytes / 4) {
   if (!arena) return;  // the caller has checked the device (a gfx950 holding the arena)
   pool_.set_arena(arena, bytes);
   staging_.set_pageable();
@@ -284,7 +285,8 @@ Executor::Executor(hipStream_t stream, void *arena, size_t bytes)
 }
 
 Executor::Executor(hipStream_t stream)
-    : spec_combos_(kSpecCombos), long_seg_(kMinSeg), max_table_bytes_(kMaxTableBytes) {
+    : mfma_min_round_(kMfmaMinRound), spec_combos_(kSpecCombos), long_seg_(kMinSeg),
+      max_table_bytes_(kMaxTableBytes) {
   int dev = 0, cnt = 0;
   hipDeviceProp_t prop;
   if (hipGetDeviceCount(&cnt) != hipSuccess || cnt <= 0 || hipGetDevice(&dev) != hipSuccess ||
@@ -946,7 +948,7 @@ int Executor::schedule(Job &job, int sharing) {
     }
     int rc = f.u > 0 ? ensure_table(job, g, f.u, false) : QD_OK;
     if (!rc && f.use_tops) rc = ensure_table(job, g, t - f.u, true);
-    if (!rc && f.u > 0 && planned >= kMfmaMinRound && job.mfma && !arena() && !job.force_words &&
+    if (!rc && f.u > 0 && planned >= mfma_min_round_ && job.mfma && !arena() && !job.force_words &&
         job.census_below == 0)
       rc = ensure_mtable(job, g, f.u, job.partial ? 1 : job.mks);
     if (rc) return rc;
@@ -1078,7 +1080,7 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         d.mpack = job.mpack;
         // A large round without the matrix-core form (no room for it) needs
         // the vector-ALU kernel; small rounds run its streaming loop anywhere.
-        if (f.u > 0 && !d.mtable && f.planned >= kMfmaMinRound) L.mfma = false;
+        if (f.u > 0 && !d.mtable && f.planned >= mfma_min_round_) L.mfma = false;
         if (d.mtable) L.any_mtable = true;
         if (d.mtable) (job.mpack ? L.packed : L.plain) = true;
         // groups and runs travel with this step's upload (set by flush)

@@ -201,6 +201,9 @@ class Executor {
   // Whether rounds take the measured launch shapes (tune_lookup) where
   // installed; the serving engine keeps its latency-minded model rules.
   void set_tuned(bool on) { tuned_ = on; }
+  // Rounds of at least this many combinations take the matrix cores (with
+  // the expansion of their saved table); smaller ones the vector ALU.
+  void set_mfma_min_round(unsigned long long c) { mfma_min_round_ = c; }
 
   // Host-side preparation of a job (input check, basis, diagonalizations,
   // plan).  Thread-safe; touches no device state.
@@ -234,6 +237,7 @@ class Executor {
 
   bool ok_ = false;
   bool tuned_ = true;
+  unsigned long long mfma_min_round_;
   unsigned long long spec_combos_;
   unsigned long_seg_;
   bool own_stream_ = false;

@@ -117,6 +117,7 @@ qd_engine *qd_engine_create(size_t mem_budget, int max_active, void *stream) {
   // that arrive meanwhile wait for it.
   e->ex->set_long_seg(256);
   e->ex->set_tuned(false);  // latency first: short tiles, whatever a throughput tuning chose
+  e->ex->set_mfma_min_round(1ull << 26);  // and no table expansion for rounds of a few microseconds
   e->budget = mem_budget ? mem_budget : (size_t(8) << 30);
   e->max_active = max_active > 0 ? max_active : 512;
   qd_engine *raw = e.release();
