@@ -1052,17 +1052,34 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
   unsigned long long max_tiles = 0;
   // One launch per word count D for the saved-sum kernel, then per D for
   // the codes on the plain walk.
-  for (int kind = 0; kind < 8; ++kind) {
+  // A piece goes to the matrix-core launch of its word count unless it is a
+  // large round whose table has no matrix-core form (no room for one): those
+  // get a launch of the vector-ALU kernel of their own, so the others keep
+  // the matrix cores.  A code may then have pieces in both launches; each
+  // launch commits it after its own pieces.
+  auto matrix_class = [&](const Job &job, const Flight &f) {
+    if (f.walk || !job.mfma || job.force_words || job.census_below > 0 || arena()) return false;
+    if (f.u == 0) return true;
+    const int need_ks = job.partial ? 1 : job.mks;
+    return job.gd[f.j].mtable_ks[f.u] >= need_ks || f.planned < mfma_min_round_;
+  };
+  std::vector<unsigned long long> tiles_left(jobs.size());  // tiles each code may still send this step
+  for (size_t i = 0; i < jobs.size(); ++i) tiles_left[i] = jobs[i]->opt.cancel ? kCancelTilesPerStep : ~0ull;
+  for (int kind = 0; kind < 16; ++kind) {
     const int D = kind % 4 + 1;
-    const bool walk = kind >= 4;
-    Launch L{D, walk, false, true, !arena(), false, false, false, descs_.size(), 0, 0, 0, false};
-    for (Job *jp : jobs) {
+    const bool walk = (kind / 4) % 2 == 1;
+    const bool mclass = kind >= 8;
+    if (walk && mclass) continue;
+    Launch L{D, walk, false, true, mclass && !arena(), false, false, false, descs_.size(), 0, 0, 0, false};
+    for (size_t ji = 0; ji < jobs.size(); ++ji) {
+      Job *jp = jobs[ji];
       Job &job = *jp;
       if (job.done || job.D != D || job.status || (job.opt.walk > 0) != walk) continue;
       bool first = true;  // the first piece of the code in this launch commits it
-      unsigned long long job_left = job.opt.cancel ? kCancelTilesPerStep : ~0ull;  // tiles this step
+      unsigned long long &job_left = tiles_left[ji];
       for (size_t fi = 0; fi < job.fl.size(); ++fi) {
         Flight &f = job.fl[fi];
+        if (matrix_class(job, f) != mclass) continue;
         const unsigned long long left = f.tiles - f.sent;
         const unsigned long long take =
             std::min({left, kTilesPerLaunch - std::min(kTilesPerLaunch, L.tiles), job_left});
