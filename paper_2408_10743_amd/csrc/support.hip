@@ -119,8 +119,9 @@ __global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
 // folds the code's spread counters into its visited and evaluated-word
 // counts.
 // Matrix-core forms of a step's saved tables (ExpandBatch): thread t of a
-// table writes the 16 bytes of lane t % 64 of (chunk, K-step) t / 64, so a
-// wave writes one contiguous kilobyte.
+// table reads entry 16 c + r of chunk c once and writes its four groups of
+// K-step s (t = (c mks + s) 16 + r); each of its four 16-byte stores meets
+// those of the 15 neighbouring entries in one contiguous 256-byte run.
 __global__ __launch_bounds__(256) void qd_expand_kernel(ExpandBatch eb) {
   const unsigned long long wfirst = eb.base + static_cast<unsigned long long>(blockIdx.x) * blockDim.x;
   if (wfirst >= eb.threads) return;
@@ -131,25 +132,41 @@ __global__ __launch_bounds__(256) void qd_expand_kernel(ExpandBatch eb) {
     else hi = mid;
   }
   const ExpandParams &ep = eb.req[lo];
-  const unsigned long long t = wfirst - ep.first + threadIdx.x;
   const unsigned long long nchunk = (ep.nent + kChunk - 1) / kChunk;
-  if (t >= nchunk * ep.mks * kWave) return;
-  const int lane = static_cast<int>(t % kWave), g = lane / kChunk;
-  const int s = static_cast<int>((t / kWave) % ep.mks);
-  const unsigned long long e = (t / (static_cast<unsigned long long>(kWave) * ep.mks)) * kChunk + lane % kChunk;
-  const bool packed = ep.pack && s == ep.D - 2;
-  uint4 o = {0u, 0u, 0u, 0u};
-  if (e < ep.nent && (g < 3 || packed)) {
-    const int D = ep.D;
+  // A table's threads number 16 per (chunk, K-step): below 2^32 for any
+  // table the engine builds (at most 2^29 bytes, 8 bytes per entry or more).
+  const uint32_t t = static_cast<uint32_t>(wfirst - ep.first) + threadIdx.x;
+  const uint32_t cs = t / kChunk, r = t % kChunk;
+  if (cs >= nchunk * ep.mks) return;
+  const uint32_t mks = static_cast<uint32_t>(ep.mks);
+  const uint32_t c = cs / mks;
+  const int s = static_cast<int>(cs - c * mks);
+  const int D = ep.D;
+  const bool packed = ep.pack && s == D - 2;
+  const unsigned long long e = static_cast<unsigned long long>(c) * kChunk + r;
+  uint32_t x = 0, z = 0, xl = 0, zl = 0;
+  if (e < ep.nent) {
     const uint32_t *b = ep.table + (e / kBlock) * (2 * D * kBlock) + e % kBlock;
-    const uint32_t w = group_word(g, packed, b[s * kBlock], b[(D + s) * kBlock], b[(D - 1) * kBlock],
-                                  b[(2 * D - 1) * kBlock]);
-    o.x = sign_nibbles(w);
-    o.y = sign_nibbles(w >> 8);
-    o.z = sign_nibbles(w >> 16);
-    o.w = sign_nibbles(w >> 24);
+    x = b[s * kBlock];
+    z = b[(D + s) * kBlock];
+    if (packed) {
+      xl = b[(D - 1) * kBlock];
+      zl = b[(2 * D - 1) * kBlock];
+    }
   }
-  ep.mtable[t] = o;
+  uint4 *out = ep.mtable + static_cast<size_t>(cs) * kWave + r;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const uint32_t w = group_word(g, packed, x, z, xl, zl);
+    uint4 o = {0u, 0u, 0u, 0u};
+    if (e < ep.nent && (g < 3 || packed)) {
+      o.x = sign_nibbles(w);
+      o.y = sign_nibbles(w >> 8);
+      o.z = sign_nibbles(w >> 16);
+      o.w = sign_nibbles(w >> 24);
+    }
+    out[g * kChunk] = o;
+  }
 }
 
 __global__ __launch_bounds__(256) void qd_commit_kernel(LaunchParams lp) {

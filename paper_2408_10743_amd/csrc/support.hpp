@@ -84,9 +84,10 @@ struct ExpandBatch {
   unsigned long long base;             // first thread of this launch (a slice of `threads`)
 };
 
-// Threads of a table's expansion, rounded up to whole workgroups.
+// Threads of a table's expansion (one per entry and K-step), rounded up to
+// whole workgroups.
 __host__ __device__ inline unsigned long long expand_threads(unsigned long long nent, int mks) {
-  const unsigned long long t = (nent + kChunk - 1) / kChunk * mks * kWave;
+  const unsigned long long t = (nent + kChunk - 1) / kChunk * mks * kChunk;
   return (t + 255) / 256 * 256;
 }
 
