@@ -49,7 +49,7 @@ PEAK_FP4_FLOPS = 10.1e15
 # scaled by what it reads for a 1 GiB device copy in the same runs), valid
 # only for the kernel source with this fingerprint (sha256 prefixes of
 # round.hip and kernels.hpp, the enumeration kernel and its data layouts).
-TRAFFIC = {"fingerprint": "43ad9ab4c67d65c0a38cd37dcef04b3b", "bytes_per_launch": 763021494}
+TRAFFIC = {"fingerprint": "7fd7a00cf85cf43db9ef50a5d3f3087d", "bytes_per_launch": 1174690448}
 
 
 def kernel_fingerprint():

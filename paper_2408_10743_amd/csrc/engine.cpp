@@ -475,7 +475,9 @@ void Executor::prepare_gammas(Job &job) {
   job.partial = job.D >= 2 && (job.opt.partial_weight == 1 ||
                                (job.opt.partial_weight == 0 && job.pc.predicted >= kPartialMinWork));
   // Matrix cores: the last word goes into a spare group when it is short.
-  job.mfma = job.opt.matrix_cores == 0 && job.opt.walk == 0;
+  // One word per half costs the vector ALU 5 operations per codeword, less
+  // than a K-step of 128 signs on the matrix cores.
+  job.mfma = job.opt.matrix_cores == 0 && job.opt.walk == 0 && job.D >= 2;
   job.mpack = job.D >= 3 && n - 32 * (job.D - 1) <= kMaxPackedQubits ? 1 : 0;
   job.mks = job.D - job.mpack;
   for (int j = 0; j < h; ++j) {

@@ -12,7 +12,8 @@ pytestmark = pytest.mark.gpu
 from oracle import oracle as O
 from paper_2408_10743_amd import workloads as W
 
-# n -> (D, packed last word)
+# n -> (D, packed last word); one word per half stays on the vector ALU (n = 20
+# checks that the choice keeps it exact)
 LAYOUTS = {20: (1, False), 50: (2, False), 70: (3, True), 90: (3, False), 100: (4, True), 120: (4, False)}
 
 
@@ -24,10 +25,11 @@ def Q():
     return qdist
 
 
-def big_round(rd):
-    """A round that takes the matrix cores: a saved table and at least 2^20
-    combinations (smaller rounds stay on the vector ALU)."""
-    return rd["saved_depth"] > 0 and rd["planned"] >= 1 << 20
+def big_round(rd, D=2):
+    """A round that takes the matrix cores: two or more words per half, a
+    saved table and at least 2^20 combinations (smaller rounds and one-word
+    codes stay on the vector ALU)."""
+    return D >= 2 and rd["saved_depth"] > 0 and rd["planned"] >= 1 << 20
 
 
 def swt(v):
@@ -77,7 +79,7 @@ def test_distance_matches_vector_alu(Q, n):
             assert (d0, s0.L, s0.U) == (d1, s1.L, s1.U)
             assert s0.combinations == s1.combinations
             assert s1.matrix_core_launches == 0
-            if any(big_round(rd) for rd in s0.rounds()):
+            if any(big_round(rd, s0.D) for rd in s0.rounds()):
                 assert s0.matrix_core_launches > 0
             B = O.expand(G, 2)
             assert swt(w0) == d0 and O.in_rowspace(B, w0)
@@ -95,7 +97,7 @@ def test_batch_mixed_layouts(Q):
     for (G, f), d, w, x, s in zip(codes, ds, wits, sts, stats):
         st1, d1, _, s1 = Q.qd_distance_ex(G, f, **opts)
         assert (x, d) == (st1, d1)
-        if any(big_round(rd) for rd in s.rounds()):
+        if any(big_round(rd, s.D) for rd in s.rounds()):
             assert s.matrix_core_launches > 0
         assert swt(w) == d and O.in_rowspace(O.expand(G, f), w)
 
