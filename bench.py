@@ -265,7 +265,19 @@ def kernel_roofline(stats, launches=None):
     ms = sum(s.enumerated_kernel_ms for s in stats)
     assert all(s.words == s.D * s.enumerated for s in stats), "not an every-word run"
     enumerated = sum(s.enumerated for s in stats)
-    if all(s.matrix_core_launches == s.launches and s.launches > 0 for s in stats):
+    mc = [s for s in stats if s.matrix_core_launches == s.launches and s.launches > 0]
+    va = [s for s in stats if s.matrix_core_launches == 0]
+    if mc and len(mc) < len(stats):
+        # A batch of both kinds (one-word codes and small rounds keep the vector
+        # ALU): each part against its own peak; codes whose launches were of
+        # both kinds are left out of both.
+        out = {"bound": "mixed", "frac": None, "codewords_enumerated": enumerated, "kernel_ms_total": ms,
+               "matrix_cores": kernel_roofline(mc), "codes_matrix_cores": len(mc),
+               "codes_vector_alu": len(va), "codes_both": len(stats) - len(mc) - len(va)}
+        if va:
+            out["vector_alu"] = kernel_roofline(va)
+        return out
+    if mc:
         flops = sum(s.enumerated * flops_per_codeword(s.n) for s in stats)
         hw = sum(s.enumerated * mfma_flops_per_codeword(s.n) for s in stats)
         achieved = flops / (ms * 1e-3)
