@@ -111,6 +111,29 @@ int saved_depth(const GammaDev &g, int D, int t, int cap, unsigned long long max
   return u;
 }
 
+// Partial-weight rounds on the matrix cores: the depth u <= deepest whose
+// tables cost the fewest bytes to write, the saved table (8D bytes per
+// entry) with its expanded K-step 0 (64 bytes per entry) and the tops
+// table (one element per top), among the depths whose tops fit a table.
+// The round kernel's time hardly depends on the depth (its tiles are 64
+// tops by seg entries at any depth), while the expanded table of the
+// deepest one can cost more than a tenth of the round.
+int partial_mfma_depth(const GammaDev &g, int D, int t, int deepest, unsigned long long max_tops) {
+  int best = deepest;
+  double least = -1.0;
+  for (int u = 1; u <= deepest; ++u) {
+    const unsigned long long tops = g.suffix[size_t(t - u)];
+    if (tops > max_tops) continue;
+    const double bytes = double(g.prefix[size_t(g.P) * g.R + u]) * (8.0 * D + double(kWave * sizeof(uint4)) / kChunk) +
+                         double(tops) * (kElemWords * 4);
+    if (least < 0 || bytes < least) {
+      least = bytes;
+      best = u;
+    }
+  }
+  return best;
+}
+
 // Table entries per tile: long enough to amortize a tile's setup, short
 // enough that the round gives its share (1/sharing) of about kTargetTiles
 // tiles per step, where `sharing` codes run their rounds in the same steps.
@@ -708,7 +731,7 @@ void Executor::release_tables(Job &job) {
 int Executor::ensure_mtable(Job &job, GammaDev &g, int u, int mks) {
   if (g.mtable[u].p && g.mtable_ks[u] >= mks) return QD_OK;
   const unsigned long long nent = g.prefix[size_t(g.P) * g.R + u];
-  const unsigned long long chunks = (nent + kChunk - 1) / kChunk;
+  const unsigned long long chunks = (nent + kChunk - 1) / kChunk + kMtablePadChunks;
   const size_t bytes = size_t(chunks) * mks * kWave * sizeof(uint4);
   release_mtable(g, u);
   if (mtable_held_ + bytes > mtable_budget_ || !alloc(g.mtable[u], bytes)) {
@@ -943,6 +966,10 @@ int Executor::schedule(Job &job, int sharing) {
     f.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : tuned ? tseg : choose_seg(planned, sharing, long_seg_);
     const int tm = job.opt.tops_mode;
     const unsigned long long max_tops = std::min(kMaxTopEntries, max_table_bytes_ / (kElemWords * 4));
+    const bool expanded = planned >= mfma_min_round_ && job.mfma && !arena() && !job.force_words &&
+                          job.census_below == 0;  // the saved table gets its matrix-core form
+    if (expanded && job.partial && !tuned && job.opt.saved_depth == 0 && tm == 0 && planned > kTinyRound)
+      f.u = partial_mfma_depth(g, job.D, t, f.u, max_tops);
     f.use_tops = tm == 1 || (tm == 0 && g.suffix[t - f.u] <= max_tops);
     if (planned <= kTinyRound && job.opt.saved_depth == 0 && tm == 0) {
       f.u = 0;
@@ -950,9 +977,7 @@ int Executor::schedule(Job &job, int sharing) {
     }
     int rc = f.u > 0 ? ensure_table(job, g, f.u, false) : QD_OK;
     if (!rc && f.use_tops) rc = ensure_table(job, g, t - f.u, true);
-    if (!rc && f.u > 0 && planned >= mfma_min_round_ && job.mfma && !arena() && !job.force_words &&
-        job.census_below == 0)
-      rc = ensure_mtable(job, g, f.u, job.partial ? 1 : job.mks);
+    if (!rc && f.u > 0 && expanded) rc = ensure_mtable(job, g, f.u, job.partial ? 1 : job.mks);
     if (rc) return rc;
     f.tiles = plan_round(g, t, f.u, f.seg, job.scalar, f.hg, f.hr);
     f.planned = planned;

@@ -113,9 +113,11 @@ struct RoundDesc {
   // is 32 - 2 popcount(a ^ b), and over x, z and x ^ z each qubit where
   // the sum is not identity contributes exactly 2 to the popcounts.  With
   // G groups, dot = 32 G - 4 wt.  K-step s (128 signs, one MFMA) holds the
-  // groups x_s, z_s, x_s ^ z_s and a fourth group that is empty, or, with
-  // mpack, for s = D - 2 the last word packed as x | z << 10 | (x ^ z) << 20
-  // (at most 10 qubits in it).  mtable: chunk c of 16 entries, K-step s:
+  // groups x_s, z_s, x_s ^ z_s and a fourth group: for s = 0 the bias group
+  // (32 values 2.0: against the tops' bias codes it adds 32 G, so the
+  // products sum to 4 wt with no accumulator input); with mpack, for
+  // s = D - 2 the last word packed as x | z << 10 | (x ^ z) << 20 (at most
+  // 10 qubits in it); else empty.  mtable: chunk c of 16 entries, K-step s:
   // 64 lanes x 16 bytes at (c * mks + s) * 64 + lane, lane = 16 g + r for
   // group g of entry 16 c + r, dword i holding the e2m1 codes of bits
   // 8i..8i+7 (nibble j: bit 8i + j).  mks: K-steps stored per chunk (1: the
@@ -161,6 +163,9 @@ inline unsigned int walk_lds_bytes(int P, int t) {
 
 // Matrix-core layout of table entries and tops (RoundDesc::mtable).
 constexpr int kChunk = 16;             // table entries per chunk (MFMA rows)
+// Chunks allocated past an expanded table's last (never written): the
+// shared-chunk stream of the round kernel reads whole groups of chunks.
+constexpr int kMtablePadChunks = 4;
 constexpr int kMaxPackedQubits = 10;   // last word packed into a spare group
 
 // e2m1 codes of 8 sign bits: nibble j is -1.0 (0xA) for bit j set, +1.0
@@ -172,6 +177,20 @@ __device__ __forceinline__ uint32_t sign_nibbles(uint32_t b) {
   x = (x | (x << 3)) & 0x11111111u;
   return (x << 3) | 0x22222222u;
 }
+
+// Bias group of K-step 0 (the fourth group; never the packed one, which
+// needs D >= 3 and sits in K-step D - 2): table entries hold e2m1 2.0 in
+// all 32 places, and a top's B operand holds, in dwords 0-1 and 2-3, the
+// codes of two values v_lo, v_hi with v_lo + v_hi = G, so the group adds
+// 8 x 2 x (2 v_lo + 2 v_hi) = 32 G.  G is 3 (first word alone) or
+// 3 KS + (KS < D): 6, 7, 9, 10 or 12.
+constexpr uint32_t kBiasEntry = 0x44444444u;
+__host__ __device__ constexpr uint32_t bias_code(int G, bool hi) {
+  // e2m1 codes: 0x3 = 1.5, 0x5 = 3.0, 0x6 = 4.0, 0x7 = 6.0
+  return (G == 3 ? 0x3u : G == 6 ? 0x5u : G == 7 ? (hi ? 0x6u : 0x5u) : G == 9 ? (hi ? 0x7u : 0x5u)
+          : G == 10 ? (hi ? 0x7u : 0x6u) : G == 12 ? 0x7u : 0x0u) * 0x11111111u;
+}
+static_assert(bias_code(3, false) == 0x33333333u && bias_code(10, true) == 0x77777777u, "bias codes");
 
 // Group g of K-step s of a codeword: x_s, z_s, x_s ^ z_s, or (g = 3) the
 // packed last word (xl, zl) when `packed` (else an empty group).

@@ -325,9 +325,9 @@ __device__ __forceinline__ uint32_t partial_blocks(const uint32_t (&ax)[D], cons
 // kernels.hpp).  Entries are the A rows (lane 16 g + r: row r, group g),
 // tops the B columns (lane 16 g + r: top 16 nb + r of block nb), and lane
 // 16 q + r receives rows 4q..4q+3 of column r.  The tops' signs are
-// negated, so the accumulator starts at C and ends at C - dot: with
-// C = 32 G it is 4 wt, an exact non-negative float whose bits order like
-// the weights.
+// negated, so the sign groups sum to -dot = 4 wt - 32 G, and the bias group
+// of K-step 0 adds 32 G: the accumulator (zero input) ends at 4 wt, an
+// exact non-negative float whose bits order like the weights.
 // Every word on the matrix cores: kMfmaEveryWord picks the K-step layout per
 // piece; kMfmaEveryPacked / kMfmaEveryPlain serve launches whose pieces all
 // have the packed (K-steps D - 1) / plain (K-steps D) layout, with the
@@ -347,9 +347,11 @@ __device__ __forceinline__ v8i_t mfma_operand(uint4 a) {
                  0};
 }
 
-// B operands of K-steps 0..KU-1 from the wave's tops (lane l holds top l);
-// tops at or past ntop give zero operands.
-template <int D, int KU>
+// B operands of K-steps 0..KU-1 from the wave's tops (lane l holds top l)
+// for G sign groups: the tops' signs negated, so a column's products sum
+// to 4 wt - 32 G, and the bias group of K-step 0 adds 32 G back (every top,
+// so a top at or past ntop, whose other groups are zero, reads 8 G).
+template <int D, int KU, int G>
 __device__ __forceinline__ void mfma_tops(const uint32_t (&ax)[D], const uint32_t (&az)[D], uint32_t lane, int ntop,
                                           bool pack, v8i_t (&B)[KU][4]) {
   const int g = static_cast<int>(lane >> 4);
@@ -363,22 +365,24 @@ __device__ __forceinline__ void mfma_tops(const uint32_t (&ax)[D], const uint32_
       const uint32_t xl = D >= 3 ? bcast(ax[D - 1], src) : 0u, zl = D >= 3 ? bcast(az[D - 1], src) : 0u;
       const uint32_t w = group_word(g, packed, x, z, xl, zl);
       const bool on = src < ntop && (g < 3 || packed);
+      const bool bias = s == 0 && g == 3;
       const uint32_t neg = 0x88888888u;  // sign bit of every nibble
-      B[s][nb] = (v8i_t){static_cast<int>(on ? sign_nibbles(w) ^ neg : 0u),
-                         static_cast<int>(on ? sign_nibbles(w >> 8) ^ neg : 0u),
-                         static_cast<int>(on ? sign_nibbles(w >> 16) ^ neg : 0u),
-                         static_cast<int>(on ? sign_nibbles(w >> 24) ^ neg : 0u), 0, 0, 0, 0};
+      const uint32_t lo = bias_code(G, false), hi = bias_code(G, true);
+      B[s][nb] = (v8i_t){static_cast<int>(on ? sign_nibbles(w) ^ neg : bias ? lo : 0u),
+                         static_cast<int>(on ? sign_nibbles(w >> 8) ^ neg : bias ? lo : 0u),
+                         static_cast<int>(on ? sign_nibbles(w >> 16) ^ neg : bias ? hi : 0u),
+                         static_cast<int>(on ? sign_nibbles(w >> 24) ^ neg : bias ? hi : 0u), 0, 0, 0, 0};
     }
 }
 
 // One chunk, every word, from its A operands: bd[nb] keeps the least 4 wt
 // (as float bits) of the lane's column of block nb.
 template <int KS>
-__device__ __forceinline__ void mfma_every_chunk(const v8i_t (&A)[KS], const v8i_t (&B)[KS][4], v4f_t c0,
-                                                 uint32_t (&bd)[4]) {
+__device__ __forceinline__ void mfma_every_chunk(const v8i_t (&A)[KS], const v8i_t (&B)[KS][4], uint32_t (&bd)[4]) {
+  const v4f_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
   v4f_t acc[4];
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_fp4(A[0], B[0][nb], c0);
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_fp4(A[0], B[0][nb], zero);
 #pragma unroll
   for (int s = 1; s < KS; ++s)
 #pragma unroll
@@ -391,10 +395,11 @@ __device__ __forceinline__ void mfma_every_chunk(const v8i_t (&A)[KS], const v8i
 }
 
 // One chunk on K-step 0: the least 4 w0 over the chunk's 16 x 64 outputs.
-__device__ __forceinline__ uint32_t mfma_first_chunk(v8i_t A, const v8i_t (&B)[1][4], v4f_t c0) {
+__device__ __forceinline__ uint32_t mfma_first_chunk(v8i_t A, const v8i_t (&B)[1][4]) {
+  const v4f_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
   v4f_t acc[4];
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_fp4(A, B[0][nb], c0);
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_fp4(A, B[0][nb], zero);
   uint32_t pm = 0xFFFFFFFFu;
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) {
@@ -406,29 +411,30 @@ __device__ __forceinline__ uint32_t mfma_first_chunk(v8i_t A, const v8i_t (&B)[1
 
 // Chunks shared by the four waves of a workgroup (same table segment):
 // they stream through LDS in groups of kCoopChunks, double-buffered, each
-// thread moving 16 bytes per K-step, so a chunk is read from memory once
-// for the workgroup's 256 tops instead of once per wave.  Group g + 1 is
-// loaded while group g is evaluated; one barrier per group.
+// thread moving 16 bytes (wave u: chunk u of the group, K-step 0), so a
+// chunk is read from memory once for the workgroup's 256 tops instead of
+// once per wave.  Group g + 1 is loaded while group g is evaluated; one
+// barrier per group.  The last group may reach past the shared chunks,
+// at most kCoopChunks - 1 chunks past the table's last: that read stays
+// in the expanded table's padding and its values are never used.
 constexpr int kCoopChunks = 4;  // kCoopChunks * kWave = threads of a workgroup
+static_assert(kCoopChunks * kWave == kWave * kWavesPerGroup && kCoopChunks <= kMtablePadChunks, "coop groups");
 
-template <int KU>
 struct CoopStream {
-  static constexpr int kPer = kCoopChunks * KU * kWave;  // uint4 per buffer
-  uint4 r[KU];
-  __device__ __forceinline__ void load(const uint4 *__restrict__ mtab, int mks, uint32_t c0, uint32_t nu) {
-    const int t = static_cast<int>(threadIdx.x);
-#pragma unroll
-    for (int q = 0; q < KU; ++q) {
-      const int idx = q * kWavesPerGroup * kWave + t;
-      const uint32_t u = static_cast<uint32_t>(idx / (KU * kWave));
-      const int s = (idx / kWave) % KU;
-      r[q] = u < nu ? mtab[(static_cast<size_t>(c0 + u) * mks + s) * kWave + (idx % kWave)] : uint4{0u, 0u, 0u, 0u};
-    }
+  static constexpr int kPer = kCoopChunks * kWave;  // uint4 per buffer
+  const uint4 *src;
+  size_t step;
+  uint4 r;
+  __device__ __forceinline__ void start(const uint4 *__restrict__ mtab, int mks, uint32_t c) {
+    step = static_cast<size_t>(kCoopChunks) * mks * kWave;
+    src = mtab + (static_cast<size_t>(c) + threadIdx.x / kWave) * mks * kWave + threadIdx.x % kWave;
+    r = *src;
   }
-  __device__ __forceinline__ void store(uint4 *buf) const {
-#pragma unroll
-    for (int q = 0; q < KU; ++q) buf[q * kWavesPerGroup * kWave + threadIdx.x] = r[q];
+  __device__ __forceinline__ void next() {
+    src += step;
+    r = *src;
   }
+  __device__ __forceinline__ void store(uint4 *buf) const { buf[threadIdx.x] = r; }
 };
 
 // Every word of chunks [ca, cz) against the wave's tops; the least weight
@@ -438,11 +444,9 @@ constexpr int kMfmaUnroll = 2;  // chunks per group of loads (a wave alone)
 template <int D, int KS>
 __device__ uint32_t mfma_every(const uint4 *__restrict__ mtab, uint32_t ca, uint32_t cz, uint32_t lane,
                                const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop, bool pack) {
-  v8i_t B[KS][4];
-  mfma_tops<D, KS>(ax, az, lane, ntop, pack, B);
   constexpr int G = 3 * KS + (KS < D ? 1 : 0);  // sign groups (packed last word: one)
-  const float cf = static_cast<float>(32 * G);
-  const v4f_t c0 = {cf, cf, cf, cf};
+  v8i_t B[KS][4];
+  mfma_tops<D, KS, G>(ax, az, lane, ntop, pack, B);
   uint32_t bd[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
   uint32_t c = ca;
   const uint4 *mb = mtab + static_cast<size_t>(c) * KS * kWave + lane;
@@ -452,14 +456,14 @@ __device__ uint32_t mfma_every(const uint4 *__restrict__ mtab, uint32_t ca, uint
       v8i_t A[KS];
 #pragma unroll
       for (int s = 0; s < KS; ++s) A[s] = mfma_operand(mb[(u * KS + s) * kWave]);
-      mfma_every_chunk<KS>(A, B, c0, bd);
+      mfma_every_chunk<KS>(A, B, bd);
     }
   }
   for (; c < cz; ++c, mb += KS * kWave) {
     v8i_t A[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) A[s] = mfma_operand(mb[s * kWave]);
-    mfma_every_chunk<KS>(A, B, c0, bd);
+    mfma_every_chunk<KS>(A, B, bd);
   }
   uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
@@ -471,7 +475,7 @@ __device__ uint32_t mfma_every(const uint4 *__restrict__ mtab, uint32_t ca, uint
 
 // Partial weights on the first word, chunks [ca, cz) ([ca, cs) shared with
 // the workgroup, sbuf: 2 x kCoopChunks x 64 uint4): K-step 0 alone gives
-// 4 w0 (C = 96: the three groups of word 0); a chunk where some lane sees
+// 4 w0 (bias 96: the three groups of word 0); a chunk where some lane sees
 // w0 below thr is completed on the vector ALU (the lane's own top against
 // the chunk's two blocks, every word) and counted in `done`.
 template <int D, bool kCensus>
@@ -496,29 +500,28 @@ __device__ uint32_t mfma_partial(const uint32_t *__restrict__ table, const uint4
                                  const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop, bool pack, uint32_t thr,
                                  uint32_t best, uint32_t &done, Census &cs) {
   v8i_t B[1][4];
-  mfma_tops<D, 1>(ax, az, lane, ntop, pack, B);
-  const v4f_t c0 = {96.0f, 96.0f, 96.0f, 96.0f};
+  mfma_tops<D, 1, 3>(ax, az, lane, ntop, pack, B);  // the three groups of word 0
   const uint32_t T = __float_as_uint(static_cast<float>(4 * thr));
   uint32_t c = ca;
   if (coop) {
-    CoopStream<1> st;
-    constexpr int kPer = CoopStream<1>::kPer;
-    st.load(mtab, mks, c, min(kCoopChunks, static_cast<int>(cs_end - c)));
+    CoopStream st;
+    constexpr int kPer = CoopStream::kPer;
+    st.start(mtab, mks, c);
     st.store(sbuf);
     __syncthreads();
     for (int g = 0; c < cs_end; ++g, c += kCoopChunks) {
       const int nu = min(kCoopChunks, static_cast<int>(cs_end - c));
       const bool more = c + kCoopChunks < cs_end;
-      if (more) st.load(mtab, mks, c + kCoopChunks, min(kCoopChunks, static_cast<int>(cs_end - c - kCoopChunks)));
+      if (more) st.next();
       const uint4 *cur = sbuf + (g & 1) * kPer;
       uint32_t pm[kCoopChunks];
       if (nu == kCoopChunks) {  // a full group: one straight block the compiler can interleave
 #pragma unroll
-        for (int u = 0; u < kCoopChunks; ++u) pm[u] = mfma_first_chunk(mfma_operand(cur[u * kWave + lane]), B, c0);
+        for (int u = 0; u < kCoopChunks; ++u) pm[u] = mfma_first_chunk(mfma_operand(cur[u * kWave + lane]), B);
       } else {
 #pragma unroll
         for (int u = 0; u < kCoopChunks; ++u)
-          pm[u] = u < nu ? mfma_first_chunk(mfma_operand(cur[u * kWave + lane]), B, c0) : 0xFFFFFFFFu;
+          pm[u] = u < nu ? mfma_first_chunk(mfma_operand(cur[u * kWave + lane]), B) : 0xFFFFFFFFu;
       }
       const uint32_t any = min(min(pm[0], pm[1]), min(pm[2], pm[3]));
       if (__ballot(any < T)) best = complete_chunks<D, kCensus>(table, c, nu, pm, T, ax, az, best, done, cs);
@@ -533,7 +536,7 @@ __device__ uint32_t mfma_partial(const uint32_t *__restrict__ table, const uint4
     const int nu = min(kMfmaUnroll, static_cast<int>(cz - c));
     uint32_t pm[kMfmaUnroll];
 #pragma unroll
-    for (int u = 0; u < kMfmaUnroll; ++u) pm[u] = u < nu ? mfma_first_chunk(mfma_operand(mb[u * stride]), B, c0) : 0xFFFFFFFFu;
+    for (int u = 0; u < kMfmaUnroll; ++u) pm[u] = u < nu ? mfma_first_chunk(mfma_operand(mb[u * stride]), B) : 0xFFFFFFFFu;
     uint32_t any = pm[0];
 #pragma unroll
     for (int u = 1; u < kMfmaUnroll; ++u) any = min(any, pm[u]);

@@ -120,8 +120,9 @@ __global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
 // counts.
 // Matrix-core forms of a step's saved tables (ExpandBatch): thread t of a
 // table reads entry 16 c + r of chunk c once and writes its four groups of
-// K-step s (t = (c mks + s) 16 + r); each of its four 16-byte stores meets
-// those of the 15 neighbouring entries in one contiguous 256-byte run.
+// K-step s (t = (c mks + s) 16 + r; the fourth of K-step 0 is the bias
+// group); each of its four 16-byte stores meets those of the 15
+// neighbouring entries in one contiguous 256-byte run.
 __global__ __launch_bounds__(256) void qd_expand_kernel(ExpandBatch eb) {
   const unsigned long long wfirst = eb.base + static_cast<unsigned long long>(blockIdx.x) * blockDim.x;
   if (wfirst >= eb.threads) return;
@@ -164,6 +165,8 @@ __global__ __launch_bounds__(256) void qd_expand_kernel(ExpandBatch eb) {
       o.y = sign_nibbles(w >> 8);
       o.z = sign_nibbles(w >> 16);
       o.w = sign_nibbles(w >> 24);
+    } else if (e < ep.nent && s == 0) {
+      o = uint4{kBiasEntry, kBiasEntry, kBiasEntry, kBiasEntry};
     }
     out[g * kChunk] = o;
   }
