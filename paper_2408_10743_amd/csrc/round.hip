@@ -350,29 +350,42 @@ __device__ __forceinline__ v8i_t mfma_operand(uint4 a) {
 // B operands of K-steps 0..KU-1 from the wave's tops (lane l holds top l)
 // for G sign groups: the tops' signs negated, so a column's products sum
 // to 4 wt - 32 G, and the bias group of K-step 0 adds 32 G back (every top,
-// so a top at or past ntop, whose other groups are zero, reads 8 G).
+// so a top at or past ntop, whose other groups are zero, reads 8 G).  Each
+// byte of a group word becomes its dword of negated e2m1 signs through
+// `neg_lut` (256 entries in LDS, filled by the workgroup).
 template <int D, int KU, int G>
 __device__ __forceinline__ void mfma_tops(const uint32_t (&ax)[D], const uint32_t (&az)[D], uint32_t lane, int ntop,
-                                          bool pack, v8i_t (&B)[KU][4]) {
+                                          bool pack, const uint32_t *neg_lut, v8i_t (&B)[KU][4]) {
   const int g = static_cast<int>(lane >> 4);
+  // Group g of a word from its x and z halves without branches: x, z or
+  // x ^ z (g = 3: empty unless packed).
+  const uint32_t mx = g == 0 || g == 2 ? ~0u : 0u, mz = g == 1 || g == 2 ? ~0u : 0u;
+  const uint32_t lo = g == 3 ? bias_code(G, false) : 0u, hi = g == 3 ? bias_code(G, true) : 0u;
 #pragma unroll
   for (int s = 0; s < KU; ++s)
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
       const int src = nb * kChunk + static_cast<int>(lane & 15);
       const bool packed = pack && s == D - 2;
-      const uint32_t x = bcast(ax[s], src), z = bcast(az[s], src);
-      const uint32_t xl = D >= 3 ? bcast(ax[D - 1], src) : 0u, zl = D >= 3 ? bcast(az[D - 1], src) : 0u;
-      const uint32_t w = group_word(g, packed, x, z, xl, zl);
+      uint32_t w = (bcast(ax[s], src) & mx) ^ (bcast(az[s], src) & mz);
+      if (packed) {
+        const uint32_t xl = bcast(ax[D - 1], src), zl = bcast(az[D - 1], src);
+        w = g == 3 ? xl | (zl << 10) | ((xl ^ zl) << 20) : w;
+      }
       const bool on = src < ntop && (g < 3 || packed);
-      const bool bias = s == 0 && g == 3;
-      const uint32_t neg = 0x88888888u;  // sign bit of every nibble
-      const uint32_t lo = bias_code(G, false), hi = bias_code(G, true);
-      B[s][nb] = (v8i_t){static_cast<int>(on ? sign_nibbles(w) ^ neg : bias ? lo : 0u),
-                         static_cast<int>(on ? sign_nibbles(w >> 8) ^ neg : bias ? lo : 0u),
-                         static_cast<int>(on ? sign_nibbles(w >> 16) ^ neg : bias ? hi : 0u),
-                         static_cast<int>(on ? sign_nibbles(w >> 24) ^ neg : bias ? hi : 0u), 0, 0, 0, 0};
+      // Every index is below 256: read all four, then choose.
+      const uint32_t l0 = neg_lut[w & 0xFFu], l1 = neg_lut[(w >> 8) & 0xFFu], l2 = neg_lut[(w >> 16) & 0xFFu],
+                     l3 = neg_lut[w >> 24];
+      const uint32_t b0 = s == 0 ? lo : 0u, b1 = s == 0 ? hi : 0u;  // the bias group, or an empty one
+      B[s][nb] = (v8i_t){static_cast<int>(on ? l0 : b0), static_cast<int>(on ? l1 : b0),
+                         static_cast<int>(on ? l2 : b1), static_cast<int>(on ? l3 : b1), 0, 0, 0, 0};
     }
+}
+
+// Fills the workgroup's negated-sign table (a barrier must follow).
+__device__ __forceinline__ void fill_neg_lut(uint32_t *neg_lut) {
+  static_assert(kWave * kWavesPerGroup == 256, "one entry per thread");
+  neg_lut[threadIdx.x] = sign_nibbles(threadIdx.x) ^ 0x88888888u;  // sign bit of every nibble flipped
 }
 
 // One chunk, every word, from its A operands: bd[nb] keeps the least 4 wt
@@ -443,10 +456,11 @@ struct CoopStream {
 constexpr int kMfmaUnroll = 2;  // chunks per group of loads (a wave alone)
 template <int D, int KS>
 __device__ uint32_t mfma_every(const uint4 *__restrict__ mtab, uint32_t ca, uint32_t cz, uint32_t lane,
-                               const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop, bool pack) {
+                               const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop, bool pack,
+                               const uint32_t *neg_lut) {
   constexpr int G = 3 * KS + (KS < D ? 1 : 0);  // sign groups (packed last word: one)
   v8i_t B[KS][4];
-  mfma_tops<D, KS, G>(ax, az, lane, ntop, pack, B);
+  mfma_tops<D, KS, G>(ax, az, lane, ntop, pack, neg_lut, B);
   uint32_t bd[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
   uint32_t c = ca;
   const uint4 *mb = mtab + static_cast<size_t>(c) * KS * kWave + lane;
@@ -497,10 +511,10 @@ __device__ __forceinline__ uint32_t complete_chunks(const uint32_t *__restrict__
 template <int D, bool kCensus>
 __device__ uint32_t mfma_partial(const uint32_t *__restrict__ table, const uint4 *__restrict__ mtab, int mks,
                                  uint32_t ca, uint32_t cs_end, uint32_t cz, bool coop, uint4 *sbuf, uint32_t lane,
-                                 const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop, bool pack, uint32_t thr,
-                                 uint32_t best, uint32_t &done, Census &cs) {
+                                 const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop, bool pack,
+                                 const uint32_t *neg_lut, uint32_t thr, uint32_t best, uint32_t &done, Census &cs) {
   v8i_t B[1][4];
-  mfma_tops<D, 1, 3>(ax, az, lane, ntop, pack, B);  // the three groups of word 0
+  mfma_tops<D, 1, 3>(ax, az, lane, ntop, pack, neg_lut, B);  // the three groups of word 0
   const uint32_t T = __float_as_uint(static_cast<float>(4 * thr));
   uint32_t c = ca;
   if (coop) {
@@ -635,7 +649,9 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   constexpr bool kCoop = kMode == kMfmaPartial;
   __shared__ unsigned long long coop_slot[kWavesPerGroup];
   __shared__ uint4 coop_buf[kCoop ? 2 * kCoopChunks * kWave : 1];
+  __shared__ uint32_t neg_lut[kMfma ? kWave * kWavesPerGroup : 1];
   if (kCoop && (threadIdx.x & (kWave - 1)) == 0) coop_slot[threadIdx.x / kWave] = ~0ull;
+  if constexpr (kMfma) fill_neg_lut(neg_lut);
 
   // Unranking reads suffix columns, the group table and the elements with
   // data-dependent addresses: stage them in LDS once per workgroup.
@@ -657,9 +673,9 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
       E = sE;
       ld = C;
     }
-    if constexpr (!kCoop) __syncthreads();
+    if constexpr (!kMfma) __syncthreads();
   }
-  if constexpr (kCoop) __syncthreads();  // staged tables; every wave's coop_slot cleared
+  if constexpr (kMfma) __syncthreads();  // staged tables, neg_lut; every wave's coop_slot cleared
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const unsigned long long local = wtile + wave - p.tile_begin;  // tile within the piece
@@ -779,13 +795,13 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
     if constexpr (kMfmaEvery) {
       constexpr int kPackedKs = D >= 3 ? D - 1 : D;
       if constexpr (kMode == kMfmaEveryPacked)
-        best_em = mfma_every<D, kPackedKs>(p.mtable, ca, cz, lane, ax, az, ntop, true);
+        best_em = mfma_every<D, kPackedKs>(p.mtable, ca, cz, lane, ax, az, ntop, true, neg_lut);
       else if constexpr (kMode == kMfmaEveryPlain)
-        best_em = mfma_every<D, D>(p.mtable, ca, cz, lane, ax, az, ntop, false);
+        best_em = mfma_every<D, D>(p.mtable, ca, cz, lane, ax, az, ntop, false, neg_lut);
       else if (D >= 3 && p.mpack)
-        best_em = mfma_every<D, kPackedKs>(p.mtable, ca, cz, lane, ax, az, ntop, true);
+        best_em = mfma_every<D, kPackedKs>(p.mtable, ca, cz, lane, ax, az, ntop, true, neg_lut);
       else
-        best_em = mfma_every<D, D>(p.mtable, ca, cz, lane, ax, az, ntop, false);
+        best_em = mfma_every<D, D>(p.mtable, ca, cz, lane, ax, az, ntop, false, neg_lut);
       for (uint32_t i = 0; i < head; ++i, blk += 2 * D * kBlock) best = block_min<D, kCensus>(ax, az, blk, best, cs);
       blk += mid * (2 * D * kBlock);
       for (uint32_t i = head + mid; i < nfull; ++i, blk += 2 * D * kBlock)
@@ -794,7 +810,7 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
       const int c = p.credit[0];
       const uint32_t thr = U0 > c ? static_cast<uint32_t>(U0 - c) : 0u;
       best = mfma_partial<D, kCensus>(p.table, p.mtable, p.mks, ca, cs_end, cz, coop, coop_buf, lane, ax, az, ntop,
-                                      p.mpack != 0, thr, best, mf_done, cs);
+                                      p.mpack != 0, neg_lut, thr, best, mf_done, cs);
       best = partial_blocks<D, 1, kCensus>(ax, az, blk, head, best, thr, rec, cs);
       best = partial_blocks<D, 1, kCensus>(ax, az, blk + (head + mid) * (2 * D * kBlock), nfull - head - mid, best,
                                            thr, rec, cs);
