@@ -709,13 +709,19 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
 #pragma unroll
   for (int d = 0; d < D; ++d) ax[d] = az[d] = 0;
   unsigned long long lend = k1;  // this lane's end of the segment
+  // The lane's group: the tile's 64 items are consecutive, so the group
+  // of the first one is found by the whole wave at once, and a lane steps
+  // past the groups that start inside the tile at or below its item (few,
+  // usually none).
+  const unsigned long long item0 = b * kWave;
+  const int ne = static_cast<int>(run.e);
+  int a = wave_last_le(ne, item0, [GR](int i) { return GR[i].cum; });
+  for (int j = a + 1; j < ne; ++j) {
+    const unsigned long long cj = GR[j].cum;  // the same for every lane
+    if (cj >= item0 + kWave) break;
+    if (item >= cj) a = j;
+  }
   if (active) {
-    int a = 0, z = static_cast<int>(run.e);
-    while (z - a > 1) {
-      const int mid = (a + z) >> 1;
-      if (GR[mid].cum <= item) a = mid;
-      else z = mid;
-    }
     lend = min(k1, GR[a].len);
     if (p.tops) {
       const uint4 *tp = reinterpret_cast<const uint4 *>(p.tops + (GR[a].top0 + item - GR[a].cum) * kElemWords);
