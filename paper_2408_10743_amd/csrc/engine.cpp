@@ -21,7 +21,7 @@ namespace {
 
 constexpr int kDefaultSavedDepth = 4;                     // packages per saved-table entry
 constexpr unsigned long long kMaxTableBytes = 1ull << 29;
-constexpr unsigned long long kMaxTopEntries = 1ull << 24;  // 512 MB of tops
+constexpr unsigned long long kMaxTopEntries = 1ull << 24;  // at most 512 MB of tops (D = 4)
 constexpr unsigned long long kTilesPerLaunch = 1ull << 22;
 constexpr unsigned long long kTargetTiles = 1ull << 18;    // ~32 tiles per wave slot
 constexpr unsigned kMinSeg = 1024, kMaxSeg = 4096;
@@ -114,7 +114,7 @@ int saved_depth(const GammaDev &g, int D, int t, int cap, unsigned long long max
 // Partial-weight rounds on the matrix cores: the depth u <= deepest whose
 // tables cost the fewest bytes to write, the saved table (8D bytes per
 // entry) with its expanded K-step 0 (64 bytes per entry) and the tops
-// table (one element per top), among the depths whose tops fit a table.
+// table (8D bytes per top), among the depths whose tops fit a table.
 // The round kernel's time hardly depends on the depth (its tiles are 64
 // tops by seg entries at any depth), while the expanded table of the
 // deepest one can cost more than a tenth of the round.
@@ -125,7 +125,7 @@ int partial_mfma_depth(const GammaDev &g, int D, int t, int deepest, unsigned lo
     const unsigned long long tops = g.suffix[size_t(t - u)];
     if (tops > max_tops) continue;
     const double bytes = double(g.prefix[size_t(g.P) * g.R + u]) * (8.0 * D + double(kWave * sizeof(uint4)) / kChunk) +
-                         double(tops) * (kElemWords * 4);
+                         double(tops) * (8.0 * D);
     if (least < 0 || bytes < least) {
       least = bytes;
       best = u;
@@ -592,7 +592,7 @@ size_t Executor::footprint(const Job &job) {
     for (int u = 0; u <= std::min(kDefaultSavedDepth, g.R - 1); ++u)
       b += size_t(std::min<uint64_t>(g.prefix[size_t(g.P) * g.R + u] * 8ull * job.D, kMaxTableBytes));
     for (int k = 1; k <= std::min(3, g.R - 1); ++k)
-      b += size_t(std::min<uint64_t>(g.suffix[k], kMaxTopEntries) * 32ull);
+      b += size_t(std::min<uint64_t>(g.suffix[k], kMaxTopEntries) * 8ull * job.D);
   }
   return b;
 }
@@ -686,7 +686,7 @@ int Executor::ensure_table(Job &job, GammaDev &g, int u, bool tops) {
     level = levels[u - 1] + 1;  // 0 when it was built by an earlier step
   }
   const unsigned long long padded = (nent + kBuildGroup - 1) / kBuildGroup * kBuildGroup;
-  if (!alloc(buf, size_t(padded) * (tops ? kElemWords : 2 * job.D) * 4)) return QD_ERR_NOMEM;
+  if (!alloc(buf, size_t(padded) * 2 * job.D * 4)) return QD_ERR_NOMEM;  // 2D words per entry, either kind
   SavedParams sp{};
   sp.elems = g.elems;
   sp.prefix = g.dprefix;
@@ -965,7 +965,7 @@ int Executor::schedule(Job &job, int sharing) {
     f.u = saved_depth(g, job.D, t, cap, max_table_bytes_);
     f.seg = job.opt.seg_len ? unsigned(job.opt.seg_len) : tuned ? tseg : choose_seg(planned, sharing, long_seg_);
     const int tm = job.opt.tops_mode;
-    const unsigned long long max_tops = std::min(kMaxTopEntries, max_table_bytes_ / (kElemWords * 4));
+    const unsigned long long max_tops = std::min(kMaxTopEntries, max_table_bytes_ / (8ull * job.D));
     const bool expanded = planned >= mfma_min_round_ && job.mfma && !arena() && !job.force_words &&
                           job.census_below == 0;  // the saved table gets its matrix-core form
     if (expanded && job.partial && !tuned && job.opt.saved_depth == 0 && tm == 0 && planned > kTinyRound)

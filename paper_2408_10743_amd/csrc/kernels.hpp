@@ -77,7 +77,7 @@ struct WalkPart {
 struct RoundDesc {
   const uint32_t *elems;               // package i element e: (3i+e)*kElemWords
   const uint32_t *table;               // saved sums, blocks of kBlock entries
-  const uint32_t *tops;                // top codewords, kElemWords each (NULL: unrank)
+  const uint32_t *tops;                // top codewords, 2D words each: x, then z (NULL: unrank)
   const DevGroup *groups;              // sorted by len, longest first
   const DevRun *runs;
   const unsigned long long *suffix;    // (P+1) x R: e_r(c_h..c_{P-1})

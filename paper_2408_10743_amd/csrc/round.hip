@@ -724,13 +724,11 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   if (active) {
     lend = min(k1, GR[a].len);
     if (p.tops) {
-      const uint4 *tp = reinterpret_cast<const uint4 *>(p.tops + (GR[a].top0 + item - GR[a].cum) * kElemWords);
-      const uint4 tx = tp[0], tz = tp[1];
-      const uint32_t vx[4] = {tx.x, tx.y, tx.z, tx.w}, vz[4] = {tz.x, tz.y, tz.z, tz.w};
+      const uint32_t *tp = p.tops + (GR[a].top0 + item - GR[a].cum) * (2 * D);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        ax[d] = vx[d];
-        az[d] = vz[d];
+        ax[d] = tp[d];
+        az[d] = tp[D + d];
       }
     } else {
       unrank_top<D>(F, ld, E, p.csize, p.P, p.t - p.u - 1, static_cast<int>(GR[a].h), item - GR[a].cum, ax,

@@ -63,11 +63,11 @@ __global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
     while (rest >= f && c < 2) { rest -= f; ++c; }
     xor_elem<D>(p.elems, p.tops ? p.P - 1 - a : a, c, x, z);
     if (p.tops) {
-      const uint32_t *q = p.src + rest * kElemWords;
+      const uint32_t *q = p.src + rest * (2 * D);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         x[d] ^= q[d];
-        z[d] ^= q[4 + d];
+        z[d] ^= q[D + d];
       }
     } else {
       const uint32_t *q = p.src + (rest / kBlock) * (2 * D * kBlock) + (rest % kBlock);
@@ -98,11 +98,11 @@ __global__ __launch_bounds__(kBuildGroup) void qd_build_kernel(BuildParams bp) {
     }
   }
   if (p.tops) {
-    uint32_t *e = p.table + k * kElemWords;
+    uint32_t *e = p.table + k * (2 * D);
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      e[d] = d < D ? x[d] : 0u;
-      e[4 + d] = d < D ? z[d] : 0u;
+    for (int d = 0; d < D; ++d) {
+      e[d] = x[d];
+      e[D + d] = z[d];
     }
   } else {
     uint32_t *b = p.table + (k / kBlock) * (2 * D * kBlock) + (k % kBlock);

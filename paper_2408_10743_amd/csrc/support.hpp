@@ -11,7 +11,8 @@ namespace qd {
 
 // Saved table (bottoms: combinations ordered by their largest package,
 // structure of arrays in blocks of kBlock) or tops table (combinations
-// ordered by their smallest package, largest first; kElemWords per entry).
+// ordered by their smallest package, largest first; 2D words per entry, the
+// D x words then the D z words).
 struct SavedParams {
   const uint32_t *elems;
   const unsigned long long *prefix;    // (P+1) x R: e_r(c_0..c_{h-1})
