@@ -111,29 +111,6 @@ int saved_depth(const GammaDev &g, int D, int t, int cap, unsigned long long max
   return u;
 }
 
-// Partial-weight rounds on the matrix cores: the depth u <= deepest whose
-// tables cost the fewest bytes to write, the saved table (8D bytes per
-// entry) with its expanded K-step 0 (64 bytes per entry) and the tops
-// table (8D bytes per top), among the depths whose tops fit a table.
-// The round kernel's time hardly depends on the depth (its tiles are 64
-// tops by seg entries at any depth), while the expanded table of the
-// deepest one can cost more than a tenth of the round.
-int partial_mfma_depth(const GammaDev &g, int D, int t, int deepest, unsigned long long max_tops) {
-  int best = deepest;
-  double least = -1.0;
-  for (int u = 1; u <= deepest; ++u) {
-    const unsigned long long tops = g.suffix[size_t(t - u)];
-    if (tops > max_tops) continue;
-    const double bytes = double(g.prefix[size_t(g.P) * g.R + u]) * (8.0 * D + double(kWave * sizeof(uint4)) / kChunk) +
-                         double(tops) * (8.0 * D);
-    if (least < 0 || bytes < least) {
-      least = bytes;
-      best = u;
-    }
-  }
-  return best;
-}
-
 // Table entries per tile: long enough to amortize a tile's setup, short
 // enough that the round gives its share (1/sharing) of about kTargetTiles
 // tiles per step, where `sharing` codes run their rounds in the same steps.
@@ -168,6 +145,7 @@ unsigned long long plan_round(const GammaDev &g, int t, int u, unsigned seg, boo
     grp.items = items;
     grp.len = len;
     grp.top0 = g.suffix[size_t(h + 1) * R + (t - u)];
+    grp.f = g.suffix[size_t(h + 1) * R + r];
     grp.h = h;
     groups.push_back(grp);
   }
@@ -194,6 +172,37 @@ unsigned long long plan_round(const GammaDev &g, int t, int u, unsigned seg, boo
     runs.push_back(run);
   }
   return tiles;
+}
+
+// Partial-weight rounds on the matrix cores: the depth u <= deepest that
+// costs least, counting the bytes its tables take to write, the saved
+// table (8D bytes per entry) with its expanded K-step 0 (64 bytes per
+// entry) and the tops table (8D bytes per entry; tops over t - u >= 2
+// packages read the table one package shallower), at the builds' rate, and
+// the tiles of the round at a tile's setup cost (shallow tables leave many
+// short groups, each a tile per 64 tops).  Among the depths whose tops fit
+// a table.  The deepest table's expanded form alone can cost more than a
+// tenth of the round.
+constexpr double kBuildBytesPerS = 4e12;  // table builds and expansions, measured 3.8-4.4 TB/s
+constexpr double kTileSetupS = 0.65e-9;   // ~350 VALU instructions per tile on 1024 SIMDs at 2.1 GHz
+int partial_mfma_depth(const GammaDev &g, int D, int t, int deepest, unsigned long long max_tops, unsigned seg,
+                       bool scalar) {
+  int best = deepest;
+  double least = -1.0;
+  std::vector<DevGroup> hg;
+  std::vector<DevRun> hr;
+  for (int u = 1; u <= deepest; ++u) {
+    const unsigned long long tops = g.suffix[size_t(t - u >= 2 ? t - u - 1 : t - u)];  // the table built
+    if (tops > max_tops) continue;
+    const double bytes = double(g.prefix[size_t(g.P) * g.R + u]) * (8.0 * D + double(kWave * sizeof(uint4)) / kChunk) +
+                         double(tops) * (8.0 * D);
+    const double cost = bytes / kBuildBytesPerS + double(plan_round(g, t, u, seg, scalar, hg, hr)) * kTileSetupS;
+    if (least < 0 || cost < least) {
+      least = cost;
+      best = u;
+    }
+  }
+  return best;
 }
 
 }  // namespace
@@ -969,14 +978,16 @@ int Executor::schedule(Job &job, int sharing) {
     const bool expanded = planned >= mfma_min_round_ && job.mfma && !arena() && !job.force_words &&
                           job.census_below == 0;  // the saved table gets its matrix-core form
     if (expanded && job.partial && !tuned && job.opt.saved_depth == 0 && tm == 0 && planned > kTinyRound)
-      f.u = partial_mfma_depth(g, job.D, t, f.u, max_tops);
-    f.use_tops = tm == 1 || (tm == 0 && g.suffix[t - f.u] <= max_tops);
+      f.u = partial_mfma_depth(g, job.D, t, f.u, max_tops, f.seg, job.scalar);
+    f.tops_down = t - f.u >= 2;
+    const int tops_depth = f.tops_down ? t - f.u - 1 : t - f.u;
+    f.use_tops = tm == 1 || (tm == 0 && g.suffix[tops_depth] <= max_tops);
     if (planned <= kTinyRound && job.opt.saved_depth == 0 && tm == 0) {
       f.u = 0;
       f.use_tops = false;
     }
     int rc = f.u > 0 ? ensure_table(job, g, f.u, false) : QD_OK;
-    if (!rc && f.use_tops) rc = ensure_table(job, g, t - f.u, true);
+    if (!rc && f.use_tops) rc = ensure_table(job, g, tops_depth, true);
     if (!rc && f.u > 0 && expanded) rc = ensure_mtable(job, g, f.u, job.partial ? 1 : job.mks);
     if (rc) return rc;
     f.tiles = plan_round(g, t, f.u, f.seg, job.scalar, f.hg, f.hr);
@@ -1116,7 +1127,8 @@ int Executor::step(std::vector<Job *> &jobs, hipStream_t s) {
         RoundDesc d{};
         d.elems = g.elems;
         d.table = f.u == 0 ? zero_table_ : static_cast<const uint32_t *>(g.table[f.u].p);
-        d.tops = f.use_tops ? static_cast<const uint32_t *>(g.tops[f.t - f.u].p) : nullptr;
+        d.tops = f.use_tops ? static_cast<const uint32_t *>(g.tops[f.t - f.u - (f.tops_down ? 1 : 0)].p) : nullptr;
+        d.tops_down = f.use_tops && f.tops_down ? 1 : 0;
         // The matrix-core form, when it holds the K-steps the piece needs.
         const int need_ks = job.partial ? 1 : job.mks;
         d.mtable = f.u > 0 && g.mtable_ks[f.u] >= need_ks ? static_cast<const uint4 *>(g.mtable[f.u].p) : nullptr;

@@ -110,6 +110,10 @@ struct Flight {
   int t = 0, j = 0, u = 0;
   unsigned seg = 0;
   bool use_tops = true;
+  // Tops over t - u >= 2 packages come from the tops table one package
+  // shallower: element c of the top's smallest package XOR that table's
+  // entry (RoundDesc::tops_down), so the deepest tops table is not built.
+  bool tops_down = false;
   int L_before = 0;  // bound certified before the step that scheduled it
   std::vector<DevGroup> hg;
   std::vector<DevRun> hr;

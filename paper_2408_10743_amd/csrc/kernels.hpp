@@ -33,7 +33,10 @@ struct DevGroup {
   unsigned long long cum;    // items of the longer groups
   unsigned long long top0;   // first entry of the group in the tops table
   long long h;
-  long long pad;
+  // Entries of the tops table one package shallower over packages h+1..:
+  // with RoundDesc::tops_down, item i of the group is element i / f of
+  // package h XOR that table's entry i % f.
+  unsigned long long f;
 };
 
 // A run of table segments [s_begin, s_begin + nseg) that the same `e`
@@ -78,6 +81,8 @@ struct RoundDesc {
   const uint32_t *elems;               // package i element e: (3i+e)*kElemWords
   const uint32_t *table;               // saved sums, blocks of kBlock entries
   const uint32_t *tops;                // top codewords, 2D words each: x, then z (NULL: unrank)
+  int tops_down;                       // 1: tops holds tops of t - u - 1 packages (DevGroup::f)
+  int pad_tops;
   const DevGroup *groups;              // sorted by len, longest first
   const DevRun *runs;
   const unsigned long long *suffix;    // (P+1) x R: e_r(c_h..c_{P-1})

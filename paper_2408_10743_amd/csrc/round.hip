@@ -723,7 +723,23 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   }
   if (active) {
     lend = min(k1, GR[a].len);
-    if (p.tops) {
+    if (p.tops && p.tops_down) {
+      // Element c of the smallest package XOR a top one package shallower.
+      const unsigned long long f = GR[a].f;
+      unsigned long long rest = item - GR[a].cum;
+      int c = 0;
+      while (rest >= f && c < 2) {
+        rest -= f;
+        ++c;
+      }
+      const uint32_t *tp = p.tops + rest * (2 * D);
+      const uint32_t *el = p.elems + (size_t(3) * GR[a].h + c) * kElemWords;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        ax[d] = tp[d] ^ el[d];
+        az[d] = tp[D + d] ^ el[4 + d];
+      }
+    } else if (p.tops) {
       const uint32_t *tp = p.tops + (GR[a].top0 + item - GR[a].cum) * (2 * D);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
