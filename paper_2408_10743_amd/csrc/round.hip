@@ -388,18 +388,21 @@ __device__ __forceinline__ void fill_neg_lut(uint32_t *neg_lut) {
   neg_lut[threadIdx.x] = sign_nibbles(threadIdx.x) ^ 0x88888888u;  // sign bit of every nibble flipped
 }
 
-// One chunk, every word, from its A operands: bd[nb] keeps the least 4 wt
-// (as float bits) of the lane's column of block nb.
+// One chunk, every word, from its A operands: the four output blocks
+// (4 wt as float bits of the lane's column of block nb, four rows each).
 template <int KS>
-__device__ __forceinline__ void mfma_every_chunk(const v8i_t (&A)[KS], const v8i_t (&B)[KS][4], uint32_t (&bd)[4]) {
+__device__ __forceinline__ void mfma_every_chunk(const v8i_t (&A)[KS], const v8i_t (&B)[KS][4], v4f_t (&acc)[4]) {
   const v4f_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
-  v4f_t acc[4];
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_fp4(A[0], B[0][nb], zero);
 #pragma unroll
   for (int s = 1; s < KS; ++s)
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_fp4(A[s], B[s][nb], acc[nb]);
+}
+
+// bd[nb] keeps the least 4 wt (as float bits) of the lane's column of block nb.
+__device__ __forceinline__ void min_blocks(const v4f_t (&acc)[4], uint32_t (&bd)[4]) {
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) {
     bd[nb] = min(min(bd[nb], __float_as_uint(acc[nb][0])), __float_as_uint(acc[nb][1]));
@@ -462,22 +465,74 @@ __device__ uint32_t mfma_every(const uint4 *__restrict__ mtab, uint32_t ca, uint
   v8i_t B[KS][4];
   mfma_tops<D, KS, G>(ax, az, lane, ntop, pack, neg_lut, B);
   uint32_t bd[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-  uint32_t c = ca;
-  const uint4 *mb = mtab + static_cast<size_t>(c) * KS * kWave + lane;
-  for (; c + kMfmaUnroll <= cz; c += kMfmaUnroll, mb += kMfmaUnroll * KS * kWave) {
+  if constexpr (KS <= 2) {
+    // Software pipeline over pairs of chunks: a chunk's MFMAs are issued
+    // before the minimum over the previous chunk's outputs, and the operands
+    // of the next pair are loaded meanwhile (up to two chunks past cz: in the
+    // table's padding, never used).  Y starts as all-ones bits, which leave
+    // the minimum unchanged.
+    static_assert(kMtablePadChunks >= 2, "prefetch past the last chunk");
+    const uint4 *mb = mtab + static_cast<size_t>(ca) * KS * kWave + lane;
+    constexpr size_t kStep = static_cast<size_t>(KS) * kWave;
+    uint4 a0[KS], a1[KS];
 #pragma unroll
-    for (int u = 0; u < kMfmaUnroll; ++u) {
+    for (int s = 0; s < KS; ++s) {
+      a0[s] = mb[s * kWave];
+      a1[s] = mb[kStep + s * kWave];
+    }
+    const float ones = __uint_as_float(0xFFFFFFFFu);
+    v4f_t X[4], Y[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) Y[nb] = (v4f_t){ones, ones, ones, ones};
+    uint32_t c = ca;
+    for (; c + 2 <= cz; c += 2) {
       v8i_t A[KS];
 #pragma unroll
-      for (int s = 0; s < KS; ++s) A[s] = mfma_operand(mb[(u * KS + s) * kWave]);
-      mfma_every_chunk<KS>(A, B, bd);
-    }
-  }
-  for (; c < cz; ++c, mb += KS * kWave) {
-    v8i_t A[KS];
+      for (int s = 0; s < KS; ++s) A[s] = mfma_operand(a0[s]);
+      mfma_every_chunk<KS>(A, B, X);  // chunk c
+      mb += 2 * kStep;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) A[s] = mfma_operand(mb[s * kWave]);
-    mfma_every_chunk<KS>(A, B, bd);
+      for (int s = 0; s < KS; ++s) a0[s] = mb[s * kWave];
+      min_blocks(Y, bd);  // chunk c - 1
+#pragma unroll
+      for (int s = 0; s < KS; ++s) A[s] = mfma_operand(a1[s]);
+      mfma_every_chunk<KS>(A, B, Y);  // chunk c + 1
+#pragma unroll
+      for (int s = 0; s < KS; ++s) a1[s] = mb[kStep + s * kWave];
+      min_blocks(X, bd);
+    }
+    min_blocks(Y, bd);
+    if (c < cz) {  // an odd last chunk, its operands in a0
+      v8i_t A[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) A[s] = mfma_operand(a0[s]);
+      mfma_every_chunk<KS>(A, B, X);
+      min_blocks(X, bd);
+    }
+  } else {
+    // Three or four K-steps: the pipeline's second set of outputs would cost
+    // a wave per SIMD (over 128 VGPRs); chunks in pairs, loads first.
+    uint32_t c = ca;
+    const uint4 *mb = mtab + static_cast<size_t>(c) * KS * kWave + lane;
+    for (; c + 2 <= cz; c += 2, mb += 2 * KS * kWave) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        v8i_t A[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) A[s] = mfma_operand(mb[(u * KS + s) * kWave]);
+        v4f_t acc[4];
+        mfma_every_chunk<KS>(A, B, acc);
+        min_blocks(acc, bd);
+      }
+    }
+    if (c < cz) {
+      v8i_t A[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) A[s] = mfma_operand(mb[s * kWave]);
+      v4f_t acc[4];
+      mfma_every_chunk<KS>(A, B, acc);
+      min_blocks(acc, bd);
+    }
   }
   uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
