@@ -195,7 +195,18 @@ __host__ __device__ constexpr uint32_t bias_code(int G, bool hi) {
   return (G == 3 ? 0x3u : G == 6 ? 0x5u : G == 7 ? (hi ? 0x6u : 0x5u) : G == 9 ? (hi ? 0x7u : 0x5u)
           : G == 10 ? (hi ? 0x7u : 0x6u) : G == 12 ? 0x7u : 0x0u) * 0x11111111u;
 }
-static_assert(bias_code(3, false) == 0x33333333u && bias_code(10, true) == 0x77777777u, "bias codes");
+// Twice the e2m1 value of code c (0..7, sign clear): 0, 1, 2, 3, 4, 6, 8, 12.
+constexpr int e2m1_twice(uint32_t c) { return c < 2 ? int(c) : int((2u + (c & 1u)) << ((c >> 1) - 1u)); }
+// The bias group's products: 8 places per dword x entry 2.0 x the top's value.
+constexpr int bias_sum(int G) {
+  return 8 * 2 * (2 * e2m1_twice(bias_code(G, false) & 0xFu) + 2 * e2m1_twice(bias_code(G, true) & 0xFu)) / 2;
+}
+static_assert(e2m1_twice(0x2) == 2 && e2m1_twice(0x3) == 3 && e2m1_twice(0x5) == 6 && e2m1_twice(0x7) == 12 &&
+                  kBiasEntry == 0x44444444u && e2m1_twice(0x4) == 4,
+              "e2m1 codes");
+static_assert(bias_sum(3) == 32 * 3 && bias_sum(6) == 32 * 6 && bias_sum(7) == 32 * 7 && bias_sum(9) == 32 * 9 &&
+                  bias_sum(10) == 32 * 10 && bias_sum(12) == 32 * 12,
+              "the bias group adds 32 G for every G a kernel uses");
 
 // Group g of K-step s of a codeword: x_s, z_s, x_s ^ z_s, or (g = 3) the
 // packed last word (xl, zl) when `packed` (else an empty group).
