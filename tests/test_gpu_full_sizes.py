@@ -115,21 +115,25 @@ def test_config5_engine_mix(Q):
 def test_config3_golden_seeds(Q):
     """Config 3 seeds 0-4 against the oracle's BZ distances, on the default
     path (partial weights, mixed packages allowed) and with every word
-    evaluated and two-row packages first (the paper's construction)."""
+    evaluated and two-row packages first (the paper's construction), each
+    on the matrix cores (the default) and on the vector ALU alone."""
     assert len(GOLD["config3"]) == 5
     for i, d_ref in enumerate(GOLD["config3"]):
         G, f = W.config3(i)
         B = O.expand(G, f)
-        for opts in ({}, {"partial_weight": -1, "mixed_packages": -1}):
-            print(f"config3 seed {i} d={d_ref} {opts}", flush=True)
-            st, d, w, s = Q.qd_distance_ex(G, f, **opts)
-            assert st == 0 and d == d_ref, (i, opts, st, d)
-            assert swt(w) == d and O.in_rowspace(B, w)
-            words_per_codeword = s.words / max(s.enumerated, 1)
-            if opts:
-                assert words_per_codeword == s.D
-            else:
-                assert words_per_codeword < 1.1  # the partial-weight path decided the rounds
+        for base in ({}, {"partial_weight": -1, "mixed_packages": -1}):
+            for mc in (0, -1):
+                opts = dict(base, matrix_cores=mc)
+                print(f"config3 seed {i} d={d_ref} {opts}", flush=True)
+                st, d, w, s = Q.qd_distance_ex(G, f, **opts)
+                assert st == 0 and d == d_ref, (i, opts, st, d)
+                assert swt(w) == d and O.in_rowspace(B, w)
+                assert (s.matrix_core_launches > 0) == (mc == 0), (i, opts)
+                words_per_codeword = s.words / max(s.enumerated, 1)
+                if base:
+                    assert words_per_codeword == s.D
+                else:
+                    assert words_per_codeword < 1.1  # the partial-weight path decided the rounds
 
 
 def test_config4_oracle_sample(Q):
@@ -137,8 +141,8 @@ def test_config4_oracle_sample(Q):
     work (1e4..1e11 combinations, both fields, n 28..80), against the
     oracle's BZ distances: the default path (partial weights on the codes
     planned at >= 1e8 combinations, capped two-row packages where the
-    planner caps them) and every word evaluated with two-row packages
-    first."""
+    planner caps them), the same on the vector ALU alone, and every word
+    evaluated with two-row packages first."""
     rows = GOLD["config4_sample"]
     pool = W.config4(800)  # draw i is the i-th code of the bench's draw sequence
     assert len(rows) >= 24
@@ -147,7 +151,7 @@ def test_config4_oracle_sample(Q):
         G, f = pool[r["index"]]
         assert bench.predicted_work(Q, G, f) <= 1e11  # a member of the bench's batch
         B = O.expand(G, f)
-        for opts in ({}, {"partial_weight": -1, "mixed_packages": -1}):
+        for opts in ({}, {"matrix_cores": -1}, {"partial_weight": -1, "mixed_packages": -1}):
             print(f"config4 draw {r['index']} n={r['n']} field={f} d={r['d']} {opts}", flush=True)
             st, d, w, s = Q.qd_distance_ex(G, f, **opts)
             assert st == 0 and d == r["d"], (r, opts, st, d)
