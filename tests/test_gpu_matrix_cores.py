@@ -107,13 +107,18 @@ def test_shared_chunks_ragged_ends(Q, seg):
     """Short tiles over a depth-2 saved table: the four waves of a workgroup
     share a segment's chunks up to the shortest wave's end, and each wave
     finishes its own remaining chunks (ends that are not a multiple of the
-    shared group).  Config-4 draws of two and three words per half against
-    the vector ALU."""
+    shared group); with every word evaluated, tiles of odd chunk counts end
+    the pipelined loop with a single chunk.  Config-4 draws of two and three
+    words per half against the vector ALU."""
     pool = [c for c in W.config4(120) if 50 <= c[0].shape[1] // 2 <= 74 and c[1] == 2][:6]
     assert len(pool) >= 3
     for i, (G, f) in enumerate(pool):
-        opts = dict(saved_depth=2, seg_len=seg, budget=int(2e10))
-        print(f"code {i} n={G.shape[1] // 2} seg={seg}", flush=True)
-        (st0, d0, w0, s0), (st1, d1, w1, s1) = [Q.qd_distance_ex(G, f, matrix_cores=mc, **opts) for mc in (0, -1)]
-        assert (st0, d0, s0.L, s0.U, s0.combinations) == (st1, d1, s1.L, s1.U, s1.combinations)
-        assert swt(w0) == d0 and O.in_rowspace(O.expand(G, f), w0)
+        # Partial weights (shared chunks), then every word (the pipelined
+        # loop over pairs of chunks, odd chunk counts in the short tiles).
+        for pw in (0, -1):
+            opts = dict(saved_depth=2, seg_len=seg, budget=int(2e10), partial_weight=pw)
+            print(f"code {i} n={G.shape[1] // 2} seg={seg} partial_weight={pw}", flush=True)
+            (st0, d0, w0, s0), (st1, d1, w1, s1) = [Q.qd_distance_ex(G, f, matrix_cores=mc, **opts)
+                                                    for mc in (0, -1)]
+            assert (st0, d0, s0.L, s0.U, s0.combinations) == (st1, d1, s1.L, s1.U, s1.combinations)
+            assert swt(w0) == d0 and O.in_rowspace(O.expand(G, f), w0)
