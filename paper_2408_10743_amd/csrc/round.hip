@@ -563,11 +563,18 @@ __device__ __forceinline__ uint32_t complete_chunks(const uint32_t *__restrict__
   return best;
 }
 
+// Chunks [cz, ct) past the full ones hold the rest of the lanes' entries
+// (rel = entries of the tile before chunk cz; a lane's top reaches `span`
+// entries, inactive lanes none): their outputs are masked per top and row,
+// and a flagged chunk is completed entry by entry within each lane's span.
+// tail_skip: entries of the lane decided by the first word alone.
 template <int D, bool kCensus>
 __device__ uint32_t mfma_partial(const uint32_t *__restrict__ table, const uint4 *__restrict__ mtab, int mks,
-                                 uint32_t ca, uint32_t cs_end, uint32_t cz, bool coop, uint4 *sbuf, uint32_t lane,
-                                 const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop, bool pack,
-                                 const uint32_t *neg_lut, uint32_t thr, uint32_t best, uint32_t &done, Census &cs) {
+                                 uint32_t ca, uint32_t cs_end, uint32_t cz, uint32_t ct, uint32_t rel,
+                                 unsigned long long k0, uint32_t span, uint32_t send, bool coop, uint4 *sbuf,
+                                 uint32_t lane, const uint32_t (&ax)[D], const uint32_t (&az)[D], int ntop, bool pack,
+                                 const uint32_t *neg_lut, uint32_t thr, uint32_t best, uint32_t &done,
+                                 uint32_t &tail_skip, Census &cs) {
   v8i_t B[1][4];
   mfma_tops<D, 1, 3>(ax, az, lane, ntop, pack, neg_lut, B);  // the three groups of word 0
   const uint32_t T = __float_as_uint(static_cast<float>(4 * thr));
@@ -610,6 +617,41 @@ __device__ uint32_t mfma_partial(const uint32_t *__restrict__ table, const uint4
 #pragma unroll
     for (int u = 1; u < kMfmaUnroll; ++u) any = min(any, pm[u]);
     if (__ballot(any < T)) best = complete_chunks<D, kCensus>(table, c, nu, pm, T, ax, az, best, done, cs);
+  }
+  if (ct > cz) {
+    // Entries of the top of column r of block nb: lane 16 q + r holds rows
+    // 4q..4q+3 of that column.
+    const int q4 = static_cast<int>(lane >> 4) * 4;
+    int lim[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      const int src = nb * kChunk + static_cast<int>(lane & 15);
+      const int sp = static_cast<int>(bcast(span, src));
+      lim[nb] = (src < ntop ? sp : 0) - static_cast<int>(rel) - q4;
+    }
+    const uint4 *mb = mtab + static_cast<size_t>(cz) * mks * kWave + lane;
+    for (uint32_t c = cz; c < ct; ++c, mb += static_cast<size_t>(mks) * kWave) {
+      const v8i_t A = mfma_operand(*mb);
+      const v4f_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
+      uint32_t pm = 0xFFFFFFFFu;
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const v4f_t acc = mfma_fp4(A, B[0][nb], zero);
+        const int l = lim[nb] - static_cast<int>(c - cz) * kChunk;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pm = min(pm, i < l ? __float_as_uint(acc[i]) : 0xFFFFFFFFu);
+      }
+      const uint32_t r0 = rel + (c - cz) * kChunk;  // the chunk's first entry in the tile
+      if (__ballot(pm < T)) {
+        // Completed: every word of each lane's entries of the chunk.
+        for (uint32_t i = r0; i < min(r0 + kChunk, send); ++i) {
+          const uint32_t w = weight_at<D>(table, k0 + i, ax, az);
+          if (i < span) best = min(best, w);
+        }
+      } else {
+        tail_skip += span > r0 ? min(span - r0, static_cast<uint32_t>(kChunk)) : 0u;
+      }
+    }
   }
   return best;
 }
@@ -837,11 +879,17 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   // Matrix cores: chunks [ca, cz) of kChunk entries inside the full blocks;
   // the full blocks before and after them (at most one each) stay on the
   // vector ALU.
-  uint32_t ca = 0, cz = 0, mf_done = 0;
+  uint32_t ca = 0, cz = 0, ct = 0, mf_done = 0, tail_skip = 0;
+  bool tail_mfma = false;  // partial weights: the entries past the full chunks on the matrix cores too
   if (kMfma && p.mtable) {
     const uint32_t c_lo = static_cast<uint32_t>((k0 + kChunk - 1) / kChunk);
     const uint32_t c_hi = static_cast<uint32_t>((k0 + nfull * kBlock) / kChunk);
-    if (c_hi > c_lo && (kMfmaEvery ? W == D : W == 1)) {
+    if (kMode == kMfmaPartial && D >= 2 && W == 1 && k0 % kChunk == 0) {
+      ca = __builtin_amdgcn_readfirstlane(c_lo);
+      cz = __builtin_amdgcn_readfirstlane(c_hi);
+      ct = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>((k0 + send + kChunk - 1) / kChunk));
+      tail_mfma = true;
+    } else if (c_hi > c_lo && (kMfmaEvery ? W == D : W == 1)) {
       ca = __builtin_amdgcn_readfirstlane(c_lo);
       cz = __builtin_amdgcn_readfirstlane(c_hi);
     }
@@ -866,7 +914,7 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   }
   const uint32_t head = static_cast<uint32_t>((static_cast<unsigned long long>(ca) * kChunk - k0) / kBlock);
   const uint32_t mid = (cz - ca) * (kChunk / kBlock);  // full blocks on the matrix cores
-  if (kMfma && mid > 0) {
+  if (kMfma && (mid > 0 || tail_mfma)) {
     if constexpr (kMfmaEvery) {
       constexpr int kPackedKs = D >= 3 ? D - 1 : D;
       if constexpr (kMode == kMfmaEveryPacked)
@@ -884,12 +932,18 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
     } else if constexpr (D >= 2) {
       const int c = p.credit[0];
       const uint32_t thr = U0 > c ? static_cast<uint32_t>(U0 - c) : 0u;
-      best = mfma_partial<D, kCensus>(p.table, p.mtable, p.mks, ca, cs_end, cz, coop, coop_buf, lane, ax, az, ntop,
-                                      p.mpack != 0, neg_lut, thr, best, mf_done, cs);
-      best = partial_blocks<D, 1, kCensus>(ax, az, blk, head, best, thr, rec, cs);
-      best = partial_blocks<D, 1, kCensus>(ax, az, blk + (head + mid) * (2 * D * kBlock), nfull - head - mid, best,
-                                           thr, rec, cs);
-      rec += mid;  // the matrix-core blocks are counted by mf_done
+      const uint32_t rel = static_cast<uint32_t>(static_cast<unsigned long long>(cz) * kChunk - k0);
+      best = mfma_partial<D, kCensus>(p.table, p.mtable, p.mks, ca, cs_end, cz, ct, rel, k0, active ? span : 0u,
+                                      send, coop, coop_buf, lane, ax, az, ntop, p.mpack != 0, neg_lut, thr, best,
+                                      mf_done, tail_skip, cs);
+      if (tail_mfma) {
+        rec = nfull;  // the full blocks are counted by mf_done and tail_skip
+      } else {
+        best = partial_blocks<D, 1, kCensus>(ax, az, blk, head, best, thr, rec, cs);
+        best = partial_blocks<D, 1, kCensus>(ax, az, blk + (head + mid) * (2 * D * kBlock), nfull - head - mid,
+                                             best, thr, rec, cs);
+        rec += mid;  // the matrix-core blocks are counted by mf_done
+      }
     }
   } else if (W == D) {
     constexpr uint32_t kEm = kWave * EmK<D>::K;
@@ -925,7 +979,7 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
       if (W == 3) best = partial_blocks<D, 3, kCensus>(ax, az, blk, nfull, best, thr, rec, cs);
     }
   }
-  for (uint32_t i = nfull * kBlock; i < send; ++i) {
+  for (uint32_t i = tail_mfma ? send : nfull * kBlock; i < send; ++i) {
     const uint32_t w = weight_at<D>(p.table, k0 + i, ax, az);
     if (i < span) {
       best = min(best, w);
@@ -935,6 +989,7 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
   if (!active) best = 0xFFFFFFFFu;
   const uint32_t wmin = wave_min(min(best, best_em));
   const uint32_t visited = wave_sum(active ? span : 0u);
+  const uint32_t tail_skipped = tail_mfma ? wave_sum(tail_skip) : 0u;
   const unsigned long long nact = static_cast<unsigned long long>(ntop);
   if constexpr (kCensus) {
     // Per lane at most 64 seg codewords of weight <= 128: the wave sums fit 32 bits.
@@ -953,7 +1008,8 @@ __global__ __launch_bounds__(256) void qd_round_kernel(LaunchParams lp) {
     const unsigned long long skipped =
         static_cast<unsigned long long>(nfull - rec) * kBlock * (D - W) * nact +
         (static_cast<unsigned long long>(em_partial) * nact - em_done) * (kWave * kEmPartialK) * (D - 1) +
-        (kMode == kMfmaPartial ? static_cast<unsigned long long>(cz - ca - mf_done) * kChunk * nact * (D - 1) : 0ull);
+        (kMode == kMfmaPartial ? static_cast<unsigned long long>(cz - ca - mf_done) * kChunk * nact * (D - 1) : 0ull) +
+        static_cast<unsigned long long>(tail_skipped) * (D - 1);
     unsigned long long *c = p.counters + static_cast<size_t>(wg % kCountersPerCode) * kCounterStride;
     atomicAdd(c, static_cast<unsigned long long>(visited));
     atomicAdd(c + 1, static_cast<unsigned long long>(visited) * D - skipped);
