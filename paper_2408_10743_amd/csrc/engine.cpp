@@ -114,8 +114,14 @@ int saved_depth(const GammaDev &g, int D, int t, int cap, unsigned long long max
 // Table entries per tile: long enough to amortize a tile's setup, short
 // enough that the round gives its share (1/sharing) of about kTargetTiles
 // tiles per step, where `sharing` codes run their rounds in the same steps.
-unsigned choose_seg(unsigned long long planned, int sharing, unsigned long_seg) {
-  const unsigned long long target = std::max<unsigned long long>(kTargetTiles / std::max(sharing, 1), 1024);
+// Partial-weight rounds on the matrix cores aim at 1 / 2^kPartialMfmaFewer of
+// the tiles: their chunks, tails included, cost a few MFMAs each, so a
+// tile's setup is the largest cost beside them (config 3 to exact d: 2.0
+// against 1.9 ms for a quarter of the tiles, the same for an eighth).
+constexpr int kPartialMfmaFewer = 2;
+unsigned choose_seg(unsigned long long planned, int sharing, unsigned long_seg, int fewer = 0) {
+  const unsigned long long target =
+      std::max<unsigned long long>(kTargetTiles / std::max(sharing, 1), 1024) >> fewer;
   const unsigned long long want = planned / (kWave * target);
   // Large rounds start from long_seg entries, and every round of a step
   // with many codes (their number fills the device) from kMinSeg: the
@@ -977,6 +983,8 @@ int Executor::schedule(Job &job, int sharing) {
     const unsigned long long max_tops = std::min(kMaxTopEntries, max_table_bytes_ / (8ull * job.D));
     const bool expanded = planned >= mfma_min_round_ && job.mfma && !arena() && !job.force_words &&
                           job.census_below == 0;  // the saved table gets its matrix-core form
+    if (expanded && job.partial && !tuned && !job.opt.seg_len)
+      f.seg = choose_seg(planned, sharing, long_seg_, kPartialMfmaFewer);
     if (expanded && job.partial && !tuned && job.opt.saved_depth == 0 && tm == 0 && planned > kTinyRound)
       f.u = partial_mfma_depth(g, job.D, t, f.u, max_tops, f.seg, job.scalar);
     f.tops_down = t - f.u >= 2;
