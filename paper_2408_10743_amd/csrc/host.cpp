@@ -467,16 +467,20 @@ static std::vector<double> esym_all(const Gamma &g) {
 
 static double predict_with(const std::vector<Gamma> &gs, const std::vector<std::vector<double>> &E, int h,
                            int d_est, bool halve) {
-  std::vector<int> tdone(h, 0), delta(h);
-  for (int j = 0; j < h; ++j) delta[j] = gs[j].delta;
-  if (lower_bound(tdone, delta, halve) >= d_est) return 0.0;
+  // The bound of lower_bound(), kept as it grows: finishing round t of
+  // matrix j adds max(0, t + 1 - delta_j) - max(0, t - delta_j), i.e. 1
+  // when t >= delta_j.
+  int Lraw = 0;
+  for (int j = 0; j < h; ++j) Lraw += std::max(0, 1 - gs[j].delta);
+  auto bound = [&] { return halve ? (Lraw + 1) / 2 : Lraw; };
+  if (bound() >= d_est) return 0.0;
   double w = 0.0;
   for (int t = 1; t <= kMaxN * 2; ++t) {
     for (int j = 0; j < h; ++j) {
       if (t > gs[j].P()) continue;
       w += E[j][t];
-      tdone[j] = t;
-      if (lower_bound(tdone, delta, halve) >= d_est || t == gs[j].P()) return w;
+      if (t >= gs[j].delta) ++Lraw;
+      if (bound() >= d_est || t == gs[j].P()) return w;
     }
   }
   return w;
